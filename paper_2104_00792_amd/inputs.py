@@ -1,0 +1,151 @@
+"""Seeded synthetic workloads for the HashGraph build and probe.
+
+This module holds no hashing, bucketing, partitioning or counting: it only
+draws keys and queries.  Both the GPU path and the CPU oracle read the arrays
+it returns, so nothing here can make the two agree by sharing arithmetic.
+
+Generator: SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014), used counter-style: output i of stream
+``seed`` is mix(seed + (i + 1) * GAMMA), so any slice can be drawn on its own.
+
+Workload shapes follow the paper's experiment section (Sec. 4.3): keys drawn
+uniformly or sequential {1..2^k}, as many queries as keys, table size equal
+to the key count (C = 1).  Queries hit an inserted key with probability 1/2.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_CHUNK = 1 << 22
+
+# Seeds of the named workloads: keys and queries of workload c use
+# KEY_SEED + c and QUERY_SEED + c.
+KEY_SEED = 0x5EED0000
+QUERY_SEED = 0x5EED0100
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output mixer (in place on a uint64 array)."""
+    z ^= z >> np.uint64(30)
+    z *= _M1
+    z ^= z >> np.uint64(27)
+    z *= _M2
+    z ^= z >> np.uint64(31)
+    return z
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs start .. start+count-1 of the SplitMix64 stream ``seed``."""
+    out = np.empty(count, np.uint64)
+    seed = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    for c0 in range(0, count, _CHUNK):
+        c1 = min(count, c0 + _CHUNK)
+        idx = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
+        z = idx * GAMMA
+        z += seed
+        out[c0:c1] = _mix(z)
+    return out
+
+
+def uniform_u32(n: int, seed: int) -> np.ndarray:
+    """n keys uniform over [0, 2^32): the high half of each draw."""
+    return (splitmix64(seed, 0, n) >> np.uint64(32)).astype(np.uint32)
+
+
+def uniform_u64(n: int, seed: int) -> np.ndarray:
+    return splitmix64(seed, 0, n)
+
+
+def sequential(n: int, dtype=np.uint32) -> np.ndarray:
+    """The paper's sequential key set {1, ..., n} (Sec. 4.3)."""
+    return np.arange(1, n + 1, dtype=dtype)
+
+
+def sample_with_replacement(n: int, seed: int, dtype=np.uint32) -> np.ndarray:
+    """The paper's random key set: n draws with replacement from {1..n}."""
+    w = splitmix64(seed, 0, n) >> np.uint64(32)
+    return ((w * np.uint64(n)) >> np.uint64(32)).astype(dtype) + dtype(1)
+
+
+def queries_hit50(keys: np.ndarray, q: int, seed: int) -> np.ndarray:
+    """q queries; each is, with probability 1/2, an inserted key chosen
+    uniformly by position, else a uniform value of the key width (which can
+    hit by chance).  Two draws per query: bit 63 of the first picks hit or
+    miss, its low 32 bits pick the position; the second gives the miss value.
+    """
+    n = keys.size
+    dt = keys.dtype
+    out = np.empty(q, dt)
+    for c0 in range(0, q, _CHUNK):
+        c1 = min(q, c0 + _CHUNK)
+        w = splitmix64(seed, 2 * c0, 2 * (c1 - c0))
+        wa, wb = w[0::2], w[1::2]
+        if dt == np.uint32:
+            miss = (wb >> np.uint64(32)).astype(np.uint32)
+        else:
+            miss = wb.copy()
+        if n == 0:
+            out[c0:c1] = miss
+            continue
+        hit = (wa >> np.uint64(63)).astype(bool)
+        pos = ((wa & np.uint64(0xFFFFFFFF)) * np.uint64(n)) >> np.uint64(32)
+        out[c0:c1] = np.where(hit, keys[pos.astype(np.int64)], miss)
+    return out
+
+
+def zipf_ranks(n: int, K: int, seed: int, s: float = 1.0) -> np.ndarray:
+    """n ranks in 1..K with P(r) proportional to r^-s (inverse CDF on a
+    sequentially summed table; the sampler decides inputs only)."""
+    cdf = np.cumsum(1.0 / np.arange(1, K + 1, dtype=np.float64) ** s)
+    out = np.empty(n, np.uint64)
+    for c0 in range(0, n, _CHUNK):
+        c1 = min(n, c0 + _CHUNK)
+        w = splitmix64(seed, c0, c1 - c0)
+        u = (w >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) * cdf[-1]
+        r = np.searchsorted(cdf, u, side="right") + 1
+        out[c0:c1] = np.minimum(r, K).astype(np.uint64)
+    return out
+
+
+def zipf_u64(n: int, K: int, seed: int, s: float = 1.0) -> np.ndarray:
+    """n 64-bit keys, Zipf(s) over K distinct values.  The value of rank r is
+    the SplitMix64 mixer of r: a bijection on 64-bit words, so the K ranks give
+    K distinct, well spread values."""
+    return _mix(zipf_ranks(n, K, seed, s))
+
+
+# --------------------------------------------------------------------------
+# Named workloads.  Each returns (keys, queries, build options).
+# --------------------------------------------------------------------------
+
+WORKLOADS = {
+    # Plain single table, n = 2^20 uint32 uniform, V = n, 2^20 queries.
+    "plain_u32_2^20": dict(idx=1, n=1 << 20, kind="u32", P=1, num=1, den=1),
+    # One GPU's share of the multi-GPU build: n = 2^28, P = 16, V_p = n_p.
+    "p16_u32_2^28": dict(idx=2, n=1 << 28, kind="u32", P=16, num=1, den=1),
+    # Duplicate-heavy: 2^27 uint64 Zipf(1.0) over 2^20 values, V = n / 2.
+    "zipf_u64_2^27": dict(idx=3, n=1 << 27, kind="zipf64", P=1, num=1, den=2),
+    # Plain reference point at the headline size: P = 1, V = n = 2^28.
+    "plain_u32_2^28": dict(idx=2, n=1 << 28, kind="u32", P=1, num=1, den=1),
+}
+
+
+def make_workload(name: str, n: int | None = None, q: int | None = None):
+    """Keys, queries and build options of a named workload, optionally at a
+    smaller n (same recipe, same seeds)."""
+    w = WORKLOADS[name]
+    n = w["n"] if n is None else n
+    q = n if q is None else q
+    ks, qs = KEY_SEED + w["idx"], QUERY_SEED + w["idx"]
+    if w["kind"] == "u32":
+        keys = uniform_u32(n, ks)
+        queries = queries_hit50(keys, q, qs)
+    else:
+        keys = zipf_u64(n, 1 << 20, ks)
+        queries = zipf_u64(q, 1 << 20, qs)
+    opts = dict(P=w["P"], num=w["num"], den=w["den"])
+    return keys, queries, opts

@@ -1,0 +1,62 @@
+"""The seeded workload generators (no hash table arithmetic in them)."""
+
+import os
+
+import numpy as np
+
+from paper_2104_00792_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_splitmix64_published_sequence():
+    with open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) as f:
+        want = [int(x) for x in f if x.strip() and not x.startswith("#")]
+    assert [int(x) for x in inputs.splitmix64(1234567, 0, len(want))] == want
+
+
+def test_counter_based_slices():
+    full = inputs.splitmix64(99, 0, 10000)
+    assert np.array_equal(inputs.splitmix64(99, 1234, 777), full[1234:1234 + 777])
+    q = inputs.queries_hit50(inputs.uniform_u32(5000, 1), 9000, 5)
+    assert q.size == 9000
+
+
+def test_uniform_u32_spread():
+    k = inputs.uniform_u32(1 << 20, 3)
+    assert k.dtype == np.uint32
+    # top nibble close to uniform
+    c = np.bincount(k >> np.uint32(28), minlength=16)
+    assert np.all(np.abs(c - (1 << 16)) < 6 * 256)
+
+
+def test_hit_rate_about_half():
+    keys = inputs.uniform_u32(1 << 20, 4)
+    q = inputs.queries_hit50(keys, 1 << 20, 8)
+    hit = np.isin(q, keys).mean()
+    assert 0.49 < hit < 0.51
+
+
+def test_zipf_rank_one_frequency():
+    K, n = 1 << 20, 1 << 21
+    r = inputs.zipf_ranks(n, K, 6)
+    H = np.sum(1.0 / np.arange(1, K + 1))
+    f1 = np.count_nonzero(r == 1) / n
+    assert abs(f1 - 1.0 / H) < 0.005
+    assert r.min() >= 1 and r.max() <= K
+    v = inputs.zipf_u64(1 << 16, K, 6)
+    assert v.dtype == np.uint64
+
+
+def test_sequential_and_sample_with_replacement():
+    assert inputs.sequential(5).tolist() == [1, 2, 3, 4, 5]
+    s = inputs.sample_with_replacement(1 << 16, 2)
+    assert s.min() >= 1 and s.max() <= 1 << 16
+
+
+def test_named_workloads_shapes():
+    for name in inputs.WORKLOADS:
+        keys, queries, opts = inputs.make_workload(name, n=1000)
+        assert keys.size == 1000 and queries.size == 1000
+        assert keys.dtype == queries.dtype
+        assert set(opts) == {"P", "num", "den"}
