@@ -1,0 +1,188 @@
+/*
+ * hg.h -- C ABI of the HashGraph build and probe on one MI355X (gfx950).
+ *
+ * The method (Tripathy & Green, "Scalable Hash Table for NUMA Systems",
+ * arXiv 2104.00792) stores a static hash table as a CSR graph: an offset
+ * array over the hash range and a key array grouped by hash value
+ * (Sec. 3.1, "Compressed-Sparse Row" and "Building HashGraph").  The table is
+ * built by hashing, counting keys per hash value, an exclusive prefix sum and
+ * a scatter (Algorithm 1).  The multi-GPU build first splits the keys into
+ * hash-range partitions by count, prefix sum and scatter (Algorithm 2,
+ * Phase 2); this library performs one GPU's share of it: the split, then a
+ * local table per partition, with no cross-GPU exchange.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are device pointers on the current HIP device; the
+ *     others are host pointers.  Inputs are never modified.
+ *   - Work is enqueued on `stream` and is asynchronous unless stated.  The
+ *     caller keeps inputs and outputs alive until the stream reaches them.
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and return HG_ERR_INVALID_ARG or HG_ERR_UNSUPPORTED; outputs are then
+ *     untouched.  HIP failures return HG_ERR_HIP (hg_last_error() holds the
+ *     message).  On any error nothing is leaked.
+ *   - Keys are unsigned 32- or 64-bit integers; every value is a legal key
+ *     (no sentinel).  n and q are below 2^32 per call.
+ *   - hash(k) is the MurmurHash3 finalizer of the key value: fmix32 for
+ *     32-bit keys, fmix64 for 64-bit keys (Sec. 4.2 names Murmur).
+ *   - Partition of a key: the top log2(P) bits of hash(k).
+ *   - Table size of partition p: V_p = max(1, floor(n_p * ratio_num /
+ *     ratio_den)), i.e. V = N / C with load factor C (Sec. 2); a plain table
+ *     (P == 1) may instead fix V with num_buckets.
+ *   - Bucket of a key: hash(k) mod V_p (Algorithm 1, first loop; a true
+ *     remainder).  Global bucket g = bucket_base[p] + bucket, where
+ *     bucket_base is the exclusive prefix sum of V_p, so the P local tables
+ *     form one CSR over sum(V_p) buckets.
+ *   - The library is thread-safe across distinct tables and streams.
+ */
+#ifndef HG_H
+#define HG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hg_status {
+  HG_OK = 0,
+  HG_ERR_INVALID_ARG = 1,   /* null pointer, n >= 2^32, V = 0, bad P ...   */
+  HG_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                     */
+  HG_ERR_HIP = 3,           /* a HIP call failed (see hg_last_error)        */
+  HG_ERR_UNSUPPORTED = 4    /* legal request outside what is implemented    */
+} hg_status;
+
+typedef enum hg_key_type { HG_KEY_U32 = 0, HG_KEY_U64 = 1 } hg_key_type;
+
+/* Build options.
+ *   P            number of hash-range partitions: 1 (plain table) or a power
+ *                of two up to 256 (Algorithm 2, Phase 2 with equal ranges).
+ *   ratio_num/ratio_den
+ *                table ratio 1/C: V_p = max(1, floor(n_p * num / den)).
+ *                Both nonzero unless num_buckets is used.
+ *   num_buckets  if nonzero and P == 1: the bucket count V itself
+ *                (1 <= V <= 2^32 - 2); otherwise ignored.
+ * The total bucket count sum(V_p) must stay below 2^32 - 1 (32-bit offsets,
+ * Sec. 4.3 keeps the table size 32-bit). */
+typedef struct hg_build_opts {
+  uint32_t P;
+  uint32_t ratio_num;
+  uint32_t ratio_den;
+  uint32_t reserved0; /* must be 0 */
+  uint64_t num_buckets;
+} hg_build_opts;
+
+/* Opaque table.  It owns device memory for:
+ *   keys[n]            keys grouped by global bucket (order inside a bucket
+ *                      is unspecified, as with the atomics of Algorithm 1),
+ *   offsets[B + 1]     CSR offsets, B = sum(V_p): bucket g holds
+ *                      keys[offsets[g] .. offsets[g+1]), offsets[B] = n,
+ *   part_offsets[P+1]  first key of each partition, part_offsets[P] = n,
+ *   bucket_base[P+1]   first global bucket of each partition. */
+typedef struct hg_table hg_table;
+
+/* Host-side description of a built table (hg_table_info). */
+typedef struct hg_table_desc {
+  uint64_t n;             /* keys in the table                              */
+  uint64_t num_buckets;   /* B = sum(V_p)                                   */
+  uint32_t P;             /* partitions                                     */
+  uint32_t key_type;      /* hg_key_type                                    */
+  const void* d_keys;     /* n keys                                         */
+  const uint32_t* d_offsets;      /* B + 1                                  */
+  const uint32_t* d_part_offsets; /* P + 1                                  */
+  const uint32_t* d_bucket_base;  /* P + 1                                  */
+} hg_table_desc;
+
+/* hg_build -- build a static table from all n keys (Algorithm 1; with
+ * P > 1, Algorithm 2 Phase 2 then Phase 4 on this GPU's keys).
+ *   d_keys  n keys of type kt (read only; the table keeps its own copy).
+ *   opts    build options (required).
+ *   out     receives the new table; set only on HG_OK.
+ * Allocates the table and temporary workspace from the library's
+ * stream-ordered pool; the call does not synchronize.  n = 0 builds an empty
+ * table (every bucket empty, every count 0).  Errors: HG_ERR_INVALID_ARG for
+ * null d_keys with n > 0, null opts/out, n >= 2^32, P not a power of two,
+ * a zero ratio without num_buckets, or too many buckets; HG_ERR_UNSUPPORTED
+ * for P > 256. */
+hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt,
+                   const hg_build_opts* opts, hipStream_t stream,
+                   hg_table** out);
+
+/* hg_count -- exact multiplicity of each query among the table's keys: the
+ * query hashes to its bucket and every key of the bucket is compared
+ * (Sec. 3.3 "Querying"; Sec. 5.4: the count of each key's appearances).
+ *   d_queries  q keys of the table's key type; d_counts  q uint32 outputs.
+ * Errors: HG_ERR_INVALID_ARG for a null table, or null pointers with q > 0,
+ * or q >= 2^32. */
+hg_status hg_count(const hg_table* table, const void* d_queries, uint64_t q,
+                   uint32_t* d_counts, hipStream_t stream);
+
+/* hg_query -- existence of each query: d_found[i] = 1 if the query occurs
+ * among the keys, else 0 (Sec. 3.3 "Querying").  Same arguments and errors
+ * as hg_count, with q uint8 outputs. */
+hg_status hg_query(const hg_table* table, const void* d_queries, uint64_t q,
+                   uint8_t* d_found, hipStream_t stream);
+
+/* hg_bin_partition -- the hash-range split alone (Algorithm 2, Phase 2:
+ * count per destination, prefix sum, scatter into a buffer), with P equal
+ * hash ranges.  Writes d_out_keys[n] grouped by partition (order inside a
+ * partition unspecified; Sec. 3.3 leaves it open) and d_part_offsets[P+1]
+ * (part_offsets[P] = n).  The output is the send buffer of the exchange that
+ * a multi-GPU build would run next.  d_out_keys must not overlap d_keys.
+ * Errors: as hg_build for n and P; null outputs. */
+hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt,
+                           uint32_t P, void* d_out_keys,
+                           uint32_t* d_part_offsets, hipStream_t stream);
+
+/* hg_hash_bucket -- the first loop of Algorithm 1 on its own: for each key,
+ * d_hash[i] = hash(k) (uint64; for 32-bit keys the upper half is 0) and
+ * d_bucket[i] = hash(k) mod V.  Either output may be null.  1 <= V < 2^32.
+ * Exposed so the bucket map can be checked for any V without a table. */
+hg_status hg_hash_bucket(const void* d_keys, uint64_t n, hg_key_type kt,
+                         uint64_t V, uint64_t* d_hash, uint32_t* d_bucket,
+                         hipStream_t stream);
+
+/* hg_table_info -- fill *desc.  Reading num_buckets waits for the table's
+ * build to finish (it is computed on the device); the other fields do not
+ * wait.  The device pointers stay owned by the table. */
+hg_status hg_table_info(const hg_table* table, hg_table_desc* desc);
+
+/* hg_table_export -- copy the table's arrays into caller-owned device
+ * buffers on `stream`: d_part_offsets[P+1], d_bucket_base[P+1],
+ * d_offsets[num_buckets+1] and d_keys[n] (sizes from hg_table_info).  Any
+ * destination may be null (skipped).  Errors: HG_ERR_INVALID_ARG for a null
+ * table. */
+hg_status hg_table_export(const hg_table* table, uint32_t* d_part_offsets,
+                          uint32_t* d_bucket_base, uint32_t* d_offsets,
+                          void* d_keys, hipStream_t stream);
+
+/* hg_table_free -- release the table's memory in stream order on the stream
+ * it was built on.  Work that uses the table on other streams must be
+ * ordered before that stream's later work.  NULL is a no-op. */
+void hg_table_free(hg_table* table);
+
+/* Human-readable name of a status code (static storage). */
+const char* hg_status_string(hg_status status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* hg_last_error(void);
+
+/* Per-kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by HIP events on the stream it is launched on.
+ * hg_profile_collect synchronizes those events, adds their durations to
+ * per-kernel totals, and resets the event log; hg_profile_read copies up to
+ * `cap` entries (name, launches, total milliseconds) and returns the number
+ * of kernels seen.  hg_profile_reset clears the totals. */
+hg_status hg_profile_enable(int on);
+hg_status hg_profile_collect(void);
+int hg_profile_read(const char** names, uint64_t* launches, double* total_ms,
+                    int cap);
+void hg_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HG_H */

@@ -1,0 +1,286 @@
+"""HashGraph build and probe on MI355X: Python binding of ``libhg.so``.
+
+The binding only marshals arguments: device pointers and the HIP stream come
+from torch tensors and ``torch.cuda.current_stream()``; every step of the
+build and the probe runs in the library's HIP kernels.  If ``libhg.so`` has
+not been built the first call raises; there is no fallback path.
+
+Entry points mirror ``include/hg.h``: :func:`hg_build`, :func:`hg_count`,
+:func:`hg_query`, :func:`hg_bin_partition`, :func:`hg_hash_bucket`.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "HGError", "Table", "hg_build", "hg_count", "hg_query", "hg_bin_partition",
+    "hg_hash_bucket", "lib", "lib_path", "profile",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhg.so")
+
+HG_KEY_U32 = 0
+HG_KEY_U64 = 1
+
+_lib = None
+
+
+class HGError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {detail} (status {status})")
+
+
+class _BuildOpts(ctypes.Structure):
+    _fields_ = [
+        ("P", ctypes.c_uint32),
+        ("ratio_num", ctypes.c_uint32),
+        ("ratio_den", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("num_buckets", ctypes.c_uint64),
+    ]
+
+
+class _TableDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("num_buckets", ctypes.c_uint64),
+        ("P", ctypes.c_uint32),
+        ("key_type", ctypes.c_uint32),
+        ("d_keys", ctypes.c_void_p),
+        ("d_offsets", ctypes.c_void_p),
+        ("d_part_offsets", ctypes.c_void_p),
+        ("d_bucket_base", ctypes.c_void_p),
+    ]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhg.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch first: its HIP runtime (same soname) is then the one libhg.so
+    # binds to, so streams and pointers from torch are valid in the library.
+    _torch()
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"{_LIB_PATH} is missing: build it with __graft_entry__.build() "
+            "(there is no fallback path)")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.hg_build.argtypes = [vp, u64, i32, ctypes.POINTER(_BuildOpts), vp, ctypes.POINTER(vp)]
+    L.hg_build.restype = i32
+    L.hg_count.argtypes = [vp, vp, u64, vp, vp]
+    L.hg_count.restype = i32
+    L.hg_query.argtypes = [vp, vp, u64, vp, vp]
+    L.hg_query.restype = i32
+    L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
+    L.hg_bin_partition.restype = i32
+    L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
+    L.hg_hash_bucket.restype = i32
+    L.hg_table_info.argtypes = [vp, ctypes.POINTER(_TableDesc)]
+    L.hg_table_info.restype = i32
+    L.hg_table_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.hg_table_export.restype = i32
+    L.hg_table_free.argtypes = [vp]
+    L.hg_table_free.restype = None
+    L.hg_status_string.argtypes = [i32]
+    L.hg_status_string.restype = ctypes.c_char_p
+    L.hg_last_error.argtypes = []
+    L.hg_last_error.restype = ctypes.c_char_p
+    L.hg_profile_enable.argtypes = [i32]
+    L.hg_profile_enable.restype = i32
+    L.hg_profile_collect.argtypes = []
+    L.hg_profile_collect.restype = i32
+    L.hg_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(u64),
+                                  ctypes.POINTER(ctypes.c_double), i32]
+    L.hg_profile_read.restype = i32
+    L.hg_profile_reset.argtypes = []
+    L.hg_profile_reset.restype = None
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        L = lib()
+        raise HGError(status, where, L.hg_last_error().decode() or L.hg_status_string(status).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _key_type(t) -> int:
+    torch = _torch()
+    if t.dtype in (torch.uint32, torch.int32):
+        return HG_KEY_U32
+    if t.dtype in (torch.uint64, torch.int64):
+        return HG_KEY_U64
+    raise TypeError(f"keys must be 32- or 64-bit integers, got {t.dtype}")
+
+
+def _dev_ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr() if t.numel() > 0 else None
+
+
+def _stream(stream) -> int | None:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream or None
+
+
+class Table:
+    """A built table (owns device memory until :meth:`free`)."""
+
+    def __init__(self, handle: int, key_type: int, n: int, P: int):
+        self._h = handle
+        self.key_type = key_type
+        self.n = n
+        self.P = P
+
+    @property
+    def handle(self) -> int:
+        if not self._h:
+            raise ValueError("table already freed")
+        return self._h
+
+    def count(self, queries, out=None, stream=None):
+        return hg_count(self, queries, out, stream)
+
+    def query(self, queries, out=None, stream=None):
+        return hg_query(self, queries, out, stream)
+
+    def info(self) -> dict:
+        d = _TableDesc()
+        _check(lib().hg_table_info(self.handle, ctypes.byref(d)), "hg_table_info")
+        return {"n": d.n, "num_buckets": d.num_buckets, "P": d.P, "key_type": d.key_type,
+                "d_keys": d.d_keys, "d_offsets": d.d_offsets,
+                "d_part_offsets": d.d_part_offsets, "d_bucket_base": d.d_bucket_base}
+
+    def export(self, stream=None):
+        """Device copies of (part_offsets, bucket_base, offsets, keys)."""
+        torch = _torch()
+        d = self.info()
+        kdt = torch.uint32 if self.key_type == HG_KEY_U32 else torch.uint64
+        po = torch.empty(self.P + 1, dtype=torch.uint32, device="cuda")
+        bb = torch.empty(self.P + 1, dtype=torch.uint32, device="cuda")
+        offs = torch.empty(d["num_buckets"] + 1, dtype=torch.uint32, device="cuda")
+        keys = torch.empty(self.n, dtype=kdt, device="cuda")
+        _check(lib().hg_table_export(self.handle, _dev_ptr(po), _dev_ptr(bb), _dev_ptr(offs), _dev_ptr(keys),
+                                     _stream(stream)), "hg_table_export")
+        return po, bb, offs, keys
+
+    def free(self):
+        if self._h:
+            lib().hg_table_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None) -> Table:
+    """Build a table from a device tensor of 32- or 64-bit keys.
+
+    V_p = max(1, n_p * ratio[0] // ratio[1]); with P == 1 a nonzero
+    ``num_buckets`` fixes V instead."""
+    kt = _key_type(keys)
+    opts = _BuildOpts(P, ratio[0], ratio[1], 0, num_buckets)
+    h = ctypes.c_void_p()
+    _check(lib().hg_build(_dev_ptr(keys), keys.numel(), kt, ctypes.byref(opts), _stream(stream),
+                          ctypes.byref(h)), "hg_build")
+    return Table(h.value, kt, keys.numel(), P)
+
+
+def hg_count(table: Table, queries, out=None, stream=None):
+    """Exact multiplicity of each query (uint32 device tensor)."""
+    torch = _torch()
+    if _key_type(queries) != table.key_type:
+        raise TypeError("queries and table keys differ in width")
+    if out is None:
+        out = torch.empty(queries.numel(), dtype=torch.uint32, device=queries.device)
+    _check(lib().hg_count(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), _stream(stream)),
+           "hg_count")
+    return out
+
+
+def hg_query(table: Table, queries, out=None, stream=None):
+    """Existence of each query (uint8 device tensor of 0/1)."""
+    torch = _torch()
+    if _key_type(queries) != table.key_type:
+        raise TypeError("queries and table keys differ in width")
+    if out is None:
+        out = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
+    _check(lib().hg_query(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), _stream(stream)),
+           "hg_query")
+    return out
+
+
+def hg_bin_partition(keys, P: int, out=None, part_offsets=None, stream=None):
+    """Hash-range split into P partitions: (keys grouped by partition,
+    part_offsets[P+1])."""
+    torch = _torch()
+    kt = _key_type(keys)
+    if out is None:
+        out = torch.empty_like(keys)
+    if part_offsets is None:
+        part_offsets = torch.empty(P + 1, dtype=torch.uint32, device=keys.device)
+    _check(lib().hg_bin_partition(_dev_ptr(keys), keys.numel(), kt, P, _dev_ptr(out), _dev_ptr(part_offsets),
+                                  _stream(stream)), "hg_bin_partition")
+    return out, part_offsets
+
+
+def hg_hash_bucket(keys, V: int, want_hash: bool = True, stream=None):
+    """(hash(k) as uint64, hash(k) mod V as uint32) for every key."""
+    torch = _torch()
+    kt = _key_type(keys)
+    n = keys.numel()
+    h = torch.empty(n, dtype=torch.uint64, device=keys.device) if want_hash else None
+    b = torch.empty(n, dtype=torch.uint32, device=keys.device)
+    _check(lib().hg_hash_bucket(_dev_ptr(keys), n, kt, V, _dev_ptr(h), _dev_ptr(b), _stream(stream)),
+           "hg_hash_bucket")
+    return h, b
+
+
+class profile:
+    """Per-kernel HIP-event timing of the library's launches.
+
+    ``with profile() as p: ...`` then ``p.results`` maps kernel name to
+    (launches, total milliseconds)."""
+
+    def __enter__(self):
+        L = lib()
+        L.hg_profile_reset()
+        _check(L.hg_profile_enable(1), "hg_profile_enable")
+        self.results = {}
+        return self
+
+    def __exit__(self, *exc):
+        L = lib()
+        L.hg_profile_enable(0)
+        _check(L.hg_profile_collect(), "hg_profile_collect")
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        launches = (ctypes.c_uint64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        k = L.hg_profile_read(names, launches, ms, cap)
+        self.results = {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(min(k, cap))}
+        return False

@@ -1,0 +1,127 @@
+// Device-side building blocks of the HashGraph path on gfx950.
+//
+// Hash: MurmurHash3 finalizers on the key value (fmix32 / fmix64; the paper
+// names Murmur in Sec. 4.2).  Bucket: a true remainder hash mod V
+// (Algorithm 1, first loop), computed without a divide instruction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- hashing
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+template <typename K> struct KeyTraits;
+template <> struct KeyTraits<uint32_t> {
+  typedef uint32_t Hash;
+  static constexpr int kBits = 32;
+  __host__ __device__ static __forceinline__ uint32_t hash(uint32_t k) { return fmix32(k); }
+};
+template <> struct KeyTraits<uint64_t> {
+  typedef uint64_t Hash;
+  static constexpr int kBits = 64;
+  __host__ __device__ static __forceinline__ uint64_t hash(uint64_t k) { return fmix64(k); }
+};
+
+// Partition of a hash: its top log2P bits (0 when log2P == 0).
+template <typename H>
+__host__ __device__ __forceinline__ uint32_t part_of(H h, uint32_t log2P) {
+  constexpr int w = sizeof(H) * 8;
+  return log2P == 0 ? 0u : static_cast<uint32_t>(h >> (w - log2P));
+}
+
+// ------------------------------------------------------------ bucket map
+// h mod V by a truncated reciprocal.  With m = floor((2^w - 1) / V) the
+// estimate q = floor(h * m / 2^w) satisfies floor(h/V) - 1 <= q <= floor(h/V)
+// (h * m / 2^w lies in (h/V - 1, h/V)), so r = h - q*V lies in [0, 2V) and one
+// conditional subtraction gives the exact remainder.  r never exceeds h, so
+// no intermediate overflows.
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(a) * b) >> 32);
+}
+
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+  return static_cast<uint64_t>((static_cast<unsigned __int128>(a) * b) >> 64);
+}
+
+__host__ __device__ __forceinline__ uint32_t recip32(uint32_t V) { return 0xFFFFFFFFu / V; }
+__host__ __device__ __forceinline__ uint64_t recip64(uint32_t V) { return ~0ull / V; }
+
+__host__ __device__ __forceinline__ uint32_t mod_by_recip(uint32_t h, uint32_t V, uint32_t m32, uint64_t) {
+  const uint32_t q = mulhi32(h, m32);
+  uint32_t r = h - q * V;
+  return r >= V ? r - V : r;
+}
+
+__host__ __device__ __forceinline__ uint32_t mod_by_recip(uint64_t h, uint32_t V, uint32_t, uint64_t m64) {
+  const uint64_t q = mulhi64(h, m64);
+  uint64_t r = h - q * static_cast<uint64_t>(V);
+  return static_cast<uint32_t>(r >= V ? r - V : r);
+}
+
+// Per-partition table descriptor: table size, first global bucket, and the
+// two reciprocals of the bucket map.
+struct PartDesc {
+  uint32_t V;
+  uint32_t base;
+  uint32_t m32;
+  uint32_t pad;
+  uint64_t m64;
+};
+
+// Global bucket of a hash under descriptor d.
+template <typename H>
+__device__ __forceinline__ uint32_t global_bucket(H h, const PartDesc& d) {
+  return d.base + mod_by_recip(h, d.V, d.m32, d.m64);
+}
+
+// ------------------------------------------------------ wave primitives
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return static_cast<uint32_t>(__popcll(m)); }
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+
+// Inclusive sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t u = __shfl_up(v, d, kWave);
+    if (l >= static_cast<uint32_t>(d)) v += u;
+  }
+  return v;
+}
+
+}  // namespace hg

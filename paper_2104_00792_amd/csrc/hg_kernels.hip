@@ -1,0 +1,571 @@
+// HashGraph kernels for gfx950 (wave64, 160 KiB LDS per CU).
+//
+// Build (Algorithm 1 of Tripathy & Green, arXiv 2104.00792): hash + bucket,
+// histogram of bucket sizes, exclusive prefix sum into the CSR offsets,
+// scatter of the keys.  With P > 1 the keys are first split into hash-range
+// partitions (Algorithm 2, Phase 2): per-tile partition counts, a prefix sum
+// over (partition, tile), and a stable scatter.  Probe: hash the query, read
+// its bucket's offset range, compare every key of the bucket (Sec. 3.3
+// "Querying"; exact counts as in Sec. 5.4).
+//
+// Every kernel reads keys in 16-byte vector loads when a tile is whole and the
+// base is 16-byte aligned, and recomputes the hash instead of storing it
+// (the paper materialises H_A; recomputing saves 8 bytes per key per pass).
+#include "hg_internal.h"
+
+namespace hg {
+namespace {
+
+constexpr int kWaves = kBlock / kWave;
+
+template <typename K> struct Vec {
+  static constexpr int kPer = 16 / sizeof(K);   // keys per 16-byte load
+  static constexpr int kLoads = kItems / kPer;  // loads per thread per tile
+};
+
+// Position inside its tile of item i (load i / kPer, component i % kPer) of
+// thread t: each 16-byte load of a wave covers 64 * 16 contiguous bytes.
+template <typename K>
+__device__ __forceinline__ uint32_t tile_index(int i, uint32_t t) {
+  constexpr int P = Vec<K>::kPer;
+  return (static_cast<uint32_t>(i / P) * kBlock + t) * P + static_cast<uint32_t>(i % P);
+}
+
+// Loads tile `tile` of src[0, n) into v; bit i of the result marks item i as
+// inside the array.
+template <typename K>
+__device__ __forceinline__ uint32_t load_tile(const K* __restrict__ src, uint32_t n, uint32_t tile,
+                                              K (&v)[kItems]) {
+  const uint64_t start = static_cast<uint64_t>(tile) * kTileKeys;
+  const uint32_t t = threadIdx.x;
+  constexpr int P = Vec<K>::kPer;
+  if (start + kTileKeys <= n && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const uint4* p = reinterpret_cast<const uint4*>(src + start);
+#pragma unroll
+    for (int j = 0; j < Vec<K>::kLoads; ++j) {
+      const uint4 x = p[j * kBlock + t];
+      K tmp[P];
+      __builtin_memcpy(tmp, &x, 16);
+#pragma unroll
+      for (int c = 0; c < P; ++c) v[j * P + c] = tmp[c];
+    }
+    return (1u << kItems) - 1u;
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const uint64_t e = start + tile_index<K>(i, t);
+    if (e < n) {
+      v[i] = src[e];
+      mask |= 1u << i;
+    } else {
+      v[i] = 0;
+    }
+  }
+  return mask;
+}
+
+// Exclusive sum over the workgroup; `total` receives the sum of all values.
+// Every thread of the workgroup must call it (it contains barriers).
+__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* wtot, uint32_t& total) {
+  const uint32_t inc = wave_inclusive_sum(v);
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) wtot[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int x = 0; x < kWaves; ++x) {
+    const uint32_t c = wtot[x];
+    base += (x < static_cast<int>(w)) ? c : 0u;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - v;
+}
+
+// Wave-level multisplit (ballot on each digit bit, as in Ashkiani et al.,
+// "GPU Multisplit", PPoPP 2016): for item i of every lane, the lanes holding
+// the same digit form `match`; the item's rank is this wave's running count of
+// its digit (wcnt, private to the wave) plus the matching lanes below it.
+// The order is (item, lane): deterministic, so an inverse pass can recompute it.
+__device__ __forceinline__ void wave_multisplit(const uint32_t (&d)[kItems], uint32_t mask,
+                                                uint32_t log2P, uint32_t* wcnt,
+                                                uint32_t (&rank)[kItems]) {
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = (mask >> i) & 1u;
+    uint64_t match = ballot(valid);
+    for (uint32_t b = 0; b < log2P; ++b) {
+      const bool bit = (d[i] >> b) & 1u;
+      const uint64_t bb = ballot(bit);
+      match &= bit ? bb : ~bb;
+    }
+    const uint32_t below = popc64(match & lt);
+    uint32_t prior = 0;
+    if (valid) prior = wcnt[d[i]];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) wcnt[d[i]] = prior + popc64(match);
+    __builtin_amdgcn_wave_barrier();
+    rank[i] = prior + below;
+  }
+}
+
+template <typename K>
+__device__ __forceinline__ void tile_digits(const K (&v)[kItems], uint32_t mask, uint32_t log2P,
+                                            uint32_t (&d)[kItems]) {
+#pragma unroll
+  for (int i = 0; i < kItems; ++i)
+    d[i] = ((mask >> i) & 1u) ? part_of(KeyTraits<K>::hash(v[i]), log2P) : 0u;
+}
+
+// ------------------------------------------------------------------ fill
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint64_t len, uint32_t value) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < len; i += stride) p[i] = value;
+}
+
+// ------------------------------------------------- partition count (a2)
+// tile_counts is partition-major: tile_counts[p * num_tiles + tile].
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, uint32_t n, uint32_t log2P,
+                                                       uint32_t num_tiles, uint32_t* __restrict__ tile_counts) {
+  __shared__ uint32_t wcnt[kWaves][kMaxP];
+  const uint32_t t = threadIdx.x, w = t / kWave, P = 1u << log2P;
+  for (uint32_t i = t; i < kWaves * kMaxP; i += kBlock) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  K v[kItems];
+  uint32_t d[kItems], r[kItems];
+  const uint32_t mask = load_tile(keys, n, blockIdx.x, v);
+  tile_digits(v, mask, log2P, d);
+  wave_multisplit(d, mask, log2P, wcnt[w], r);
+  __syncthreads();
+  for (uint32_t p = t; p < P; p += kBlock) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int x = 0; x < kWaves; ++x) s += wcnt[x][p];
+    tile_counts[static_cast<uint64_t>(p) * num_tiles + blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------- partition scatter (a4)
+// tile_base: exclusive scan of tile_counts in (partition, tile) order, i.e.
+// the output position of this tile's first key of every partition.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_part_scatter(const K* __restrict__ keys, uint32_t n, uint32_t log2P,
+                                                         uint32_t num_tiles, const uint32_t* __restrict__ tile_base,
+                                                         K* __restrict__ out) {
+  __shared__ uint32_t wcnt[kWaves][kMaxP];
+  __shared__ uint32_t dstart[kMaxP];
+  __shared__ uint32_t gbase[kMaxP];
+  __shared__ uint32_t wtot[kWaves];
+  __shared__ K stage[kTileKeys];
+  __shared__ uint8_t sdig[kTileKeys];
+  const uint32_t t = threadIdx.x, w = t / kWave, P = 1u << log2P, tile = blockIdx.x;
+  for (uint32_t i = t; i < kWaves * kMaxP; i += kBlock) (&wcnt[0][0])[i] = 0;
+  for (uint32_t p = t; p < P; p += kBlock) gbase[p] = tile_base[static_cast<uint64_t>(p) * num_tiles + tile];
+  __syncthreads();
+  K v[kItems];
+  uint32_t d[kItems], r[kItems];
+  const uint32_t mask = load_tile(keys, n, tile, v);
+  tile_digits(v, mask, log2P, d);
+  wave_multisplit(d, mask, log2P, wcnt[w], r);
+  __syncthreads();
+  // Per digit: wave bases inside the digit, then digit starts in the tile.
+  uint32_t tot = 0;
+  if (t < P) {
+#pragma unroll
+    for (int x = 0; x < kWaves; ++x) {
+      const uint32_t c = wcnt[x][t];
+      wcnt[x][t] = tot;
+      tot += c;
+    }
+  }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_sum(t < P ? tot : 0u, wtot, total);
+  if (t < P) {
+    dstart[t] = ex;
+#pragma unroll
+    for (int x = 0; x < kWaves; ++x) wcnt[x][t] += ex;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    if ((mask >> i) & 1u) {
+      const uint32_t pos = wcnt[w][d[i]] + r[i];
+      stage[pos] = v[i];
+      sdig[pos] = static_cast<uint8_t>(d[i]);
+    }
+  }
+  __syncthreads();
+  const uint64_t start = static_cast<uint64_t>(tile) * kTileKeys;
+  const uint32_t len = static_cast<uint32_t>(min(static_cast<uint64_t>(kTileKeys), n - start));
+  for (uint32_t j = t; j < len; j += kBlock) {
+    const uint32_t dd = sdig[j];
+    out[gbase[dd] + (j - dstart[dd])] = stage[j];
+  }
+}
+
+// ------------------------------------------------------------- scans (a3, a6)
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ a, const uint32_t* len_dev,
+                                                        uint64_t len_bound, uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t wtot[kWaves];
+  const uint64_t len = len_dev ? static_cast<uint64_t>(*len_dev) : len_bound;
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanChunk;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanChunk / kBlock; ++j) {
+    const uint64_t e = base + static_cast<uint64_t>(j) * kBlock + threadIdx.x;
+    if (e < len) s += a[e];
+  }
+  uint32_t total;
+  block_exclusive_sum(s, wtot, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_spine(uint32_t* __restrict__ bs, uint32_t nb) {
+  __shared__ uint32_t wtot[kWaves];
+  constexpr int kPer = 16;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nb; c0 += kBlock * kPer) {
+    uint32_t x[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t idx = c0 + threadIdx.x * kPer + j;
+      x[j] = idx < nb ? bs[idx] : 0u;
+      s += x[j];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_exclusive_sum(s, wtot, total);
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t idx = c0 + threadIdx.x * kPer + j;
+      if (idx < nb) bs[idx] = run;
+      run += x[j];
+    }
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, const uint32_t* len_dev,
+                                                      uint64_t len_bound, const uint32_t* __restrict__ block_sums) {
+  constexpr int kPer = kScanChunk / kBlock;  // 16
+  __shared__ uint32_t buf[kScanChunk + kScanChunk / kPer];
+  __shared__ uint32_t wtot[kWaves];
+  const uint64_t len = len_dev ? static_cast<uint64_t>(*len_dev) : len_bound;
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanChunk;
+  if (base >= len) return;  // whole workgroup leaves together
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = j * kBlock + t;
+    const uint64_t e = base + i;
+    buf[i + i / kPer] = e < len ? a[e] : 0u;
+  }
+  __syncthreads();
+  uint32_t x[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = t * kPer + j;
+    x[j] = buf[i + i / kPer];
+    s += x[j];
+  }
+  uint32_t total;
+  uint32_t run = block_sums[blockIdx.x] + block_exclusive_sum(s, wtot, total);
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = t * kPer + j;
+    buf[i + i / kPer] = run;
+    run += x[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const uint32_t i = j * kBlock + t;
+    const uint64_t e = base + i;
+    if (e < len) a[e] = buf[i + i / kPer];
+  }
+}
+
+// ----------------------------------------------------------------- layout
+// Partition offsets from the scanned tile counts; table sizes
+// V_p = max(1, floor(n_p * num / den)) (or V_plain); bucket bases; the
+// bucket-map reciprocals.  One workgroup; P <= 256.
+__global__ __launch_bounds__(kBlock) void k_layout(const uint32_t* __restrict__ tile_base, uint32_t num_tiles,
+                                                   uint32_t P, uint32_t n, uint32_t num, uint32_t den,
+                                                   uint64_t V_plain, uint32_t* __restrict__ po,
+                                                   uint32_t* __restrict__ bb, PartDesc* __restrict__ desc) {
+  __shared__ uint32_t spo[kMaxP + 1];
+  __shared__ uint32_t wtot[kWaves];
+  const uint32_t t = threadIdx.x;
+  if (t < P) spo[t] = (tile_base != nullptr && num_tiles != 0) ? tile_base[static_cast<uint64_t>(t) * num_tiles] : 0u;
+  if (t == 0) spo[P] = n;
+  __syncthreads();
+  if (t < P) po[t] = spo[t];
+  if (t == 0) po[P] = n;
+  if (bb == nullptr) return;  // uniform over the workgroup
+  uint32_t V = 0;
+  if (t < P) {
+    const uint64_t np = spo[t + 1] - spo[t];
+    uint64_t v = (P == 1 && V_plain != 0) ? V_plain : np * num / den;
+    if (v < 1) v = 1;
+    V = static_cast<uint32_t>(v);
+  }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_sum(V, wtot, total);
+  if (t < P) {
+    PartDesc pd;
+    pd.V = V;
+    pd.base = ex;
+    pd.m32 = recip32(V);
+    pd.pad = 0;
+    pd.m64 = recip64(V);
+    desc[t] = pd;
+    bb[t] = ex;
+  }
+  if (t == 0) bb[P] = total;
+}
+
+// ------------------------------------------------ histogram and scatter (a5, a7)
+// One atomic per lane, except that the lanes sharing the first active lane's
+// bucket are combined into a single atomic (duplicate-heavy inputs).
+template <bool kReturn>
+__device__ __forceinline__ uint32_t aggregated_add(uint32_t* __restrict__ ctr, uint32_t g, bool valid) {
+  const uint64_t act = ballot(valid);
+  if (act == 0) return 0;
+  const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(act)) - 1);
+  const uint32_t gl = readlane(g, leader);
+  const bool in = valid && g == gl;
+  const uint64_t same = ballot(in);
+  uint32_t base = 0;
+  if (lane_id() == leader) {
+    if (kReturn)
+      base = atomicAdd(&ctr[gl], popc64(same));
+    else
+      atomicAdd(&ctr[gl], popc64(same));
+  }
+  uint32_t pos = 0;
+  if (kReturn) {
+    base = readlane(base, leader);
+    if (in) pos = base + popc64(same & lanemask_lt());
+    else if (valid) pos = atomicAdd(&ctr[g], 1u);
+  } else if (valid && !in) {
+    atomicAdd(&ctr[g], 1u);
+  }
+  return pos;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, uint32_t n, uint32_t log2P, uint32_t P,
+                                                 const PartDesc* __restrict__ desc, uint32_t* __restrict__ cnt) {
+  __shared__ PartDesc sd[kMaxP];
+  for (uint32_t i = threadIdx.x; i < P; i += kBlock) sd[i] = desc[i];
+  __syncthreads();
+  K v[kItems];
+  const uint32_t mask = load_tile(keys, n, blockIdx.x, v);
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = (mask >> i) & 1u;
+    uint32_t g = 0;
+    if (valid) {
+      const auto h = KeyTraits<K>::hash(v[i]);
+      g = global_bucket(h, sd[part_of(h, log2P)]);
+    }
+    aggregated_add<false>(cnt, g, valid);
+  }
+}
+
+// cursor[g] starts at the first position of bucket g and ends at the first
+// position of bucket g + 1 (the CSR offsets shifted by one).
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys, uint32_t n, uint32_t log2P, uint32_t P,
+                                                    const PartDesc* __restrict__ desc, uint32_t* __restrict__ cursor,
+                                                    K* __restrict__ out) {
+  __shared__ PartDesc sd[kMaxP];
+  for (uint32_t i = threadIdx.x; i < P; i += kBlock) sd[i] = desc[i];
+  __syncthreads();
+  K v[kItems];
+  const uint32_t mask = load_tile(keys, n, blockIdx.x, v);
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    const bool valid = (mask >> i) & 1u;
+    uint32_t g = 0;
+    if (valid) {
+      const auto h = KeyTraits<K>::hash(v[i]);
+      g = global_bucket(h, sd[part_of(h, log2P)]);
+    }
+    const uint32_t pos = aggregated_add<true>(cursor, g, valid);
+    if (valid) out[pos] = v[i];
+  }
+}
+
+// ------------------------------------------------------------- probe (a8)
+template <typename K, bool kCount>
+__global__ __launch_bounds__(kBlock) void k_probe(const K* __restrict__ tkeys, const uint32_t* __restrict__ offs,
+                                                  const PartDesc* __restrict__ desc, uint32_t log2P, uint32_t P,
+                                                  const K* __restrict__ qs, uint32_t q, void* __restrict__ out) {
+  __shared__ PartDesc sd[kMaxP];
+  for (uint32_t i = threadIdx.x; i < P; i += kBlock) sd[i] = desc[i];
+  __syncthreads();
+  K v[kItems];
+  const uint32_t mask = load_tile(qs, q, blockIdx.x, v);
+  uint32_t lo[kItems], hi[kItems];
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    uint32_t g = 0;
+    if ((mask >> i) & 1u) {
+      const auto h = KeyTraits<K>::hash(v[i]);
+      g = global_bucket(h, sd[part_of(h, log2P)]);
+      lo[i] = offs[g];
+      hi[i] = offs[g + 1];
+    } else {
+      lo[i] = hi[i] = 0;
+    }
+  }
+  const uint64_t start = static_cast<uint64_t>(blockIdx.x) * kTileKeys;
+#pragma unroll
+  for (int i = 0; i < kItems; ++i) {
+    uint32_t c = 0;
+    for (uint32_t j = lo[i]; j < hi[i]; ++j) c += (tkeys[j] == v[i]) ? 1u : 0u;
+    if ((mask >> i) & 1u) {
+      const uint64_t e = start + tile_index<K>(i, threadIdx.x);
+      if (kCount)
+        static_cast<uint32_t*>(out)[e] = c;
+      else
+        static_cast<uint8_t*>(out)[e] = c != 0 ? 1 : 0;
+    }
+  }
+}
+
+// --------------------------------------------------------- hash + bucket (a1)
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hash_bucket(const K* __restrict__ keys, uint32_t n, uint32_t V,
+                                                        uint32_t m32, uint64_t m64, uint64_t* __restrict__ hash,
+                                                        uint32_t* __restrict__ bucket) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+    const auto h = KeyTraits<K>::hash(keys[i]);
+    if (hash) hash[i] = static_cast<uint64_t>(h);
+    if (bucket) bucket[i] = mod_by_recip(h, V, m32, m64);
+  }
+}
+
+inline uint32_t grid_for(uint64_t len) {
+  const uint64_t b = (len + kBlock - 1) / kBlock;
+  return static_cast<uint32_t>(b < 8192 ? (b == 0 ? 1 : b) : 8192);
+}
+
+}  // namespace
+
+// ================================================================ launchers
+hipError_t launch_fill_u32(uint32_t* p, uint64_t len, uint32_t value, hipStream_t s) {
+  if (len == 0) return hipSuccess;
+  k_fill_u32<<<grid_for(len), kBlock, 0, s>>>(p, len, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_count(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t num_tiles,
+                             uint32_t* tile_counts, hipStream_t s) {
+  if (num_tiles == 0) return hipSuccess;
+  if (kt == 0)
+    k_part_count<uint32_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, num_tiles, tile_counts);
+  else
+    k_part_count<uint64_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, num_tiles, tile_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_part_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t num_tiles,
+                               const uint32_t* tile_base, void* out, hipStream_t s) {
+  if (num_tiles == 0) return hipSuccess;
+  if (kt == 0)
+    k_part_scatter<uint32_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, num_tiles,
+                                                          tile_base, static_cast<uint32_t*>(out));
+  else
+    k_part_scatter<uint64_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, num_tiles,
+                                                          tile_base, static_cast<uint64_t*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t len_bound, uint32_t* block_sums,
+                                 hipStream_t s) {
+  if (len_bound == 0) return hipSuccess;
+  const uint32_t nb = div_up(len_bound, kScanChunk);
+  k_scan_reduce<<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_spine<<<1, kBlock, 0, s>>>(block_sums, nb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_down<<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout(const uint32_t* tile_base, uint32_t num_tiles, uint32_t P, uint32_t n, uint32_t num,
+                         uint32_t den, uint64_t V_plain, uint32_t* part_offsets, uint32_t* bucket_base,
+                         PartDesc* desc, hipStream_t s) {
+  k_layout<<<1, kBlock, 0, s>>>(tile_base, num_tiles, P, n, num, den, V_plain, part_offsets, bucket_base, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                       uint32_t* cnt, hipStream_t s) {
+  const uint32_t tiles = div_up(n, kTileKeys);
+  if (tiles == 0) return hipSuccess;
+  if (kt == 0)
+    k_hist<uint32_t><<<tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, P, desc, cnt);
+  else
+    k_hist<uint64_t><<<tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, P, desc, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                          uint32_t* cursor, void* out, hipStream_t s) {
+  const uint32_t tiles = div_up(n, kTileKeys);
+  if (tiles == 0) return hipSuccess;
+  if (kt == 0)
+    k_scatter<uint32_t><<<tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, P, desc, cursor,
+                                                 static_cast<uint32_t*>(out));
+  else
+    k_scatter<uint64_t><<<tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, P, desc, cursor,
+                                                 static_cast<uint64_t*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_probe(int kt, bool count, const void* tkeys, const uint32_t* offsets, const PartDesc* desc,
+                        uint32_t log2P, uint32_t P, const void* queries, uint32_t q, void* out, hipStream_t s) {
+  const uint32_t tiles = div_up(q, kTileKeys);
+  if (tiles == 0) return hipSuccess;
+  if (kt == 0) {
+    const uint32_t* tk = static_cast<const uint32_t*>(tkeys);
+    const uint32_t* qs = static_cast<const uint32_t*>(queries);
+    if (count)
+      k_probe<uint32_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+    else
+      k_probe<uint32_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+  } else {
+    const uint64_t* tk = static_cast<const uint64_t*>(tkeys);
+    const uint64_t* qs = static_cast<const uint64_t*>(queries);
+    if (count)
+      k_probe<uint64_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+    else
+      k_probe<uint64_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_bucket(int kt, const void* keys, uint32_t n, uint32_t V, uint64_t* hash, uint32_t* bucket,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t m32 = recip32(V);
+  const uint64_t m64 = recip64(V);
+  if (kt == 0)
+    k_hash_bucket<uint32_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, V, m32, m64, hash, bucket);
+  else
+    k_hash_bucket<uint64_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, V, m32, m64, hash, bucket);
+  return hipGetLastError();
+}
+
+}  // namespace hg

@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/hg.h declares, and rejects bad arguments before any HIP call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hg.h")
+LIB = os.path.join(ROOT, "paper_2104_00792_amd", "libhg.so")
+
+HG_OK, HG_ERR_INVALID_ARG, HG_ERR_OUT_OF_MEMORY, HG_ERR_HIP, HG_ERR_UNSUPPORTED = range(5)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_uint32), ("ratio_num", ctypes.c_uint32), ("ratio_den", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32), ("num_buckets", ctypes.c_uint64)]
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libhg.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.hg_build.argtypes = [vp, u64, i32, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.hg_count.argtypes = [vp, vp, u64, vp, vp]
+    L.hg_query.argtypes = [vp, vp, u64, vp, vp]
+    L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
+    L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
+    L.hg_table_info.argtypes = [vp, vp]
+    L.hg_table_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.hg_status_string.argtypes = [i32]
+    L.hg_status_string.restype = ctypes.c_char_p
+    L.hg_last_error.restype = ctypes.c_char_p
+    L.hg_table_free.argtypes = [vp]
+    L.hg_table_free.restype = None
+    return L
+
+
+def test_header_declares_the_core_calls():
+    fns = declared_functions()
+    for name in ["hg_build", "hg_count", "hg_query", "hg_bin_partition", "hg_hash_bucket", "hg_table_info",
+                 "hg_table_export", "hg_table_free", "hg_status_string", "hg_last_error"]:
+        assert name in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in hg.h but not exported"
+
+
+def test_status_strings(lib):
+    for code, name in enumerate(["HG_OK", "HG_ERR_INVALID_ARG", "HG_ERR_OUT_OF_MEMORY", "HG_ERR_HIP",
+                                 "HG_ERR_UNSUPPORTED"]):
+        assert lib.hg_status_string(code).decode() == name
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, reserved=0, out=True):
+    opts = Opts(P, num, den, reserved, V)
+    h = ctypes.c_void_p()
+    return lib.hg_build(keys, n, kt, ctypes.byref(opts), None, ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("case, expected", [
+    (dict(keys=None, n=10), HG_ERR_INVALID_ARG),             # null keys
+    (dict(keys=FAKE, n=1 << 32), HG_ERR_INVALID_ARG),        # n >= 2^32
+    (dict(keys=FAKE, n=10, kt=7), HG_ERR_INVALID_ARG),       # key type
+    (dict(keys=FAKE, n=10, P=0), HG_ERR_INVALID_ARG),        # P = 0
+    (dict(keys=FAKE, n=10, P=12), HG_ERR_INVALID_ARG),       # P not a power of two
+    (dict(keys=FAKE, n=10, P=512), HG_ERR_UNSUPPORTED),      # P above 256
+    (dict(keys=FAKE, n=10, num=0), HG_ERR_INVALID_ARG),      # zero ratio
+    (dict(keys=FAKE, n=10, den=0), HG_ERR_INVALID_ARG),
+    (dict(keys=FAKE, n=10, V=(1 << 32) - 1), HG_ERR_INVALID_ARG),  # V too large
+    (dict(keys=FAKE, n=(1 << 32) - 1, num=2), HG_ERR_INVALID_ARG),  # too many buckets
+    (dict(keys=FAKE, n=10, reserved=1), HG_ERR_INVALID_ARG),
+    (dict(keys=FAKE, n=10, out=False), HG_ERR_INVALID_ARG),  # null out
+])
+def test_build_rejects(lib, case, expected):
+    assert build(lib, **case) == expected
+    assert lib.hg_last_error().decode() != ""
+
+
+def test_build_null_opts(lib):
+    h = ctypes.c_void_p()
+    assert lib.hg_build(FAKE, 10, 0, None, None, ctypes.byref(h)) == HG_ERR_INVALID_ARG
+
+
+def test_probe_rejects(lib):
+    assert lib.hg_count(None, FAKE, 10, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_query(None, FAKE, 10, FAKE, None) == HG_ERR_INVALID_ARG
+
+
+def test_bin_partition_rejects(lib):
+    assert lib.hg_bin_partition(FAKE, 10, 0, 3, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_bin_partition(FAKE, 10, 0, 16, FAKE, None, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_bin_partition(None, 10, 0, 16, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_bin_partition(FAKE, 1 << 32, 0, 16, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_bin_partition(FAKE, 10, 0, 1024, FAKE, FAKE, None) == HG_ERR_UNSUPPORTED
+
+
+def test_hash_bucket_rejects(lib):
+    assert lib.hg_hash_bucket(FAKE, 10, 0, 0, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_hash_bucket(FAKE, 10, 0, 1 << 32, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_hash_bucket(None, 10, 0, 5, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    # nothing to do: no outputs requested, or no keys
+    assert lib.hg_hash_bucket(FAKE, 10, 0, 5, None, None, None) == HG_OK
+    assert lib.hg_hash_bucket(None, 0, 0, 5, FAKE, FAKE, None) == HG_OK
+
+
+def test_table_calls_reject_null(lib):
+    assert lib.hg_table_info(None, FAKE) == HG_ERR_INVALID_ARG
+    assert lib.hg_table_export(None, None, None, None, None, None) == HG_ERR_INVALID_ARG
+    lib.hg_table_free(None)  # no-op

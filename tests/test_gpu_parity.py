@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Sizes span several 4096-key tiles with ragged tails; key sets cover the
+paper's workloads (uniform, sequential {1..n}, sampling with replacement,
+Sec. 4.3) and the degenerate ones (empty, one key, all keys equal, Zipf
+duplicates, the extreme values 0 and 2^w - 1).  Everything here is integer,
+so the bar is bit-exact: part_offsets, bucket_base and offsets raw; keys after
+sorting each bucket (the order inside a bucket is left to the atomics of
+Algorithm 1); counts raw; found == (count > 0).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2104_00792_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def make_keys(kind: str, n: int, dtype, seed: int) -> np.ndarray:
+    if kind == "uniform":
+        return inputs.uniform_u32(n, seed) if dtype == np.uint32 else inputs.uniform_u64(n, seed)
+    if kind == "equal":
+        return np.full(n, 0xDEADBEEF, dtype=dtype)
+    if kind == "seq":
+        return inputs.sequential(n, dtype)
+    if kind == "swr":
+        return inputs.sample_with_replacement(n, seed, dtype)
+    if kind == "zipf":
+        v = inputs.zipf_u64(n, max(1, n // 8), seed)
+        return v if dtype == np.uint64 else (v >> np.uint64(32)).astype(np.uint32)
+    if kind == "extremes":
+        top = np.iinfo(dtype).max
+        base = np.array([0, top, 1, top - 1, top // 2, top // 2 + 1], dtype=dtype)
+        return np.resize(base, n)
+    raise ValueError(kind)
+
+
+def to_dev(a: np.ndarray):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def check_table(hg, keys, P=1, num=1, den=1, V=0, queries=None):
+    import torch
+
+    t = hg.hg_build(to_dev(keys), P=P, ratio=(num, den), num_buckets=V)
+    ref = oracle.build_table(keys, P=P, num=num, den=den, V=V)
+    po, bb, offs, tk = t.export()
+    if queries is None:
+        queries = inputs.queries_hit50(keys, max(keys.size, 97), 0xC0FFEE)
+    qd = to_dev(queries)
+    counts = hg.hg_count(t, qd)
+    found = hg.hg_query(t, qd)
+    torch.cuda.synchronize()
+    assert np.array_equal(po.cpu().numpy(), ref["part_offsets"]), "part_offsets"
+    assert np.array_equal(bb.cpu().numpy(), ref["bucket_base"]), "bucket_base"
+    got_offs = offs.cpu().numpy()
+    assert np.array_equal(got_offs, ref["offsets"]), "offsets"
+    got_keys = oracle.canonicalize(got_offs, tk.cpu().numpy())
+    assert np.array_equal(got_keys, ref["keys"]), "bucket contents"
+    want = oracle.count(keys, queries)
+    got_c = counts.cpu().numpy()
+    assert np.array_equal(got_c, want), f"counts: {np.count_nonzero(got_c != want)} of {want.size} differ"
+    assert np.array_equal(found.cpu().numpy(), (want > 0).astype(np.uint8)), "found"
+    t.free()
+
+
+SIZES = [0, 1, 2, 63, 64, 65, 4095, 4096, 4097, 3 * 4096 + 17, 65536 + 3]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("P", [1, 16])
+def test_uniform_u32_sizes(gpu, n, P):
+    check_table(gpu, make_keys("uniform", n, np.uint32, 11 + n), P=P)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "equal", "seq", "swr", "zipf", "extremes"])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("P", [1, 2, 16])
+def test_distributions(gpu, kind, dtype, P):
+    n = 20000 + 7
+    check_table(gpu, make_keys(kind, n, dtype, 5), P=P)
+
+
+@pytest.mark.parametrize("ratio", [(1, 2), (3, 2), (1, 7), (5, 1)])
+@pytest.mark.parametrize("P", [1, 4, 256])
+def test_ratios(gpu, ratio, P):
+    n = 50000 + 1
+    check_table(gpu, make_keys("uniform", n, np.uint32, 3), P=P, num=ratio[0], den=ratio[1])
+
+
+@pytest.mark.parametrize("V", [1, 2, 3, 1000, (1 << 20) + 1, 1 << 22])
+def test_explicit_bucket_count(gpu, V):
+    n = 30000
+    check_table(gpu, make_keys("uniform", n, np.uint32, 17), V=V)
+    check_table(gpu, make_keys("zipf", n, np.uint64, 17), V=V)
+
+
+@pytest.mark.parametrize("P", [1, 2, 16, 256])
+def test_plain_2p20(gpu, P):
+    keys, queries, _ = inputs.make_workload("plain_u32_2^20")
+    check_table(gpu, keys, P=P, queries=queries)
+
+
+def test_zipf_u64_small(gpu):
+    keys, queries, opts = inputs.make_workload("zipf_u64_2^27", n=1 << 18)
+    check_table(gpu, keys, P=opts["P"], num=opts["num"], den=opts["den"], queries=queries)
+
+
+def test_repeat_is_deterministic(gpu):
+    import torch
+
+    keys = make_keys("swr", 100003, np.uint32, 9)
+    kd = to_dev(keys)
+    outs = []
+    for _ in range(3):
+        t = gpu.hg_build(kd, P=16)
+        po, bb, offs, tk = t.export()
+        torch.cuda.synchronize()
+        o = offs.cpu().numpy()
+        outs.append((po.cpu().numpy(), o, oracle.canonicalize(o, tk.cpu().numpy())))
+        t.free()
+    for a in outs[1:]:
+        for x, y in zip(outs[0], a):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+def test_hash_bucket(gpu, dtype):
+    import torch
+
+    top = int(np.iinfo(dtype).max)
+    edge = np.array([0, 1, 2, top, top - 1, top // 2, top // 2 + 1, 0x80000000, 0x7FFFFFFF], dtype=dtype)
+    keys = np.concatenate([edge, make_keys("uniform", 100000, dtype, 23)])
+    kd = to_dev(keys)
+    divisors = [1, 2, 3, 5, 7, 641, 65535, 65536, 65537, (1 << 24) - 3, (1 << 31) - 1, 1 << 31,
+                (1 << 31) + 1, 3 << 30, (1 << 32) - 2, (1 << 32) - 1, 2654435761, 4294967291]
+    for V in divisors:
+        h, b = gpu.hg_hash_bucket(kd, V)
+        torch.cuda.synchronize()
+        rh, rb = oracle.hash_bucket(keys, V)
+        assert np.array_equal(h.cpu().numpy(), rh), f"hash, V={V}"
+        assert np.array_equal(b.cpu().numpy(), rb), f"bucket, V={V}"
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 100003])
+@pytest.mark.parametrize("P", [1, 2, 16, 256])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+def test_bin_partition(gpu, n, P, dtype):
+    import torch
+
+    keys = make_keys("uniform", n, dtype, 31 + n)
+    out, po = gpu.hg_bin_partition(to_dev(keys), P)
+    torch.cuda.synchronize()
+    rpo, rkeys = oracle.bin_partition(keys, P)
+    got_po = po.cpu().numpy()
+    assert np.array_equal(got_po, rpo)
+    assert np.array_equal(oracle.canonicalize(got_po, out.cpu().numpy()), rkeys)
+
+
+def test_empty_table_counts_zero(gpu):
+    import torch
+
+    keys = np.empty(0, np.uint32)
+    queries = make_keys("uniform", 5000, np.uint32, 1)
+    check_table(gpu, keys, P=1, queries=queries)
+    check_table(gpu, keys, P=16, queries=queries)
+    t = gpu.hg_build(to_dev(keys))
+    c = gpu.hg_count(t, to_dev(np.empty(0, np.uint32)))
+    torch.cuda.synchronize()
+    assert c.numel() == 0
+    t.free()
