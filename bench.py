@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: HashGraph build + probe on one MI355X.
+
+One step = hg_build of n keys (P hash-range partitions, local tables with
+V_p = n_p) + hg_count of q = n queries + freeing the table, on device-resident
+synthetic inputs.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+value = n * K / (timed seconds): build+probe keys/s.  The per-kernel launch
+durations come from HIP events that the library records around each of its
+launches on the launch stream, over the timed steps.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "build+probe keys/s and % HBM peak at 2^28 u32; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2104_00792_amd", "csrc", "hg_kernels.hip")
+
+DESCRIPTIONS = {
+    "p16_u32_2^28": "n=2^28 uint32 keys uniform; P=16 hash-range partitions (top 4 bits of fmix32); "
+                    "local tables V_p=n_p; 2^28 queries at 50% hit",
+    "plain_u32_2^28": "n=2^28 uint32 keys uniform; plain table V=n; 2^28 queries at 50% hit",
+    "plain_u32_2^20": "n=2^20 uint32 keys uniform; plain table V=n; 2^20 queries at 50% hit",
+    "zipf_u64_2^27": "n=2^27 uint64 keys Zipf(1.0) over 2^20 values; fmix64; V=n/2; 2^27 Zipf queries",
+}
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> float:
+    """Bytes the kernel's function must move per launch, independent of how
+    the kernel moves them (n keys of ks bytes, q queries, B buckets).  Split
+    passes run once on the keys (build) and once on the queries (probe); with
+    q == n both launches move the same bytes."""
+    table = {
+        # build, sorted path
+        "part_count": ks * n,                       # read keys
+        "split1_count": ks * n,                     # read keys
+        "split1_scatter": 2 * ks * n,               # keys in, keys out
+        "split2_count": ks * n,                     # read keys
+        "split2_scatter": 2 * ks * n,               # keys in, keys out
+        "lds_build": 2 * ks * n + 4 * B,            # keys in, keys out, offsets out
+        # probe, sorted path
+        "qsplit1_count": ks * q,                    # read queries
+        "lds_probe": ks * q + 4 * B + ks * n + 4 * q,  # queries, offsets, table keys, counts out
+        "qgather2": ks * q + 8 * q,                 # queries, counts in, counts out
+        "qgather1": ks * q + 8 * q,
+        # atomic path and direct probe
+        "zero_counts": 4 * (B + 1),                 # counters written
+        "bucket_hist": ks * n + 4 * B,              # keys in, counters out once
+        "bucket_scan": 8 * B,                       # counters in, offsets out
+        "bucket_scatter": 2 * ks * n + 8 * B,       # keys in and out, cursors in and out
+        "part_scatter": 2 * ks * n,
+        "probe_count": q * (ks + 4 + 8 + ks),       # query, count, two offsets, one key
+        "probe_found": q * (ks + 1 + 8 + ks),
+    }
+    return float(table.get(kernel, 0))
+
+
+def read_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when absent or taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = f"hbm_bytes_per_launch.{kernel}"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(workload: str, n_sample: int):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    from paper_2104_00792_amd import inputs
+
+    keys, queries, opts = inputs.make_workload(workload, n=n_sample)
+    t0 = time.perf_counter()
+    oracle.build_table(keys, P=opts["P"], num=opts["num"], den=opts["den"])
+    oracle.count(keys, queries)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{workload} recipe at n=q={n_sample}: oracle build (sort of (p,b,key) tuples + "
+                      f"run-length) + oracle count (sorted copy + equal_range), single thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="p16_u32_2^28", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--n", type=int, default=None, help="override the key count (same recipe)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(one GPU's share of the paper's multi-GPU build is what it measures)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2104_00792_amd as hg
+    from paper_2104_00792_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hg.lib()
+
+    w = inputs.WORKLOADS[args.workload]
+    n = w["n"] if args.n is None else args.n
+    log(f"generating {args.workload} n={n} on {torch.cuda.get_device_name(dev)}")
+    keys, queries, opts = inputs.make_workload(args.workload, n=n, device=dev)
+    q = queries.numel()
+    ks = keys.element_size()
+    counts = torch.empty(q, dtype=torch.uint32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        t = hg.hg_build(keys, P=opts["P"], ratio=(opts["num"], opts["den"]))
+        hg.hg_count(t, queries, out=counts)
+        t.free()
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_probe = hg.hg_build(keys, P=opts["P"], ratio=(opts["num"], opts["den"]))
+    B = t_probe.info()["num_buckets"]
+    t_probe.free()
+
+    log(f"timing {args.steps} steps")
+    with hg.profile() as prof:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = n / (ms_per_step / 1000.0)
+
+    kernels = {}
+    for name, (launches, total_ms) in prof.results.items():
+        avg = total_ms / launches
+        per_step = total_ms / args.steps
+        ab = algorithmic_bytes(name, n, q, B, ks, opts["P"])
+        kernels[name] = {"launches_per_step": launches // args.steps, "avg_ms": round(avg, 5),
+                         "ms_per_step": round(per_step, 5),
+                         "alg_GBs": round(ab / (avg / 1000.0) / 1e9, 1) if avg > 0 and ab else None}
+    dom = max((k for k in kernels if algorithmic_bytes(k, n, q, B, ks, opts["P"]) > 0),
+              key=lambda k: kernels[k]["ms_per_step"])
+    dom_avg_s = kernels[dom]["avg_ms"] / 1000.0
+    dom_bytes = algorithmic_bytes(dom, n, q, B, ks, opts["P"])
+    achieved = dom_bytes / dom_avg_s / 1e9
+    traffic = read_traffic(args.workload, dom)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if ks == 4 else "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {DESCRIPTIONS[args.workload]}", "n": n, "q": q,
+                   "P": opts["P"], "table_ratio": f"{opts['num']}/{opts['den']}", "num_buckets": B},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline on a sample of {args.cpu_sample}")
+        result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

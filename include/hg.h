@@ -70,9 +70,24 @@ typedef struct hg_build_opts {
   uint32_t P;
   uint32_t ratio_num;
   uint32_t ratio_den;
-  uint32_t reserved0; /* must be 0 */
+  uint32_t flags;     /* HG_BUILD_* below; 0 lets the library choose */
   uint64_t num_buckets;
 } hg_build_opts;
+
+/* Build strategies (same table, different kernels).  ATOMIC: histogram and
+ * scatter with global atomics, as written in Algorithm 1 (fast while the
+ * counters fit in cache).  SORTED: two stable splits down to sub-bins of
+ * 2^15 buckets, then histogram, scan and scatter inside LDS (the paper's
+ * local binning of Sec. 3.2 carried down to LDS size). */
+#define HG_BUILD_ATOMIC 1u
+#define HG_BUILD_SORTED 2u
+
+/* Probe strategies for hg_count_ex / hg_query_ex.  DIRECT: each query reads
+ * its bucket's offsets and keys where they lie.  SORTED: queries take the
+ * table's two splits, are counted against LDS-resident windows of the table,
+ * and return to input order by two gathers. */
+#define HG_PROBE_DIRECT 1u
+#define HG_PROBE_SORTED 2u
 
 /* Opaque table.  It owns device memory for:
  *   keys[n]            keys grouped by global bucket (order inside a bucket
@@ -104,8 +119,8 @@ typedef struct hg_table_desc {
  * stream-ordered pool; the call does not synchronize.  n = 0 builds an empty
  * table (every bucket empty, every count 0).  Errors: HG_ERR_INVALID_ARG for
  * null d_keys with n > 0, null opts/out, n >= 2^32, P not a power of two,
- * a zero ratio without num_buckets, or too many buckets; HG_ERR_UNSUPPORTED
- * for P > 256. */
+ * a zero ratio without num_buckets, too many buckets, or unknown flags;
+ * HG_ERR_UNSUPPORTED for P > 256. */
 hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt,
                    const hg_build_opts* opts, hipStream_t stream,
                    hg_table** out);
@@ -124,6 +139,14 @@ hg_status hg_count(const hg_table* table, const void* d_queries, uint64_t q,
  * as hg_count, with q uint8 outputs. */
 hg_status hg_query(const hg_table* table, const void* d_queries, uint64_t q,
                    uint8_t* d_found, hipStream_t stream);
+
+/* hg_count_ex / hg_query_ex -- hg_count / hg_query with an explicit probe
+ * strategy (flags: 0 = library's choice, HG_PROBE_DIRECT, HG_PROBE_SORTED).
+ * Results do not depend on the strategy.  Unknown flags: HG_ERR_INVALID_ARG. */
+hg_status hg_count_ex(const hg_table* table, const void* d_queries, uint64_t q,
+                      uint32_t* d_counts, uint32_t flags, hipStream_t stream);
+hg_status hg_query_ex(const hg_table* table, const void* d_queries, uint64_t q,
+                      uint8_t* d_found, uint32_t flags, hipStream_t stream);
 
 /* hg_bin_partition -- the hash-range split alone (Algorithm 2, Phase 2:
  * count per destination, prefix sum, scatter into a buffer), with P equal

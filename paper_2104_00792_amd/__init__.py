@@ -25,6 +25,15 @@ _LIB_PATH = os.path.join(_HERE, "libhg.so")
 HG_KEY_U32 = 0
 HG_KEY_U64 = 1
 
+# Build strategies (include/hg.h): global atomics as in Algorithm 1, or two
+# stable splits down to LDS-sized sub-bins.  0 lets the library choose.
+HG_BUILD_ATOMIC = 1
+HG_BUILD_SORTED = 2
+# Probe strategies: each query reads its bucket in place, or queries are split
+# like the table, counted against LDS windows and gathered back.
+HG_PROBE_DIRECT = 1
+HG_PROBE_SORTED = 2
+
 _lib = None
 
 
@@ -39,7 +48,7 @@ class _BuildOpts(ctypes.Structure):
         ("P", ctypes.c_uint32),
         ("ratio_num", ctypes.c_uint32),
         ("ratio_den", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
         ("num_buckets", ctypes.c_uint64),
     ]
 
@@ -81,6 +90,10 @@ def lib() -> ctypes.CDLL:
     L.hg_count.restype = i32
     L.hg_query.argtypes = [vp, vp, u64, vp, vp]
     L.hg_query.restype = i32
+    L.hg_count_ex.argtypes = [vp, vp, u64, vp, u32, vp]
+    L.hg_count_ex.restype = i32
+    L.hg_query_ex.argtypes = [vp, vp, u64, vp, u32, vp]
+    L.hg_query_ex.restype = i32
     L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
     L.hg_bin_partition.restype = i32
     L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
@@ -159,11 +172,11 @@ class Table:
             raise ValueError("table already freed")
         return self._h
 
-    def count(self, queries, out=None, stream=None):
-        return hg_count(self, queries, out, stream)
+    def count(self, queries, out=None, stream=None, flags=0):
+        return hg_count(self, queries, out, stream, flags)
 
-    def query(self, queries, out=None, stream=None):
-        return hg_query(self, queries, out, stream)
+    def query(self, queries, out=None, stream=None, flags=0):
+        return hg_query(self, queries, out, stream, flags)
 
     def info(self) -> dict:
         d = _TableDesc()
@@ -197,40 +210,42 @@ class Table:
             pass
 
 
-def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None) -> Table:
+def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None, flags: int = 0) -> Table:
     """Build a table from a device tensor of 32- or 64-bit keys.
 
     V_p = max(1, n_p * ratio[0] // ratio[1]); with P == 1 a nonzero
-    ``num_buckets`` fixes V instead."""
+    ``num_buckets`` fixes V instead.  ``flags``: HG_BUILD_ATOMIC or
+    HG_BUILD_SORTED to pin the strategy (the table is the same)."""
     kt = _key_type(keys)
-    opts = _BuildOpts(P, ratio[0], ratio[1], 0, num_buckets)
+    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets)
     h = ctypes.c_void_p()
     _check(lib().hg_build(_dev_ptr(keys), keys.numel(), kt, ctypes.byref(opts), _stream(stream),
                           ctypes.byref(h)), "hg_build")
     return Table(h.value, kt, keys.numel(), P)
 
 
-def hg_count(table: Table, queries, out=None, stream=None):
-    """Exact multiplicity of each query (uint32 device tensor)."""
+def hg_count(table: Table, queries, out=None, stream=None, flags: int = 0):
+    """Exact multiplicity of each query (uint32 device tensor).  ``flags``:
+    HG_PROBE_DIRECT or HG_PROBE_SORTED to pin the strategy."""
     torch = _torch()
     if _key_type(queries) != table.key_type:
         raise TypeError("queries and table keys differ in width")
     if out is None:
         out = torch.empty(queries.numel(), dtype=torch.uint32, device=queries.device)
-    _check(lib().hg_count(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), _stream(stream)),
-           "hg_count")
+    _check(lib().hg_count_ex(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), flags,
+                             _stream(stream)), "hg_count")
     return out
 
 
-def hg_query(table: Table, queries, out=None, stream=None):
+def hg_query(table: Table, queries, out=None, stream=None, flags: int = 0):
     """Existence of each query (uint8 device tensor of 0/1)."""
     torch = _torch()
     if _key_type(queries) != table.key_type:
         raise TypeError("queries and table keys differ in width")
     if out is None:
         out = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
-    _check(lib().hg_query(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), _stream(stream)),
-           "hg_query")
+    _check(lib().hg_query_ex(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), flags,
+                             _stream(stream)), "hg_query")
     return out
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhg.so")
-SOURCES = ["hg_kernels.hip", "hg_api.cpp"]
+SOURCES = ["hg_kernels.hip", "hg_split.hip", "hg_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

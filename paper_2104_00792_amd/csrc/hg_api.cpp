@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -30,6 +31,11 @@ struct hg_table {
   uint32_t* d_part_offsets; // P + 1
   uint32_t* d_bucket_base;  // P + 1
   hg::PartDesc* d_desc;     // P
+  uint32_t* d_unsorted;     // 1 + kMaxUnsorted: long buckets left unsorted
+  int split_mode;           // level-1 split: 0 by partition, 1 by coarse bucket range
+  uint32_t sh1;             // coarse range 2^sh1 buckets (mode 1)
+  uint32_t nd1;             // level-1 digits
+  uint32_t log2S;           // sub-bins of 2^log2S buckets
   std::mutex mu;
   bool have_num_buckets;
   uint64_t num_buckets;
@@ -219,14 +225,235 @@ hg_status run_partition(const void* keys, uint32_t n, hg_key_type kt, uint32_t l
   return HG_OK;
 }
 
-hg_status probe(const hg_table* t, const void* d_queries, uint64_t q, void* d_out, bool count, hipStream_t s) {
+
+// ------------------------------------------------ level-1 split parameters
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+struct SplitParams {
+  int mode;        // 0: partitions, 1: coarse bucket ranges
+  uint32_t sh1;    // mode 1: 2^sh1 buckets per range
+  uint32_t nd1;    // level-1 digits
+  uint32_t log2S;  // regular sub-bins hold 2^log2S buckets
+};
+
+// Sub-bins of about 2^14 keys (log2S shrinks as keys per bucket grow).
+// Level-1 digits by partition when an average partition's table fits kMaxD2
+// sub-bins, the last of which may grow to 2^kLog2SLds buckets in LDS;
+// otherwise by coarse bucket ranges of at most kMaxD2 sub-bins each.
+SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound) {
+  SplitParams sp;
+  const uint64_t buckets = bound > P ? bound - P : 1;
+  uint32_t rho_log = 0;  // ceil(log2(keys per bucket)), at least 0
+  while ((buckets << rho_log) < n) ++rho_log;
+  uint32_t l = hg::kLog2SMax > rho_log ? hg::kLog2SMax - rho_log : 0;
+  if (l < hg::kLog2SMin) l = hg::kLog2SMin;
+  sp.log2S = l;
+  const uint64_t S = 1ull << l;
+  const uint64_t fits = (hg::kMaxD2 - 1) * S + (1ull << hg::kLog2SLds) / 2;
+  if (P > 1 && (buckets + P - 1) / P <= fits) {
+    sp.mode = 0;
+    sp.sh1 = 0;
+    sp.nd1 = P;
+    return sp;
+  }
+  const uint32_t lb = ceil_log2(bound < 2 ? 2 : bound);
+  uint32_t sh = lb > 5 ? lb - 5 : 0;
+  const uint32_t lo = std::max<uint32_t>(l, lb > 8 ? lb - 8 : 0);
+  const uint32_t hi = l + 10;  // kMaxD2 sub-bins per range
+  if (sh < lo) sh = lo;
+  if (sh > hi) sh = hi;
+  sp.mode = 1;
+  sp.sh1 = sh;
+  sp.nd1 = static_cast<uint32_t>((bound + (1ull << sh) - 1) >> sh);
+  if (sp.nd1 == 0) sp.nd1 = 1;
+  return sp;
+}
+
+uint32_t probe_log2W(hg_key_type kt, uint64_t n, uint64_t buckets) {
+  const uint64_t kcap = hg::kProbeKeyCapBytes / key_bytes(kt);
+  const double per_bucket = buckets ? static_cast<double>(n) / static_cast<double>(buckets) : 1.0;
+  uint32_t l = hg::kMaxLog2W;
+  while (l > 6 && static_cast<double>(1u << l) * (per_bucket * 1.1 + 0.01) > static_cast<double>(kcap)) --l;
+  return l;
+}
+
+// Level-1 split of n keys (or queries) against layout (log2P, desc, bb):
+// per-tile counts, scan, plan of level 2; then the level-1 scatter into buf1.
+// `layout_from_counts` (builds with mode 0) also runs the layout kernel on the
+// partition counts before the plan.
+struct SplitBufs {
+  uint32_t* counts1;
+  uint32_t* bsums;
+  hg::SegPlan* plan;
+  uint32_t* counts2;
+  void* buf1;
+  void* buf2;
+  uint32_t tiles1;
+  uint32_t max_tiles2;
+  uint32_t max_counts2;
+};
+
+hg_status split_two_levels(const void* src, uint32_t n, hg_key_type kt, const SplitParams& sp, uint32_t log2P,
+                           uint32_t P, const hg::PartDesc* desc, const uint32_t* bb, uint32_t* offsets_or_null,
+                           const SplitBufs& w, hipStream_t s) {
+  const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  HG_LAUNCH("split1_scatter", s,
+            hg::launch_msplit(kt, 1, hg::OP_SCATTER, dig1, src, n, 0, nullptr, sp.nd1, log2P, P, desc, sp.sh1,
+                              w.counts1, w.buf1, nullptr, nullptr, s));
+  HG_LAUNCH("split2_count", s,
+            hg::launch_msplit(kt, 2, hg::OP_COUNT, hg::DIG_SUB, w.buf1, n, w.max_tiles2, w.plan, 0, log2P, P, desc,
+                              sp.log2S, w.counts2, nullptr, nullptr, nullptr, s));
+  HG_LAUNCH("split2_scan", s, hg::launch_scan_exclusive(w.counts2, &w.plan->total_counts, w.max_counts2, w.bsums, s));
+  HG_LAUNCH("split2_scatter", s,
+            hg::launch_msplit(kt, 2, hg::OP_SCATTER, hg::DIG_SUB, w.buf1, n, w.max_tiles2, w.plan, 0, log2P, P, desc,
+                              sp.log2S, w.counts2, w.buf2, nullptr, nullptr, s));
+  (void)offsets_or_null;
+  (void)tile2;
+  (void)bb;
+  return HG_OK;
+}
+
+hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams& sp, uint32_t P, uint64_t bound,
+                      SplitBufs& w, uint64_t extra_scan) {
+  const size_t ks = key_bytes(kt);
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  w.tiles1 = hg::div_up(n, hg::kL1Tile);
+  w.max_tiles2 = hg::div_up(n, tile2) + sp.nd1;
+  w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
+                                                           0xFFFFFFFFull));
+  (void)bound;
+  const uint64_t len1 = static_cast<uint64_t>(std::max(sp.nd1, P)) * w.tiles1;
+  const uint64_t scan_max = std::max<uint64_t>(std::max<uint64_t>(len1, w.max_counts2), extra_scan);
+  void *c1 = nullptr, *bs = nullptr, *pl = nullptr, *c2 = nullptr, *b1 = nullptr, *b2 = nullptr;
+  HG_TRY(mem.get(&c1, std::max<uint64_t>(len1, 1) * sizeof(uint32_t)), "allocate level-1 counts");
+  HG_TRY(mem.get(&bs, (hg::div_up(scan_max, hg::kScanChunk) + 1) * sizeof(uint32_t)), "allocate scan workspace");
+  HG_TRY(mem.get(&pl, sizeof(hg::SegPlan)), "allocate split plan");
+  HG_TRY(mem.get(&c2, std::max<uint64_t>(w.max_counts2, 1) * sizeof(uint32_t)), "allocate level-2 counts");
+  HG_TRY(mem.get(&b1, std::max<uint64_t>(n, 1) * ks), "allocate level-1 buffer");
+  HG_TRY(mem.get(&b2, std::max<uint64_t>(n, 1) * ks), "allocate level-2 buffer");
+  w.counts1 = static_cast<uint32_t*>(c1);
+  w.bsums = static_cast<uint32_t*>(bs);
+  w.plan = static_cast<hg::SegPlan*>(pl);
+  w.counts2 = static_cast<uint32_t*>(c2);
+  w.buf1 = b1;
+  w.buf2 = b2;
+  return HG_OK;
+}
+
+// The LDS-sorted build (splits + one LDS counting sort per sub-bin).
+hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P, uint32_t log2P,
+                       const hg_build_opts* opts, bool plain_V, uint64_t bound, const SplitParams& sp,
+                       uint32_t* po, uint32_t* bb, hg::PartDesc* desc, uint32_t* offs, void* keys_out,
+                       uint32_t* long_count, uint32_t* long_list, Allocs& mem, hipStream_t s) {
+  SplitBufs w;
+  hg_status st = alloc_split(mem, n, kt, sp, P, bound, w, 0);
+  if (st != HG_OK) return st;
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  const uint32_t max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
+  if (sp.mode == 0) {
+    HG_LAUNCH("split1_count", s,
+              hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_PART, keys, n, 0, nullptr, P, log2P, P, nullptr, 0,
+                                w.counts1, nullptr, nullptr, nullptr, s));
+    HG_LAUNCH("split1_scan", s,
+              hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(P) * w.tiles1, w.bsums, s));
+    HG_LAUNCH("layout", s,
+              hg::launch_layout(w.counts1, w.tiles1, P, n, opts->ratio_num, opts->ratio_den, 0, po, bb, desc, s));
+  } else {
+    if (P > 1) {
+      HG_LAUNCH("part_count", s, hg::launch_part_count(kt, keys, n, log2P, hg::div_up(n, hg::kTileKeys), w.counts1, s));
+      HG_LAUNCH("part_scan", s,
+                hg::launch_scan_exclusive(w.counts1, nullptr,
+                                          static_cast<uint64_t>(P) * hg::div_up(n, hg::kTileKeys), w.bsums, s));
+      HG_LAUNCH("layout", s,
+                hg::launch_layout(w.counts1, hg::div_up(n, hg::kTileKeys), P, n, opts->ratio_num, opts->ratio_den, 0,
+                                  po, bb, desc, s));
+    } else {
+      HG_LAUNCH("layout", s,
+                hg::launch_layout(nullptr, 0, 1, n, opts->ratio_num, opts->ratio_den,
+                                  plain_V ? opts->num_buckets : 0, po, bb, desc, s));
+    }
+    HG_LAUNCH("split1_count", s,
+              hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_COARSE, keys, n, 0, nullptr, sp.nd1, log2P, P, desc,
+                                sp.sh1, w.counts1, nullptr, nullptr, nullptr, s));
+    HG_LAUNCH("split1_scan", s,
+              hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
+  }
+  HG_LAUNCH("plan", s,
+            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, P, sp.sh1, sp.log2S, tile2, offs, w.plan, s));
+  st = split_two_levels(keys, n, kt, sp, log2P, P, desc, bb, offs, w, s);
+  if (st != HG_OK) return st;
+  HG_LAUNCH("lds_build", s,
+            hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, log2P, P, desc, offs, keys_out,
+                                 long_count, long_list, s));
+  return HG_OK;
+}
+
+// Sorted probe: the table's two splits on the queries, LDS-window counting,
+// two gathers back to input order.
+hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void* out, bool count, hipStream_t s) {
+  const hg_key_type kt = t->kt;
+  SplitParams sp;
+  sp.mode = t->split_mode;
+  sp.sh1 = t->sh1;
+  sp.nd1 = t->nd1;
+  sp.log2S = t->log2S;
+  Allocs mem(s);
+  SplitBufs w;
+  hg_status st = alloc_split(mem, q, kt, sp, t->P, t->buckets_bound, w, 0);
+  if (st != HG_OK) return st;
+  void *c2v = nullptr, *c1v = nullptr;
+  HG_TRY(mem.get(&c2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate split-order counts");
+  HG_TRY(mem.get(&c1v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-1-order counts");
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
+  const uint32_t max_subbins = hg::div_up(t->buckets_bound, 1ull << sp.log2S) + sp.nd1;
+  HG_LAUNCH("qsplit1_count", s,
+            hg::launch_msplit(kt, 1, hg::OP_COUNT, dig1, queries, q, 0, nullptr, sp.nd1, t->log2P, t->P, t->d_desc,
+                              sp.sh1, w.counts1, nullptr, nullptr, nullptr, s));
+  HG_LAUNCH("qsplit1_scan", s,
+            hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
+  HG_LAUNCH("qplan", s,
+            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->P, sp.sh1, sp.log2S, tile2,
+                            nullptr, w.plan, s));
+  st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, t->d_bucket_base, nullptr, w, s);
+  if (st != HG_OK) return st;
+  uint32_t* c2 = static_cast<uint32_t*>(c2v);
+  uint32_t* c1 = static_cast<uint32_t*>(c1v);
+  HG_LAUNCH("lds_probe", s,
+            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, t->log2P, t->P, t->d_desc, t->d_offsets,
+                                 t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
+  HG_LAUNCH("qgather2", s,
+            hg::launch_msplit(kt, 2, hg::OP_GATHER, hg::DIG_SUB, w.buf1, q, w.max_tiles2, w.plan, 0, t->log2P, t->P,
+                              t->d_desc, sp.log2S, w.counts2, nullptr, c2, c1, s));
+  HG_LAUNCH("qgather1", s,
+            hg::launch_msplit(kt, 1, count ? hg::OP_GATHER : hg::OP_GATHER_FOUND, dig1, queries, q, 0, nullptr,
+                              sp.nd1, t->log2P, t->P, t->d_desc, sp.sh1, w.counts1, nullptr, c1, out, s));
+  return HG_OK;
+}
+
+bool use_sorted_probe(const hg_table* t, uint64_t q, uint32_t flags) {
+  if (flags & HG_PROBE_DIRECT) return false;
+  if (flags & HG_PROBE_SORTED) return true;
+  return t->buckets_bound >= (1ull << 22) && q >= (1ull << 20);
+}
+
+hg_status probe(const hg_table* t, const void* d_queries, uint64_t q, void* d_out, bool count, uint32_t flags,
+                hipStream_t s) {
   if (t == nullptr) return fail(HG_ERR_INVALID_ARG, "null table");
   if (q >= (1ull << 32)) return fail(HG_ERR_INVALID_ARG, "q = %llu is not below 2^32", (unsigned long long)q);
   if (q > 0 && (d_queries == nullptr || d_out == nullptr)) return fail(HG_ERR_INVALID_ARG, "null queries or output");
+  if ((flags & ~(HG_PROBE_DIRECT | HG_PROBE_SORTED)) != 0 || flags == (HG_PROBE_DIRECT | HG_PROBE_SORTED))
+    return fail(HG_ERR_INVALID_ARG, "unknown probe flags 0x%x", flags);
   if (q == 0) return HG_OK;
+  if (use_sorted_probe(t, q, flags)) return probe_sorted(t, d_queries, static_cast<uint32_t>(q), d_out, count, s);
   HG_LAUNCH(count ? "probe_count" : "probe_found", s,
-            hg::launch_probe(t->kt, count, t->d_keys, t->d_offsets, t->d_desc, t->log2P, t->P, d_queries,
-                             static_cast<uint32_t>(q), d_out, s));
+            hg::launch_probe(t->kt, count, t->d_keys, t->d_offsets, t->d_desc, t->log2P, t->P, t->d_unsorted,
+                             d_queries, static_cast<uint32_t>(q), d_out, s));
   return HG_OK;
 }
 
@@ -240,7 +467,9 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   hg_status st = check_n_P(n, kt, opts->P);
   if (st != HG_OK) return st;
   if (n > 0 && d_keys == nullptr) return fail(HG_ERR_INVALID_ARG, "null keys");
-  if (opts->reserved0 != 0) return fail(HG_ERR_INVALID_ARG, "reserved field is not 0");
+  if ((opts->flags & ~(HG_BUILD_ATOMIC | HG_BUILD_SORTED)) != 0 ||
+      opts->flags == (HG_BUILD_ATOMIC | HG_BUILD_SORTED))
+    return fail(HG_ERR_INVALID_ARG, "unknown build flags 0x%x", opts->flags);
   const uint32_t P = opts->P;
   const bool plain_V = (P == 1 && opts->num_buckets != 0);
   uint64_t bound;
@@ -263,7 +492,8 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
 
   Allocs mem(stream);
   void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr;
-  const size_t meta_bytes = 2 * sizeof(uint32_t) * (P + 1) + 8 + sizeof(hg::PartDesc) * P;
+  const size_t meta_bytes =
+      2 * sizeof(uint32_t) * (P + 1) + 8 + sizeof(hg::PartDesc) * P + sizeof(uint32_t) * (1 + hg::kMaxUnsorted);
   HG_TRY(mem.get(&keys_out, n * ks), "allocate table keys");
   HG_TRY(mem.get(&offsets, (bound + 1) * sizeof(uint32_t)), "allocate table offsets");
   HG_TRY(mem.get(&meta, meta_bytes), "allocate table metadata");
@@ -272,7 +502,26 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   uintptr_t dp = reinterpret_cast<uintptr_t>(bb + (P + 1));
   dp = (dp + 7) & ~static_cast<uintptr_t>(7);
   hg::PartDesc* desc = reinterpret_cast<hg::PartDesc*>(dp);
+  uint32_t* unsorted = reinterpret_cast<uint32_t*>(desc + P);
 
+  // Long-bucket bookkeeping: at most n / (kLongT + 1) buckets exceed kLongT.
+  void* longv = nullptr;
+  const uint64_t long_cap = n / (hg::kLongT + 1) + 1;
+  HG_TRY(mem.get(&longv, (2 + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
+  uint32_t* long_ctr = static_cast<uint32_t*>(longv);  // [0] count, [1] work counter
+  uint32_t* long_list = long_ctr + 2;
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, 2, 0u, stream));
+  HG_LAUNCH("zero_unsorted", stream, hg::launch_fill_u32(unsorted, 1, 0u, stream));
+
+  const SplitParams sp = split_params(P, n, bound);
+  uint32_t* offs = static_cast<uint32_t*>(offsets);
+  const bool sorted = (opts->flags & HG_BUILD_SORTED) != 0 ||
+                      ((opts->flags & HG_BUILD_ATOMIC) == 0 && bound >= (1ull << 22) && n >= (1ull << 20));
+  if (sorted) {
+    st = build_sorted(d_keys, n32, kt, P, log2P, opts, plain_V, bound, sp, po, bb, desc, offs, keys_out, long_ctr,
+                      long_list, mem, stream);
+    if (st != HG_OK) return st;
+  } else {
   const uint64_t part_elems = P > 1 ? static_cast<uint64_t>(P) * num_tiles : 0;
   const uint64_t scan_max = part_elems > bound ? part_elems : bound;
   void *tile_counts = nullptr, *buffer = nullptr, *bsums = nullptr;
@@ -295,12 +544,15 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
                                 plain_V ? opts->num_buckets : 0, po, bb, desc, stream));
   }
 
-  uint32_t* offs = static_cast<uint32_t*>(offsets);
   HG_LAUNCH("zero_counts", stream, hg::launch_fill_u32(offs, bound + 1, 0u, stream));
   HG_LAUNCH("bucket_hist", stream, hg::launch_hist(kt, src, n32, log2P, P, desc, offs + 1, stream));
   HG_LAUNCH("bucket_scan", stream,
             hg::launch_scan_exclusive(offs + 1, bb + P, bound, static_cast<uint32_t*>(bsums), stream));
   HG_LAUNCH("bucket_scatter", stream, hg::launch_scatter(kt, src, n32, log2P, P, desc, offs + 1, keys_out, stream));
+  HG_LAUNCH("find_long", stream, hg::launch_find_long(offs, bb + P, bound, long_ctr, long_list, stream));
+  }
+  HG_LAUNCH("long_sort", stream,
+            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted, stream));
 
   hg_table* t = new hg_table();
   t->device = device;
@@ -316,6 +568,11 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   t->d_part_offsets = po;
   t->d_bucket_base = bb;
   t->d_desc = desc;
+  t->d_unsorted = unsorted;
+  t->split_mode = sp.mode;
+  t->sh1 = sp.sh1;
+  t->nd1 = sp.nd1;
+  t->log2S = sp.log2S;
   t->have_num_buckets = false;
   t->num_buckets = 0;
   mem.release(keys_out);
@@ -326,11 +583,21 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
 }
 
 hg_status hg_count(const hg_table* table, const void* d_queries, uint64_t q, uint32_t* d_counts, hipStream_t stream) {
-  return probe(table, d_queries, q, d_counts, true, stream);
+  return probe(table, d_queries, q, d_counts, true, 0, stream);
 }
 
 hg_status hg_query(const hg_table* table, const void* d_queries, uint64_t q, uint8_t* d_found, hipStream_t stream) {
-  return probe(table, d_queries, q, d_found, false, stream);
+  return probe(table, d_queries, q, d_found, false, 0, stream);
+}
+
+hg_status hg_count_ex(const hg_table* table, const void* d_queries, uint64_t q, uint32_t* d_counts, uint32_t flags,
+                      hipStream_t stream) {
+  return probe(table, d_queries, q, d_counts, true, flags, stream);
+}
+
+hg_status hg_query_ex(const hg_table* table, const void* d_queries, uint64_t q, uint8_t* d_found, uint32_t flags,
+                      hipStream_t stream) {
+  return probe(table, d_queries, q, d_found, false, flags, stream);
 }
 
 hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t P, void* d_out_keys,

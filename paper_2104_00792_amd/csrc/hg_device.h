@@ -124,4 +124,38 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
   return v;
 }
 
+// ------------------------------------------------------ bucket counting
+// Whether long bucket g is known to be sorted (see the table's unsorted
+// block: word 0 = number of unsorted long buckets, then their ids).
+__device__ __forceinline__ bool long_bucket_sorted(const uint32_t* unsorted, uint32_t nunsorted, uint32_t g,
+                                                   uint32_t max_listed) {
+  if (nunsorted == 0) return true;
+  if (nunsorted > max_listed) return false;
+  for (uint32_t i = 0; i < nunsorted; ++i)
+    if (unsorted[1 + i] == g) return false;
+  return true;
+}
+
+// Occurrences of q among a[lo, hi): a linear scan, or two binary searches
+// when the range is sorted.
+template <typename K, typename Ptr>
+__device__ __forceinline__ uint32_t count_equal(Ptr a, uint32_t lo, uint32_t hi, K q, bool sorted) {
+  if (!sorted) {
+    uint32_t c = 0;
+    for (uint32_t x = lo; x < hi; ++x) c += a[x] == q ? 1u : 0u;
+    return c;
+  }
+  uint32_t l = lo, h = hi;  // first position with a[x] >= q
+  while (l < h) {
+    const uint32_t mid = l + ((h - l) >> 1);
+    if (a[mid] < q) l = mid + 1; else h = mid;
+  }
+  uint32_t u = l, uh = hi;  // first position with a[x] > q
+  while (u < uh) {
+    const uint32_t mid = u + ((uh - u) >> 1);
+    if (a[mid] <= q) u = mid + 1; else uh = mid;
+  }
+  return u - l;
+}
+
 }  // namespace hg

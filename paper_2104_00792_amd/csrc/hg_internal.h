@@ -17,6 +17,97 @@ constexpr uint32_t kMaxP = 256;
 
 inline uint32_t div_up(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
 
+// ------------------------------------------------ the LDS-sorted path
+// Keys (or queries) reach LDS-sized sub-bins of 2^log2S buckets through two
+// stable multisplits: level 1 by partition or coarse bucket range (one
+// segment, <= 256 digits, 4096-key tiles), level 2 by sub-bin inside each
+// level-1 segment (<= kMaxD2 digits, kL2Threads x 16 (32-bit) or x 8 (64-bit)
+// key tiles).  The LDS stages then sort (build) or probe one sub-bin per
+// workgroup.
+constexpr int kMaxSeg = 256;
+constexpr uint32_t kLog2SMax = 14;  // regular sub-bins: 2^log2S <= 2^14 buckets
+constexpr uint32_t kLog2SMin = 10;
+constexpr uint32_t kLog2SLds = 15;  // a segment's last sub-bin may grow to 2^15 in LDS
+constexpr uint32_t kMaxD2 = 1024;
+constexpr int kL1Threads = 256;
+constexpr int kL1Tile = kL1Threads * 16;
+constexpr int kL2Threads = 512;
+constexpr int kLdsThreads = 1024;
+constexpr uint32_t kMaxLog2W = 13;  // probe window: at most 2^13 buckets in LDS
+constexpr uint32_t kProbeKeyCapBytes = 40 * 1024;  // table keys of one window in LDS
+
+// Long buckets (more than kLongT keys) are left sorted by the build so that
+// a probe counts them by binary search.  Buckets the build could not sort are
+// listed in the table's `unsorted` block: word 0 holds their number, words
+// 1 .. kMaxUnsorted their ids (when the number exceeds kMaxUnsorted, every
+// long bucket is scanned).
+constexpr uint32_t kLongT = 64;
+constexpr uint32_t kMaxUnsorted = 256;
+constexpr int kLongThreads = 256;
+constexpr uint32_t kLongGrid = 2048;
+
+// Long buckets of an atomic-path build: appended to long_list.
+hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,
+                            uint32_t* long_count, uint32_t* long_list, hipStream_t s);
+// Sort every listed long bucket in place (persistent workgroups; `work` is a
+// zeroed counter).
+hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
+                            uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s);
+
+inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 16 : 8); }
+
+// Segments of the level-2 split and sub-bins of the LDS stages, computed on
+// the device (no host round trip).  Segment s holds keys key0[s] .. key0[s+1]
+// of the level-1 output and global buckets g0[s] .. g0[s+1]; it has T[s]
+// level-2 tiles and D[s] sub-bins; its per-tile digit counts start at
+// cbase[s] and are laid out [digit][tile].
+struct SegPlan {
+  uint32_t nseg, total_tiles, total_counts, total_subbins;
+  uint32_t num_buckets, n, tile_keys, log2S;
+  uint32_t key0[kMaxSeg + 1];
+  uint32_t g0[kMaxSeg + 1];
+  uint32_t D[kMaxSeg + 1];
+  uint32_t T[kMaxSeg + 1];
+  uint32_t tile_first[kMaxSeg + 1];
+  uint32_t cbase[kMaxSeg + 1];
+  uint32_t sb_first[kMaxSeg + 1];
+};
+
+enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2 };
+enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1, OP_GATHER = 2, OP_GATHER_FOUND = 3 };
+
+// One multisplit pass.  level 1: a single segment [0, n) with nd digits and
+// grid ceil(n / kL1Tile); level 2: segments from `plan`, grid max_tiles.
+// dig/shift: DIG_PART (partition), DIG_COARSE (global bucket >> shift, capped
+// at nd - 1), DIG_SUB (bucket offset in the segment >> shift, capped).
+// COUNT writes per-tile digit counts; SCATTER moves `in` to `out` using the
+// scanned counts; GATHER reads gsrc at the scattered positions and writes
+// gdst in the order of `in` (u32 values, or 0/1 bytes for GATHER_FOUND).
+hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
+                         const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                         uint32_t shift, uint32_t* counts, void* out, const uint32_t* gsrc, void* gdst,
+                         hipStream_t s);
+
+// Plan of the level-2 split from the scanned level-1 counts.  mode 0: the
+// level-1 digits are partitions (g0 = bucket_base); mode 1: coarse bucket
+// ranges of 2^sh1.  Writes offsets[num_buckets] = n when offsets is not null.
+hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
+                       const uint32_t* bucket_base, uint32_t P, uint32_t sh1, uint32_t log2S, uint32_t tile2,
+                       uint32_t* offsets, SegPlan* plan, hipStream_t s);
+
+// One workgroup per sub-bin: LDS counting sort of its keys by bucket; writes
+// the sub-bin's CSR offsets and keys.  grid = max_subbins.
+hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
+                            uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
+                            uint32_t* long_count, uint32_t* long_list, hipStream_t s);
+
+// One workgroup per sub-bin of queries: windows of 2^log2W buckets of the
+// table (offsets and keys) in LDS; counts in the split order.
+hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
+                            uint32_t max_subbins, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                            const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
+                            uint32_t* c2, hipStream_t s);
+
 // kt: 0 = 32-bit keys, 1 = 64-bit keys.
 hipError_t launch_fill_u32(uint32_t* p, uint64_t len, uint32_t value, hipStream_t s);
 
@@ -45,8 +136,8 @@ hipError_t launch_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, 
                           const PartDesc* desc, uint32_t* cursor, void* out, hipStream_t s);
 
 hipError_t launch_probe(int kt, bool count, const void* tkeys, const uint32_t* offsets,
-                        const PartDesc* desc, uint32_t log2P, uint32_t P, const void* queries,
-                        uint32_t q, void* out, hipStream_t s);
+                        const PartDesc* desc, uint32_t log2P, uint32_t P, const uint32_t* unsorted,
+                        const void* queries, uint32_t q, void* out, hipStream_t s);
 
 hipError_t launch_hash_bucket(int kt, const void* keys, uint32_t n, uint32_t V, uint64_t* hash,
                               uint32_t* bucket, hipStream_t s);

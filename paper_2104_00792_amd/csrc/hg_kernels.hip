@@ -12,6 +12,7 @@
 // base is 16-byte aligned, and recomputes the hash instead of storing it
 // (the paper materialises H_A; recomputing saves 8 bytes per key per pass).
 #include "hg_internal.h"
+#include "hg_tile.h"
 
 namespace hg {
 namespace {
@@ -65,146 +66,10 @@ __device__ __forceinline__ uint32_t load_tile(const K* __restrict__ src, uint32_
   return mask;
 }
 
-// Exclusive sum over the workgroup; `total` receives the sum of all values.
-// Every thread of the workgroup must call it (it contains barriers).
-__device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* wtot, uint32_t& total) {
-  const uint32_t inc = wave_inclusive_sum(v);
-  const uint32_t w = threadIdx.x / kWave;
-  if (lane_id() == kWave - 1) wtot[w] = inc;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int x = 0; x < kWaves; ++x) {
-    const uint32_t c = wtot[x];
-    base += (x < static_cast<int>(w)) ? c : 0u;
-    tot += c;
-  }
-  __syncthreads();
-  total = tot;
-  return base + inc - v;
-}
-
-// Wave-level multisplit (ballot on each digit bit, as in Ashkiani et al.,
-// "GPU Multisplit", PPoPP 2016): for item i of every lane, the lanes holding
-// the same digit form `match`; the item's rank is this wave's running count of
-// its digit (wcnt, private to the wave) plus the matching lanes below it.
-// The order is (item, lane): deterministic, so an inverse pass can recompute it.
-__device__ __forceinline__ void wave_multisplit(const uint32_t (&d)[kItems], uint32_t mask,
-                                                uint32_t log2P, uint32_t* wcnt,
-                                                uint32_t (&rank)[kItems]) {
-  const uint64_t lt = lanemask_lt();
-#pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    const bool valid = (mask >> i) & 1u;
-    uint64_t match = ballot(valid);
-    for (uint32_t b = 0; b < log2P; ++b) {
-      const bool bit = (d[i] >> b) & 1u;
-      const uint64_t bb = ballot(bit);
-      match &= bit ? bb : ~bb;
-    }
-    const uint32_t below = popc64(match & lt);
-    uint32_t prior = 0;
-    if (valid) prior = wcnt[d[i]];
-    __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0) wcnt[d[i]] = prior + popc64(match);
-    __builtin_amdgcn_wave_barrier();
-    rank[i] = prior + below;
-  }
-}
-
-template <typename K>
-__device__ __forceinline__ void tile_digits(const K (&v)[kItems], uint32_t mask, uint32_t log2P,
-                                            uint32_t (&d)[kItems]) {
-#pragma unroll
-  for (int i = 0; i < kItems; ++i)
-    d[i] = ((mask >> i) & 1u) ? part_of(KeyTraits<K>::hash(v[i]), log2P) : 0u;
-}
-
 // ------------------------------------------------------------------ fill
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint64_t len, uint32_t value) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < len; i += stride) p[i] = value;
-}
-
-// ------------------------------------------------- partition count (a2)
-// tile_counts is partition-major: tile_counts[p * num_tiles + tile].
-template <typename K>
-__global__ __launch_bounds__(kBlock) void k_part_count(const K* __restrict__ keys, uint32_t n, uint32_t log2P,
-                                                       uint32_t num_tiles, uint32_t* __restrict__ tile_counts) {
-  __shared__ uint32_t wcnt[kWaves][kMaxP];
-  const uint32_t t = threadIdx.x, w = t / kWave, P = 1u << log2P;
-  for (uint32_t i = t; i < kWaves * kMaxP; i += kBlock) (&wcnt[0][0])[i] = 0;
-  __syncthreads();
-  K v[kItems];
-  uint32_t d[kItems], r[kItems];
-  const uint32_t mask = load_tile(keys, n, blockIdx.x, v);
-  tile_digits(v, mask, log2P, d);
-  wave_multisplit(d, mask, log2P, wcnt[w], r);
-  __syncthreads();
-  for (uint32_t p = t; p < P; p += kBlock) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int x = 0; x < kWaves; ++x) s += wcnt[x][p];
-    tile_counts[static_cast<uint64_t>(p) * num_tiles + blockIdx.x] = s;
-  }
-}
-
-// ---------------------------------------------- partition scatter (a4)
-// tile_base: exclusive scan of tile_counts in (partition, tile) order, i.e.
-// the output position of this tile's first key of every partition.
-template <typename K>
-__global__ __launch_bounds__(kBlock) void k_part_scatter(const K* __restrict__ keys, uint32_t n, uint32_t log2P,
-                                                         uint32_t num_tiles, const uint32_t* __restrict__ tile_base,
-                                                         K* __restrict__ out) {
-  __shared__ uint32_t wcnt[kWaves][kMaxP];
-  __shared__ uint32_t dstart[kMaxP];
-  __shared__ uint32_t gbase[kMaxP];
-  __shared__ uint32_t wtot[kWaves];
-  __shared__ K stage[kTileKeys];
-  __shared__ uint8_t sdig[kTileKeys];
-  const uint32_t t = threadIdx.x, w = t / kWave, P = 1u << log2P, tile = blockIdx.x;
-  for (uint32_t i = t; i < kWaves * kMaxP; i += kBlock) (&wcnt[0][0])[i] = 0;
-  for (uint32_t p = t; p < P; p += kBlock) gbase[p] = tile_base[static_cast<uint64_t>(p) * num_tiles + tile];
-  __syncthreads();
-  K v[kItems];
-  uint32_t d[kItems], r[kItems];
-  const uint32_t mask = load_tile(keys, n, tile, v);
-  tile_digits(v, mask, log2P, d);
-  wave_multisplit(d, mask, log2P, wcnt[w], r);
-  __syncthreads();
-  // Per digit: wave bases inside the digit, then digit starts in the tile.
-  uint32_t tot = 0;
-  if (t < P) {
-#pragma unroll
-    for (int x = 0; x < kWaves; ++x) {
-      const uint32_t c = wcnt[x][t];
-      wcnt[x][t] = tot;
-      tot += c;
-    }
-  }
-  uint32_t total;
-  const uint32_t ex = block_exclusive_sum(t < P ? tot : 0u, wtot, total);
-  if (t < P) {
-    dstart[t] = ex;
-#pragma unroll
-    for (int x = 0; x < kWaves; ++x) wcnt[x][t] += ex;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kItems; ++i) {
-    if ((mask >> i) & 1u) {
-      const uint32_t pos = wcnt[w][d[i]] + r[i];
-      stage[pos] = v[i];
-      sdig[pos] = static_cast<uint8_t>(d[i]);
-    }
-  }
-  __syncthreads();
-  const uint64_t start = static_cast<uint64_t>(tile) * kTileKeys;
-  const uint32_t len = static_cast<uint32_t>(min(static_cast<uint64_t>(kTileKeys), n - start));
-  for (uint32_t j = t; j < len; j += kBlock) {
-    const uint32_t dd = sdig[j];
-    out[gbase[dd] + (j - dstart[dd])] = stage[j];
-  }
 }
 
 // ------------------------------------------------------------- scans (a3, a6)
@@ -220,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     if (e < len) s += a[e];
   }
   uint32_t total;
-  block_exclusive_sum(s, wtot, total);
+  block_exclusive_sum<kBlock>(s, wtot, total);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
@@ -238,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_spine(uint32_t* __restrict__ bs
       s += x[j];
     }
     uint32_t total;
-    uint32_t run = carry + block_exclusive_sum(s, wtot, total);
+    uint32_t run = carry + block_exclusive_sum<kBlock>(s, wtot, total);
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const uint32_t idx = c0 + threadIdx.x * kPer + j;
@@ -274,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
     s += x[j];
   }
   uint32_t total;
-  uint32_t run = block_sums[blockIdx.x] + block_exclusive_sum(s, wtot, total);
+  uint32_t run = block_sums[blockIdx.x] + block_exclusive_sum<kBlock>(s, wtot, total);
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const uint32_t i = t * kPer + j;
@@ -315,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_layout(const uint32_t* __restrict__ 
     V = static_cast<uint32_t>(v);
   }
   uint32_t total;
-  const uint32_t ex = block_exclusive_sum(V, wtot, total);
+  const uint32_t ex = block_exclusive_sum<kBlock>(V, wtot, total);
   if (t < P) {
     PartDesc pd;
     pd.V = V;
@@ -406,31 +271,33 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const K* __restrict__ keys, 
 template <typename K, bool kCount>
 __global__ __launch_bounds__(kBlock) void k_probe(const K* __restrict__ tkeys, const uint32_t* __restrict__ offs,
                                                   const PartDesc* __restrict__ desc, uint32_t log2P, uint32_t P,
-                                                  const K* __restrict__ qs, uint32_t q, void* __restrict__ out) {
+                                                  const uint32_t* __restrict__ unsorted, const K* __restrict__ qs,
+                                                  uint32_t q, void* __restrict__ out) {
   __shared__ PartDesc sd[kMaxP];
   for (uint32_t i = threadIdx.x; i < P; i += kBlock) sd[i] = desc[i];
   __syncthreads();
   K v[kItems];
   const uint32_t mask = load_tile(qs, q, blockIdx.x, v);
-  uint32_t lo[kItems], hi[kItems];
+  uint32_t lo[kItems], hi[kItems], gb[kItems];
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    uint32_t g = 0;
+    gb[i] = 0;
     if ((mask >> i) & 1u) {
       const auto h = KeyTraits<K>::hash(v[i]);
-      g = global_bucket(h, sd[part_of(h, log2P)]);
-      lo[i] = offs[g];
-      hi[i] = offs[g + 1];
+      gb[i] = global_bucket(h, sd[part_of(h, log2P)]);
+      lo[i] = offs[gb[i]];
+      hi[i] = offs[gb[i] + 1];
     } else {
       lo[i] = hi[i] = 0;
     }
   }
+  const uint32_t nuns = unsorted[0];
   const uint64_t start = static_cast<uint64_t>(blockIdx.x) * kTileKeys;
 #pragma unroll
   for (int i = 0; i < kItems; ++i) {
-    uint32_t c = 0;
-    for (uint32_t j = lo[i]; j < hi[i]; ++j) c += (tkeys[j] == v[i]) ? 1u : 0u;
     if ((mask >> i) & 1u) {
+      const bool srt = hi[i] - lo[i] > kLongT && long_bucket_sorted(unsorted, nuns, gb[i], kMaxUnsorted);
+      const uint32_t c = count_equal(tkeys, lo[i], hi[i], v[i], srt);
       const uint64_t e = start + tile_index<K>(i, threadIdx.x);
       if (kCount)
         static_cast<uint32_t*>(out)[e] = c;
@@ -467,26 +334,20 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t len, uint32_t value, hipStream_
   return hipGetLastError();
 }
 
+// The partition split is the level-1 multisplit with partition digits
+// (4096-key tiles, counts laid out [partition][tile]).
 hipError_t launch_part_count(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t num_tiles,
                              uint32_t* tile_counts, hipStream_t s) {
-  if (num_tiles == 0) return hipSuccess;
-  if (kt == 0)
-    k_part_count<uint32_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, num_tiles, tile_counts);
-  else
-    k_part_count<uint64_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, num_tiles, tile_counts);
-  return hipGetLastError();
+  (void)num_tiles;
+  return launch_msplit(kt, 1, OP_COUNT, DIG_PART, keys, n, 0, nullptr, 1u << log2P, log2P, 1u << log2P, nullptr, 0,
+                       tile_counts, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_part_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t num_tiles,
                                const uint32_t* tile_base, void* out, hipStream_t s) {
-  if (num_tiles == 0) return hipSuccess;
-  if (kt == 0)
-    k_part_scatter<uint32_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, log2P, num_tiles,
-                                                          tile_base, static_cast<uint32_t*>(out));
-  else
-    k_part_scatter<uint64_t><<<num_tiles, kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, log2P, num_tiles,
-                                                          tile_base, static_cast<uint64_t*>(out));
-  return hipGetLastError();
+  (void)num_tiles;
+  return launch_msplit(kt, 1, OP_SCATTER, DIG_PART, keys, n, 0, nullptr, 1u << log2P, log2P, 1u << log2P, nullptr, 0,
+                       const_cast<uint32_t*>(tile_base), out, nullptr, nullptr, s);
 }
 
 hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t len_bound, uint32_t* block_sums,
@@ -535,23 +396,24 @@ hipError_t launch_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, 
 }
 
 hipError_t launch_probe(int kt, bool count, const void* tkeys, const uint32_t* offsets, const PartDesc* desc,
-                        uint32_t log2P, uint32_t P, const void* queries, uint32_t q, void* out, hipStream_t s) {
+                        uint32_t log2P, uint32_t P, const uint32_t* unsorted, const void* queries, uint32_t q,
+                        void* out, hipStream_t s) {
   const uint32_t tiles = div_up(q, kTileKeys);
   if (tiles == 0) return hipSuccess;
   if (kt == 0) {
     const uint32_t* tk = static_cast<const uint32_t*>(tkeys);
     const uint32_t* qs = static_cast<const uint32_t*>(queries);
     if (count)
-      k_probe<uint32_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+      k_probe<uint32_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, unsorted, qs, q, out);
     else
-      k_probe<uint32_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+      k_probe<uint32_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, unsorted, qs, q, out);
   } else {
     const uint64_t* tk = static_cast<const uint64_t*>(tkeys);
     const uint64_t* qs = static_cast<const uint64_t*>(queries);
     if (count)
-      k_probe<uint64_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+      k_probe<uint64_t, true><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, unsorted, qs, q, out);
     else
-      k_probe<uint64_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, qs, q, out);
+      k_probe<uint64_t, false><<<tiles, kBlock, 0, s>>>(tk, offsets, desc, log2P, P, unsorted, qs, q, out);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,856 @@
+// The LDS-sorted HashGraph path for gfx950.
+//
+// Algorithm 1 of Tripathy & Green (arXiv 2104.00792) counts keys per hash
+// value, prefix-sums the counts and scatters the keys with atomics at random
+// addresses.  At 2^28 keys those random accesses miss every cache; here the
+// same result is reached with streaming passes only:
+//   level-1 split  by partition (Algorithm 2, Phase 2) or by coarse bucket
+//                  range, stable, per-tile counts + scan + scatter;
+//   level-2 split  by sub-bin of 2^15 buckets inside each level-1 segment
+//                  (the paper's second, local binning for cache locality,
+//                  Sec. 3.2, sized here for the 160 KiB LDS of a CU);
+//   LDS build      one workgroup per sub-bin: histogram, exclusive scan and
+//                  scatter of Algorithm 1, all three in LDS.
+// Queries follow the same two splits, are counted against LDS-resident
+// windows of the table, and return to their input order by two gather passes
+// that recompute the stable ranks (the inverse permutations are never
+// stored).
+#include "hg_internal.h"
+#include "hg_tile.h"
+
+namespace hg {
+namespace {
+
+template <typename K>
+__device__ __forceinline__ uint32_t bucket_of(K key, uint32_t log2P, const PartDesc* sd) {
+  const auto h = KeyTraits<K>::hash(key);
+  return global_bucket(h, sd[part_of(h, log2P)]);
+}
+
+// Index of the last segment whose prefix value is <= x (arr[0] == 0, arr is
+// non-decreasing over 0..nseg).
+__device__ __forceinline__ uint32_t find_segment(const uint32_t* arr, uint32_t nseg, uint32_t x) {
+  uint32_t lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (arr[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ multisplit
+// Item i of thread t holds element elem(i, t) of its tile: with 16-byte loads
+// (a whole, aligned tile) thread t reads kVec consecutive keys per load;
+// otherwise one key per load, striped over the workgroup.  Both passes over a
+// tile take the same branch, so their orders agree.
+template <typename K, int THREADS>
+__device__ __forceinline__ uint32_t elem_of(bool vec, int i, uint32_t t) {
+  constexpr int kVec = 16 / sizeof(K);
+  return vec ? (static_cast<uint32_t>(i / kVec) * THREADS + t) * kVec + static_cast<uint32_t>(i % kVec)
+             : static_cast<uint32_t>(i) * THREADS + t;
+}
+
+template <typename K, int THREADS, int ITEMS>
+__device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_t tstart, uint32_t tlen, bool vec,
+                                               K (&v)[ITEMS]) {
+  constexpr int kVec = 16 / sizeof(K);
+  const uint32_t t = threadIdx.x;
+  if (vec) {
+    const uint4* p = reinterpret_cast<const uint4*>(in + tstart);
+#pragma unroll
+    for (int j = 0; j < ITEMS / kVec; ++j) {
+      const uint4 x = p[j * THREADS + t];
+      K tmp[kVec];
+      __builtin_memcpy(tmp, &x, 16);
+#pragma unroll
+      for (int c = 0; c < kVec; ++c) v[j * kVec + c] = tmp[c];
+    }
+    return ITEMS == 32 ? 0xFFFFFFFFu : ((1u << ITEMS) - 1u);
+  }
+  uint32_t mask = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t e = static_cast<uint32_t>(i) * THREADS + t;
+    if (e < tlen) {
+      v[i] = in[tstart + e];
+      mask |= 1u << i;
+    }
+  }
+  return mask;
+}
+
+template <typename K, int THREADS, int ITEMS, int MAXD, int OP, int DIG>
+__global__ __launch_bounds__(THREADS) void k_msplit(const K* __restrict__ in, uint32_t n,
+                                                    const SegPlan* __restrict__ plan, uint32_t nd, uint32_t log2P,
+                                                    uint32_t P, const PartDesc* __restrict__ desc, uint32_t shift,
+                                                    uint32_t* __restrict__ counts, K* __restrict__ out,
+                                                    const uint32_t* __restrict__ gsrc, void* __restrict__ gdst) {
+  constexpr int W = THREADS / kWave;
+  constexpr int TILE = THREADS * ITEMS;
+  constexpr bool kCount = OP == OP_COUNT;
+  constexpr bool kStageKeys = OP == OP_SCATTER;
+  constexpr bool kStageVals = OP == OP_GATHER || OP == OP_GATHER_FOUND;
+  __shared__ uint32_t hist[kCount ? MAXD : 1];
+  __shared__ uint32_t wcnt[kCount ? 1 : W][kCount ? 1 : MAXD / 2];
+  __shared__ uint32_t dstart[kCount ? 1 : MAXD];
+  __shared__ uint32_t gbase[kCount ? 1 : MAXD];
+  __shared__ uint32_t wtot[W];
+  __shared__ PartDesc sd[DIG == DIG_PART ? 1 : kMaxP];
+  __shared__ K stage_k[kStageKeys ? TILE : 1];
+  __shared__ uint32_t stage_v[kStageVals ? TILE : 1];
+  __shared__ uint16_t sdig[kCount ? 1 : TILE];
+
+  const uint32_t t = threadIdx.x, w = t / kWave, b = blockIdx.x;
+  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl = b;
+  if (plan != nullptr) {
+    if (b >= plan->total_tiles) return;  // whole workgroup
+    const uint32_t seg = find_segment(plan->tile_first, plan->nseg, b);
+    tl = b - plan->tile_first[seg];
+    D = plan->D[seg];
+    T = plan->T[seg];
+    k0 = plan->key0[seg];
+    k1 = plan->key0[seg + 1];
+    cb = plan->cbase[seg];
+    gs = plan->g0[seg];
+  }
+  const uint32_t tstart = k0 + tl * TILE;
+  const uint32_t tlen = min(static_cast<uint32_t>(TILE), k1 - tstart);
+  const bool vec = tlen == static_cast<uint32_t>(TILE) && (reinterpret_cast<uintptr_t>(in + tstart) & 15) == 0;
+
+  if (DIG != DIG_PART)
+    for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+  if (kCount) {
+    for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
+  } else {
+    for (uint32_t i = t; i < static_cast<uint32_t>(W * MAXD / 2); i += THREADS) (&wcnt[0][0])[i] = 0;
+  }
+  __syncthreads();
+
+  K v[ITEMS];
+  uint32_t d[ITEMS];
+  const uint32_t mask = load_items<K, THREADS, ITEMS>(in, tstart, tlen, vec, v);
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    d[i] = 0;
+    if ((mask >> i) & 1u) {
+      if (DIG == DIG_PART) {
+        d[i] = part_of(KeyTraits<K>::hash(v[i]), log2P);
+      } else {
+        const uint32_t g = bucket_of(v[i], log2P, sd);
+        d[i] = min((g - gs) >> shift, D - 1);
+      }
+    }
+  }
+
+  if (kCount) {
+    // Order does not matter for counts: one LDS atomic per key.
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+      if ((mask >> i) & 1u) atomicAdd(&hist[d[i]], 1u);
+    __syncthreads();
+    for (uint32_t dd = t; dd < D; dd += THREADS) counts[cb + dd * T + tl] = hist[dd];
+    return;
+  }
+
+  uint32_t r[ITEMS];
+  wave_multisplit<ITEMS>(d, mask, digit_bits(D), wcnt[w], r);
+  __syncthreads();
+
+  // Thread t owns digits 2t and 2t+1 (one packed word per wave): it turns
+  // the waves' counts into exclusive prefixes over the waves in place, then
+  // the digit totals give each digit's start in the tile and its output base.
+  static_assert(MAXD <= 2 * THREADS, "two digits per thread");
+  uint32_t tlo = 0, thi = 0;
+  if (2 * t < D) {
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+      const uint32_t c = wcnt[x][t];
+      wcnt[x][t] = tlo | (thi << 16);
+      tlo += c & 0xFFFFu;
+      thi += c >> 16;
+    }
+  }
+  uint32_t total;
+  const uint32_t ex = block_exclusive_sum<THREADS>(tlo + thi, wtot, total);
+  if (2 * t < D) {
+    dstart[2 * t] = ex;
+    gbase[2 * t] = counts[cb + (2 * t) * T + tl];
+  }
+  if (2 * t + 1 < D) {
+    dstart[2 * t + 1] = ex + tlo;
+    gbase[2 * t + 1] = counts[cb + (2 * t + 1) * T + tl];
+  }
+  __syncthreads();
+
+  uint32_t pos[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    pos[i] = 0;
+    if ((mask >> i) & 1u) {
+      pos[i] = dstart[d[i]] + get_half(wcnt[w], d[i]) + r[i];
+      if (kStageKeys) stage_k[pos[i]] = v[i];
+      sdig[pos[i]] = static_cast<uint16_t>(d[i]);
+    }
+  }
+  __syncthreads();
+
+  if (OP == OP_SCATTER) {
+    for (uint32_t j = t; j < tlen; j += THREADS) {
+      const uint32_t dd = sdig[j];
+      out[gbase[dd] + (j - dstart[dd])] = stage_k[j];
+    }
+    return;
+  }
+
+  // Gather: the values of this tile's keys sit in digit runs of gsrc, at the
+  // positions the scatter gave them; read the runs in order, then hand each
+  // value back to its key's original place.
+  for (uint32_t j = t; j < tlen; j += THREADS) {
+    const uint32_t dd = sdig[j];
+    stage_v[j] = gsrc[gbase[dd] + (j - dstart[dd])];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    if ((mask >> i) & 1u) {
+      const uint32_t e = tstart + elem_of<K, THREADS>(vec, i, t);
+      if (OP == OP_GATHER)
+        static_cast<uint32_t*>(gdst)[e] = stage_v[pos[i]];
+      else
+        static_cast<uint8_t*>(gdst)[e] = stage_v[pos[i]] != 0 ? 1 : 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plan
+__global__ __launch_bounds__(kMaxSeg) void k_plan(const uint32_t* __restrict__ scan1, uint32_t tiles1,
+                                                  uint32_t nseg, uint32_t n, int mode,
+                                                  const uint32_t* __restrict__ bb, uint32_t P, uint32_t sh1,
+                                                  uint32_t log2S, uint32_t tile2, uint32_t* __restrict__ offsets,
+                                                  SegPlan* __restrict__ plan) {
+  __shared__ uint32_t wtot[kMaxSeg / kWave];
+  const uint32_t t = threadIdx.x;
+  const uint32_t NB = bb[P];
+  uint32_t key0 = 0, g0 = 0, T = 0, D = 0;
+  if (t < nseg) {
+    key0 = tiles1 != 0 ? scan1[t * tiles1] : 0u;
+    const uint32_t key1 = (t + 1 < nseg) ? (tiles1 != 0 ? scan1[(t + 1) * tiles1] : 0u) : n;
+    uint32_t g1;
+    if (mode == 0) {
+      g0 = bb[t];
+      g1 = bb[t + 1];
+    } else {
+      g0 = static_cast<uint32_t>(min(static_cast<uint64_t>(t) << sh1, static_cast<uint64_t>(NB)));
+      g1 = (t + 1 < nseg) ? static_cast<uint32_t>(min(static_cast<uint64_t>(t + 1) << sh1, static_cast<uint64_t>(NB)))
+                          : NB;
+    }
+    T = (key1 - key0 + tile2 - 1) / tile2;
+    const uint64_t R = g1 - g0;
+    D = R == 0 ? 0u : static_cast<uint32_t>(min((R + (1ull << log2S) - 1) >> log2S, static_cast<uint64_t>(kMaxD2)));
+  }
+  uint32_t tot_T, tot_C, tot_D;
+  const uint32_t tf = block_exclusive_sum<kMaxSeg>(T, wtot, tot_T);
+  const uint32_t cbv = block_exclusive_sum<kMaxSeg>(D * T, wtot, tot_C);
+  const uint32_t sbf = block_exclusive_sum<kMaxSeg>(D, wtot, tot_D);
+  if (t < nseg) {
+    plan->key0[t] = key0;
+    plan->g0[t] = g0;
+    plan->D[t] = D;
+    plan->T[t] = T;
+    plan->tile_first[t] = tf;
+    plan->cbase[t] = cbv;
+    plan->sb_first[t] = sbf;
+  }
+  if (t == 0) {
+    plan->key0[nseg] = n;
+    plan->g0[nseg] = NB;
+    plan->D[nseg] = 0;
+    plan->T[nseg] = 0;
+    plan->tile_first[nseg] = tot_T;
+    plan->cbase[nseg] = tot_C;
+    plan->sb_first[nseg] = tot_D;
+    plan->nseg = nseg;
+    plan->total_tiles = tot_T;
+    plan->total_counts = tot_C;
+    plan->total_subbins = tot_D;
+    plan->num_buckets = NB;
+    plan->n = n;
+    plan->tile_keys = tile2;
+    plan->log2S = log2S;
+    if (offsets != nullptr) offsets[NB] = n;
+  }
+}
+
+// Sub-bin `b` of a plan: its segment, bucket range [gA, gB) and key range
+// [kA, kB) in the level-2 output (scan2 = scanned level-2 counts).
+struct SubBin {
+  uint32_t gA, gB, kA, kB;
+};
+
+__device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* scan2, uint32_t b) {
+  const uint32_t seg = find_segment(plan->sb_first, plan->nseg, b);
+  const uint32_t d = b - plan->sb_first[seg];
+  const uint32_t D = plan->D[seg], T = plan->T[seg];
+  SubBin s;
+  s.gA = plan->g0[seg] + (d << plan->log2S);
+  s.gB = (d + 1 == D) ? plan->g0[seg + 1] : s.gA + (1u << plan->log2S);
+  s.kA = T != 0 ? scan2[plan->cbase[seg] + d * T] : plan->key0[seg];
+  s.kB = (d + 1 < D) ? (T != 0 ? scan2[plan->cbase[seg] + (d + 1) * T] : plan->key0[seg]) : plan->key0[seg + 1];
+  return s;
+}
+
+// ------------------------------------------------------------- LDS build
+// A sub-bin of R <= kSMax buckets and m <= 65535 keys is sorted in LDS with
+// 16-bit counters, two per word (bucket i in half i & 1 of word i >> 1).  The
+// same LDS then stages the sorted keys so that they leave in whole lines.
+constexpr uint32_t kSMax = 1u << 15;
+constexpr uint32_t kBuildWords = 18432;  // 72 KiB: the counters, then the staging area
+
+// Exclusive scan in place of the R 16-bit counters packed in c[0 .. (R+1)/2).
+// Each wave scans one contiguous chunk of words in rounds of 64, then adds the
+// totals of the chunks before it.  Every prefix fits 16 bits (m <= 65535).
+template <int THREADS>
+__device__ __forceinline__ void lds_exclusive_scan16(uint32_t* c, uint32_t R, uint32_t* wsum) {
+  constexpr int W = THREADS / kWave;
+  const uint32_t words = (R + 1) >> 1;
+  const uint32_t ch = ((words + W - 1) / W + kWave - 1) / kWave * kWave;
+  const uint32_t w = threadIdx.x / kWave, l = lane_id();
+  uint32_t carry = 0;
+  for (uint32_t r0 = 0; r0 < ch; r0 += kWave) {
+    const uint32_t idx = w * ch + r0 + l;
+    const uint32_t x = idx < words ? c[idx] : 0u;
+    const uint32_t lo = x & 0xFFFFu, sum = lo + (x >> 16);
+    const uint32_t inc = wave_inclusive_sum(sum);
+    const uint32_t ex = carry + inc - sum;
+    if (idx < words) c[idx] = ex | ((ex + lo) << 16);
+    carry += readlane(inc, kWave - 1);
+  }
+  if (l == 0) wsum[w] = carry;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int x = 0; x < W; ++x) base += (x < static_cast<int>(w)) ? wsum[x] : 0u;
+  const uint32_t add = base | (base << 16);
+  for (uint32_t r0 = 0; r0 < ch; r0 += kWave) {
+    const uint32_t idx = w * ch + r0 + l;
+    if (idx < words) c[idx] += add;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t ld_l2(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_l2(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Appends bucket g to the long-bucket list.
+__device__ __forceinline__ void note_long(uint32_t* long_count, uint32_t* long_list, uint32_t g) {
+  long_list[atomicAdd(long_count, 1u)] = g;
+}
+
+template <typename K, int THREADS, int REG, int MINB>
+__global__ __launch_bounds__(THREADS, MINB) void k_lds_build(const K* __restrict__ in,
+                                                             const SegPlan* __restrict__ plan,
+                                                             const uint32_t* __restrict__ scan2, uint32_t log2P,
+                                                             uint32_t P, const PartDesc* __restrict__ desc,
+                                                             uint32_t* __restrict__ offsets, K* __restrict__ out,
+                                                             uint32_t* __restrict__ long_count,
+                                                             uint32_t* __restrict__ long_list) {
+  constexpr uint32_t kStageKeys = kBuildWords * 4 / sizeof(K);
+  __shared__ uint32_t lds[kBuildWords];
+  __shared__ PartDesc sd[kMaxP];
+  __shared__ uint32_t wsum[THREADS / kWave];
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x >= plan->total_subbins) return;  // whole workgroup
+  const SubBin sb = sub_bin(plan, scan2, blockIdx.x);
+  const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
+  for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+
+  if (R <= kSMax && m <= 0xFFFFu) {
+    for (uint32_t i = t; i < (R + 1) / 2; i += THREADS) lds[i] = 0;
+    __syncthreads();
+    const bool regs = m <= static_cast<uint32_t>(THREADS * REG);
+    K v[REG];
+    uint32_t pos[(REG + 1) / 2];
+    if (regs) {
+#pragma unroll
+      for (int j = 0; j < REG; ++j) {
+        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+        if (e < m) {
+          v[j] = in[sb.kA + e];
+          const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
+          atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
+        }
+      }
+    } else {
+      for (uint32_t e = t; e < m; e += THREADS) {
+        const uint32_t lb = bucket_of(in[sb.kA + e], log2P, sd) - sb.gA;
+        atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
+      }
+    }
+    __syncthreads();
+    lds_exclusive_scan16<THREADS>(lds, R, wsum);
+    for (uint32_t i = t; i < R; i += THREADS) {
+      const uint32_t e0 = get_half(lds, i);
+      offsets[sb.gA + i] = sb.kA + e0;
+      const uint32_t e1 = i + 1 < R ? get_half(lds, i + 1) : m;
+      if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+    }
+    __syncthreads();
+    if (!regs) {
+      // Oversized sub-bin: positions go straight to global memory.
+      for (uint32_t e = t; e < m; e += THREADS) {
+        const K key = in[sb.kA + e];
+        const uint32_t lb = bucket_of(key, log2P, sd) - sb.gA, sh = (lb & 1u) << 4;
+        const uint32_t p = (atomicAdd(&lds[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        out[sb.kA + p] = key;
+      }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+      uint32_t p = 0;
+      if (e < m) {
+        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA, sh = (lb & 1u) << 4;
+        p = (atomicAdd(&lds[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
+      }
+      if (j & 1) pos[j >> 1] |= p << 16; else pos[j >> 1] = p;
+    }
+    __syncthreads();  // every position is known: the counters are dead
+    K* stage = reinterpret_cast<K*>(lds);
+    for (uint32_t h0 = 0; h0 < m; h0 += kStageKeys) {
+#pragma unroll
+      for (int j = 0; j < REG; ++j) {
+        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+        const uint32_t p = (pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu;
+        if (e < m && p >= h0 && p < h0 + kStageKeys) stage[p - h0] = v[j];
+      }
+      __syncthreads();
+      const uint32_t len = min(kStageKeys, m - h0);
+      for (uint32_t i = t; i < len; i += THREADS) out[sb.kA + h0 + i] = stage[i];
+      __syncthreads();
+    }
+    return;
+  }
+
+  // A sub-bin wider than LDS (a level-1 segment with more buckets than its
+  // sub-bins can hold folds its tail into the last one) or with more than
+  // 65535 keys: the same three steps with the counters in global memory,
+  // offsets[gA + i] serving as the counter of bucket i.
+  __syncthreads();
+  for (uint32_t i = t; i < R; i += THREADS) st_l2(&offsets[sb.gA + i], 0u);
+  __threadfence();
+  __syncthreads();
+  for (uint32_t e = t; e < m; e += THREADS) atomicAdd(&offsets[bucket_of(in[sb.kA + e], log2P, sd)], 1u);
+  __threadfence();
+  __syncthreads();
+  uint32_t carry = sb.kA;
+  for (uint32_t c0 = 0; c0 < R; c0 += THREADS) {
+    const uint32_t i = c0 + t;
+    const uint32_t x = i < R ? ld_l2(&offsets[sb.gA + i]) : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_sum<THREADS>(x, wsum, total);
+    if (i < R) st_l2(&offsets[sb.gA + i], carry + ex);
+    carry += total;
+  }
+  __threadfence();
+  __syncthreads();
+  for (uint32_t e = t; e < m; e += THREADS) {
+    const K key = in[sb.kA + e];
+    const uint32_t p = atomicAdd(&offsets[bucket_of(key, log2P, sd)], 1u);
+    out[p] = key;
+  }
+  __threadfence();
+  __syncthreads();
+  // Each counter now holds the start of the next bucket: shift by one.
+  for (uint32_t c1 = R; c1 > 0;) {
+    const uint32_t c0 = c1 > THREADS ? c1 - THREADS : 0u;
+    const uint32_t i = c0 + t;
+    uint32_t val = 0;
+    if (i < c1) val = i == 0 ? sb.kA : ld_l2(&offsets[sb.gA + i - 1]);
+    __syncthreads();
+    if (i < c1) st_l2(&offsets[sb.gA + i], val);
+    __threadfence();
+    __syncthreads();
+    c1 = c0;
+  }
+  for (uint32_t i = t; i < R; i += THREADS) {
+    const uint32_t e0 = ld_l2(&offsets[sb.gA + i]);
+    const uint32_t e1 = i + 1 < R ? ld_l2(&offsets[sb.gA + i + 1]) : sb.kB;
+    if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+  }
+}
+
+// ------------------------------------------------------------- LDS probe
+constexpr uint32_t kProbeKeyBytes = 40 * 1024;
+
+template <typename K, int THREADS, int REG, int MINB>
+__global__ __launch_bounds__(THREADS, MINB) void k_lds_probe(const K* __restrict__ q2,
+                                                             const SegPlan* __restrict__ qplan,
+                                                             const uint32_t* __restrict__ qscan2, uint32_t log2P,
+                                                             uint32_t P, const PartDesc* __restrict__ desc,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             const K* __restrict__ tkeys,
+                                                             const uint32_t* __restrict__ unsorted, uint32_t log2W,
+                                                             uint32_t* __restrict__ c2) {
+  constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);
+  __shared__ uint32_t soff[(1u << kMaxLog2W) + 1];
+  __shared__ K skeys[KCAP];
+  __shared__ PartDesc sd[kMaxP];
+  const uint32_t t = threadIdx.x;
+  if (blockIdx.x >= qplan->total_subbins) return;  // whole workgroup
+  const SubBin sb = sub_bin(qplan, qscan2, blockIdx.x);
+  const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
+  const uint32_t Wb = 1u << log2W;
+  const uint32_t nuns = unsorted[0];
+  for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+  __syncthreads();
+
+  for (uint32_t c0 = 0; c0 < m; c0 += THREADS * REG) {  // one pass unless the sub-bin is oversized
+    K qv[REG];
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      if (e < m) qv[j] = q2[sb.kA + e];
+    }
+    // Each query's bucket lies in exactly one window: its count is written
+    // when that window is in LDS.
+    for (uint32_t w0 = 0; w0 < R; w0 += Wb) {
+      const uint32_t wl = min(Wb, R - w0);
+      for (uint32_t i = t; i <= wl; i += THREADS) soff[i] = offsets[sb.gA + w0 + i];
+      __syncthreads();
+      const uint32_t ka = soff[0], nk = soff[wl] - ka;
+      const bool in_lds = nk <= KCAP;
+      if (in_lds)
+        for (uint32_t i = t; i < nk; i += THREADS) skeys[i] = tkeys[ka + i];
+      __syncthreads();
+      // Output addresses are rebuilt in every window from one register (the
+      // empty asm keeps REG 64-bit addresses from being hoisted and spilled).
+      uint32_t ebase = c0 + t;
+      asm volatile("" : "+v"(ebase));
+#pragma unroll
+      for (int j = 0; j < REG; ++j) {
+        const uint32_t e = ebase + static_cast<uint32_t>(j) * THREADS;
+        if (e < m) {
+          // Recompute the bucket in every window rather than keep REG of
+          // them live: the empty asm stops the compiler from hoisting it.
+          asm volatile("" : "+v"(qv[j]));
+          const uint32_t lb = bucket_of(qv[j], log2P, sd) - sb.gA;
+          if (lb >= w0 && lb < w0 + wl) {
+            const uint32_t lo = soff[lb - w0], hi = soff[lb - w0 + 1];
+            const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
+            c2[sb.kA + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[j], srt)
+                                   : count_equal(tkeys, lo, hi, qv[j], srt);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------------- long buckets
+// Buckets with more than kLongT keys are sorted in place, so that a probe
+// counts them with two binary searches (the order inside a bucket is free).
+// One workgroup per long bucket, taken from a work counter:
+//   1. the distinct keys of the bucket and their multiplicities, found by
+//      leader election in each wave (one round per distinct key in the
+//      wave's 64 keys) and merged into a set of at most kSetMax;
+//   2. the bucket rewritten as runs of those keys in ascending order;
+//   3. a bucket with more distinct keys is bitonic-sorted in LDS when it has
+//      at most kSortCap keys, and otherwise listed as unsorted.
+constexpr uint32_t kSetMax = 64;
+constexpr uint32_t kSortCap = 4096;
+
+template <typename K>
+__device__ __forceinline__ K readlane_key(K v, uint32_t lane);
+template <>
+__device__ __forceinline__ uint32_t readlane_key<uint32_t>(uint32_t v, uint32_t lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+template <>
+__device__ __forceinline__ uint64_t readlane_key<uint64_t>(uint64_t v, uint32_t lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), lane);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), lane);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Adds (v, c) to the set of wave-owned slots sv/sc (size *sz), the whole wave
+// searching in parallel.  Returns false when the set is full.
+template <typename K>
+__device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, uint32_t c) {
+  const uint32_t l = lane_id();
+  const uint32_t n = *sz;
+  const uint64_t hit = ballot(l < n && sv[l] == v);
+  if (hit != 0) {
+    if (l == static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(hit)) - 1)) sc[l] += c;
+  } else {
+    if (n >= kSetMax) return false;
+    if (l == 0) {
+      sv[n] = v;
+      sc[n] = c;
+      *sz = n + 1;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  return true;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ long_list,
+                                                            const uint32_t* __restrict__ long_count,
+                                                            uint32_t* __restrict__ work, K* __restrict__ keys,
+                                                            uint32_t* __restrict__ unsorted) {
+  constexpr int W = kLongThreads / kWave;
+  __shared__ K sval[W][kSetMax];
+  __shared__ uint32_t scnt[W][kSetMax];
+  __shared__ uint32_t ssize[W];
+  __shared__ uint32_t run0[kSetMax + 1];
+  __shared__ uint32_t soverflow;
+  __shared__ uint32_t sidx;
+  __shared__ K sbuf[kSortCap];
+  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
+  const uint32_t total = *long_count;
+  for (;;) {
+    if (t == 0) sidx = atomicAdd(work, 1u);
+    if (l == 0) ssize[w] = 0;
+    if (t == 0) soverflow = 0;
+    __syncthreads();
+    const uint32_t idx = sidx;
+    if (idx >= total) break;  // uniform: every thread read the same sidx
+    const uint32_t g = long_list[idx];
+    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+
+    // 1. distinct keys with multiplicities
+    for (uint32_t c0 = w * kWave; c0 < L; c0 += kLongThreads) {
+      if (soverflow) break;
+      const uint32_t i = c0 + l;
+      const bool valid = i < L;
+      const K key = valid ? keys[lo + i] : K(0);
+      uint64_t active = ballot(valid);
+      while (active != 0) {
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(active)) - 1);
+        const K v = readlane_key(key, leader);
+        const uint64_t match = ballot(valid && key == v) & active;
+        active &= ~match;
+        if (!set_add(sval[w], scnt[w], &ssize[w], v, popc64(match))) {
+          if (l == 0) soverflow = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (w == 0 && !soverflow) {
+      for (int x = 1; x < W; ++x) {
+        const uint32_t nx = ssize[x];
+        for (uint32_t e = 0; e < nx; ++e) {
+          if (!set_add(sval[0], scnt[0], &ssize[0], sval[x][e], scnt[x][e])) {
+            if (l == 0) soverflow = 1;
+            break;
+          }
+        }
+        if (soverflow) break;
+      }
+    }
+    __syncthreads();
+
+    if (!soverflow) {
+      // 2. rank the distinct keys, then rewrite the bucket as ascending runs
+      const uint32_t nd = ssize[0];
+      K myv = 0;
+      uint32_t myc = 0, rank = 0;
+      if (t < nd) {
+        myv = sval[0][t];
+        myc = scnt[0][t];
+        for (uint32_t j = 0; j < nd; ++j) rank += sval[0][j] < myv ? 1u : 0u;
+      }
+      __syncthreads();
+      if (t < nd) {
+        sval[1][rank] = myv;
+        scnt[1][rank] = myc;
+      }
+      __syncthreads();
+      if (t == 0) {
+        uint32_t run = 0;
+        for (uint32_t r = 0; r < nd; ++r) {
+          run0[r] = run;
+          run += scnt[1][r];
+        }
+        run0[nd] = run;
+      }
+      __syncthreads();
+      for (uint32_t i = t; i < L; i += kLongThreads) {
+        uint32_t a = 0, b = nd;  // last run with run0[r] <= i
+        while (b - a > 1) {
+          const uint32_t mid = (a + b) >> 1;
+          if (run0[mid] <= i) a = mid; else b = mid;
+        }
+        keys[lo + i] = sval[1][a];
+      }
+    } else if (L <= kSortCap) {
+      // 3. many distinct keys, few enough to sort in LDS
+      uint32_t p2 = 1;
+      while (p2 < L) p2 <<= 1;
+      for (uint32_t i = t; i < p2; i += kLongThreads) sbuf[i] = i < L ? keys[lo + i] : ~K(0);
+      __syncthreads();
+      for (uint32_t k = 2; k <= p2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          for (uint32_t i = t; i < p2; i += kLongThreads) {
+            const uint32_t ixj = i ^ j;
+            if (ixj > i) {
+              const K a = sbuf[i], b = sbuf[ixj];
+              const bool up = (i & k) == 0;
+              if ((a > b) == up) {
+                sbuf[i] = b;
+                sbuf[ixj] = a;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t i = t; i < L; i += kLongThreads) keys[lo + i] = sbuf[i];
+    } else if (t == 0) {
+      const uint32_t u = atomicAdd(&unsorted[0], 1u);
+      if (u < kMaxUnsorted) unsorted[1 + u] = g;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_find_long(const uint32_t* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ nb, uint32_t* __restrict__ long_count,
+                                                   uint32_t* __restrict__ long_list) {
+  const uint32_t B = *nb;
+  for (uint32_t g = blockIdx.x * 256u + threadIdx.x; g < B; g += gridDim.x * 256u)
+    if (offsets[g + 1] - offsets[g] > kLongT) note_long(long_count, long_list, g);
+}
+
+template <typename K, int THREADS, int ITEMS, int MAXD, int OP>
+hipError_t msplit_dig(int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd, uint32_t log2P,
+                      uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out,
+                      const uint32_t* gsrc, void* gdst, hipStream_t s) {
+  if (dig == DIG_PART)
+    k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_PART><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
+                                                                            counts, out, gsrc, gdst);
+  else if (dig == DIG_COARSE)
+    k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_COARSE><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
+                                                                              counts, out, gsrc, gdst);
+  else
+    k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_SUB><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
+                                                                           counts, out, gsrc, gdst);
+  return hipGetLastError();
+}
+
+template <typename K, int THREADS, int ITEMS, int MAXD>
+hipError_t msplit_op(int op, int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd,
+                     uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out,
+                     const uint32_t* gsrc, void* gdst, hipStream_t s) {
+  switch (op) {
+    case OP_COUNT:
+      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_COUNT>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
+                                                          out, gsrc, gdst, s);
+    case OP_SCATTER:
+      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_SCATTER>(dig, grid, in, n, plan, nd, log2P, P, desc, shift,
+                                                            counts, out, gsrc, gdst, s);
+    case OP_GATHER:
+      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_GATHER>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
+                                                           out, gsrc, gdst, s);
+    default:
+      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_GATHER_FOUND>(dig, grid, in, n, plan, nd, log2P, P, desc, shift,
+                                                                 counts, out, gsrc, gdst, s);
+  }
+}
+
+template <typename K>
+hipError_t msplit_level(int level, int op, int dig, const K* in, uint32_t n, uint32_t max_tiles, const SegPlan* plan,
+                        uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift,
+                        uint32_t* counts, K* out, const uint32_t* gsrc, void* gdst, hipStream_t s) {
+  if (level == 1) {
+    const uint32_t tiles = div_up(n, kL1Tile);
+    if (tiles == 0) return hipSuccess;
+    return msplit_op<K, kL1Threads, 16, 256>(op, dig, dim3(tiles), in, n, nullptr, nd, log2P, P, desc, shift, counts,
+                                              out, gsrc, gdst, s);
+  }
+  if (max_tiles == 0) return hipSuccess;
+  constexpr int kItems2 = sizeof(K) == 4 ? 16 : 8;
+  return msplit_op<K, kL2Threads, kItems2, kMaxD2>(op, dig, dim3(max_tiles), in, n, plan, nd, log2P, P, desc, shift,
+                                                    counts, out, gsrc, gdst, s);
+}
+
+}  // namespace
+
+hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
+                         const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                         uint32_t shift, uint32_t* counts, void* out, const uint32_t* gsrc, void* gdst,
+                         hipStream_t s) {
+  if (kt == 0)
+    return msplit_level<uint32_t>(level, op, dig, static_cast<const uint32_t*>(in), n, max_tiles, plan, nd, log2P, P,
+                                  desc, shift, counts, static_cast<uint32_t*>(out), gsrc, gdst, s);
+  return msplit_level<uint64_t>(level, op, dig, static_cast<const uint64_t*>(in), n, max_tiles, plan, nd, log2P, P,
+                                desc, shift, counts, static_cast<uint64_t*>(out), gsrc, gdst, s);
+}
+
+hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
+                       const uint32_t* bucket_base, uint32_t P, uint32_t sh1, uint32_t log2S, uint32_t tile2,
+                       uint32_t* offsets, SegPlan* plan, hipStream_t s) {
+  k_plan<<<1, kMaxSeg, 0, s>>>(scan1, tiles1, nseg, n, mode, bucket_base, P, sh1, log2S, tile2, offsets, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
+                            uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
+                            uint32_t* long_count, uint32_t* long_list, hipStream_t s) {
+  if (max_subbins == 0) return hipSuccess;
+  if (kt == 0)
+    k_lds_build<uint32_t, kLdsThreads, 20, 2><<<max_subbins, kLdsThreads, 0, s>>>(
+        static_cast<const uint32_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint32_t*>(out),
+        long_count, long_list);
+  else
+    k_lds_build<uint64_t, kLdsThreads, 20, 1><<<max_subbins, kLdsThreads, 0, s>>>(
+        static_cast<const uint64_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint64_t*>(out),
+        long_count, long_list);
+  return hipGetLastError();
+}
+
+hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
+                            uint32_t max_subbins, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                            const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
+                            uint32_t* c2, hipStream_t s) {
+  if (max_subbins == 0) return hipSuccess;
+  if (kt == 0)
+    k_lds_probe<uint32_t, kLdsThreads, 20, 2><<<max_subbins, kLdsThreads, 0, s>>>(
+        static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint32_t*>(tkeys),
+        unsorted, log2W, c2);
+  else
+    k_lds_probe<uint64_t, kLdsThreads, 20, 1><<<max_subbins, kLdsThreads, 0, s>>>(
+        static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint64_t*>(tkeys),
+        unsorted, log2W, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,
+                            uint32_t* long_count, uint32_t* long_list, hipStream_t s) {
+  if (bound == 0) return hipSuccess;
+  const uint64_t blocks = (bound + 255) / 256;
+  k_find_long<<<static_cast<uint32_t>(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(offsets, num_buckets_dev,
+                                                                                   long_count, long_list);
+  return hipGetLastError();
+}
+
+hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
+                            uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s) {
+  if (kt == 0)
+    k_long_sort<uint32_t><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work,
+                                                             static_cast<uint32_t*>(keys), unsorted);
+  else
+    k_long_sort<uint64_t><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work,
+                                                             static_cast<uint64_t*>(keys), unsorted);
+  return hipGetLastError();
+}
+
+}  // namespace hg

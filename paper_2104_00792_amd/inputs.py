@@ -119,6 +119,80 @@ def zipf_u64(n: int, K: int, seed: int, s: float = 1.0) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# The same streams drawn with torch (CPU or device), bit for bit equal to the
+# numpy functions above.  64-bit words are carried as int64 bit patterns:
+# products wrap modulo 2^64 and right shifts are made logical by masking.
+# --------------------------------------------------------------------------
+
+def _s64(c: int) -> int:
+    c &= 0xFFFFFFFFFFFFFFFF
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _lsr(z, s: int):
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix_t(z):
+    z = z ^ _lsr(z, 30)
+    z = z * _s64(0xBF58476D1CE4E5B9)
+    z = z ^ _lsr(z, 27)
+    z = z * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def splitmix64_t(seed: int, start: int, count: int, device, step: int = 1, offset: int = 0):
+    """Outputs start + step*j + offset (j < count) of stream ``seed`` as an
+    int64 tensor holding the 64-bit patterns."""
+    import torch
+
+    idx = torch.arange(count, dtype=torch.int64, device=device) * step + (start + offset + 1)
+    return _mix_t(idx * _s64(int(GAMMA)) + _s64(seed))
+
+
+def _to_u32(z):
+    import torch
+
+    return (_lsr(z, 32)).to(torch.int32).view(torch.uint32)
+
+
+def uniform_u32_t(n: int, seed: int, device):
+    return _to_u32(splitmix64_t(seed, 0, n, device))
+
+
+def queries_hit50_t(keys, q: int, seed: int, device):
+    """Device twin of queries_hit50 (keys: a device tensor)."""
+    import torch
+
+    n = keys.numel()
+    wa = splitmix64_t(seed, 0, q, device, step=2, offset=0)
+    wb = splitmix64_t(seed, 0, q, device, step=2, offset=1)
+    if keys.dtype == torch.uint32:
+        miss = _to_u32(wb)
+    else:
+        miss = wb.view(torch.uint64)
+    if n == 0:
+        return miss
+    pos = _lsr((wa & 0xFFFFFFFF) * n, 32)
+    hit = wa < 0
+    if keys.dtype == torch.uint32:
+        picked = keys.view(torch.int32)[pos]
+        return torch.where(hit, picked, miss.view(torch.int32)).view(torch.uint32)
+    picked = keys.view(torch.int64)[pos]
+    return torch.where(hit, picked, miss.view(torch.int64)).view(torch.uint64)
+
+
+def zipf_u64_t(n: int, K: int, seed: int, device, s: float = 1.0):
+    import torch
+
+    cdf = torch.from_numpy(np.cumsum(1.0 / np.arange(1, K + 1, dtype=np.float64) ** s)).to(device)
+    w = splitmix64_t(seed, 0, n, device)
+    u = _lsr(w, 11).to(torch.float64) * (2.0 ** -53) * cdf[-1]
+    r = torch.clamp(torch.searchsorted(cdf, u, right=True) + 1, max=K)
+    return _mix_t(r).view(torch.uint64)
+
+
+# --------------------------------------------------------------------------
 # Named workloads.  Each returns (keys, queries, build options).
 # --------------------------------------------------------------------------
 
@@ -134,18 +208,27 @@ WORKLOADS = {
 }
 
 
-def make_workload(name: str, n: int | None = None, q: int | None = None):
+def make_workload(name: str, n: int | None = None, q: int | None = None, device=None):
     """Keys, queries and build options of a named workload, optionally at a
-    smaller n (same recipe, same seeds)."""
+    smaller n (same recipe, same seeds).  With ``device`` (a torch device)
+    the arrays are drawn there as torch tensors, equal to the numpy ones."""
     w = WORKLOADS[name]
     n = w["n"] if n is None else n
     q = n if q is None else q
     ks, qs = KEY_SEED + w["idx"], QUERY_SEED + w["idx"]
+    opts = dict(P=w["P"], num=w["num"], den=w["den"])
+    if device is not None:
+        if w["kind"] == "u32":
+            keys = uniform_u32_t(n, ks, device)
+            queries = queries_hit50_t(keys, q, qs, device)
+        else:
+            keys = zipf_u64_t(n, 1 << 20, ks, device)
+            queries = zipf_u64_t(q, 1 << 20, qs, device)
+        return keys, queries, opts
     if w["kind"] == "u32":
         keys = uniform_u32(n, ks)
         queries = queries_hit50(keys, q, qs)
     else:
         keys = zipf_u64(n, 1 << 20, ks)
         queries = zipf_u64(q, 1 << 20, qs)
-    opts = dict(P=w["P"], num=w["num"], den=w["den"])
     return keys, queries, opts

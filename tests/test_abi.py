@@ -16,7 +16,7 @@ HG_OK, HG_ERR_INVALID_ARG, HG_ERR_OUT_OF_MEMORY, HG_ERR_HIP, HG_ERR_UNSUPPORTED 
 
 class Opts(ctypes.Structure):
     _fields_ = [("P", ctypes.c_uint32), ("ratio_num", ctypes.c_uint32), ("ratio_den", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32), ("num_buckets", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("num_buckets", ctypes.c_uint64)]
 
 
 def declared_functions():
@@ -67,8 +67,8 @@ def test_status_strings(lib):
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 
 
-def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, reserved=0, out=True):
-    opts = Opts(P, num, den, reserved, V)
+def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, flags=0, out=True):
+    opts = Opts(P, num, den, flags, V)
     h = ctypes.c_void_p()
     return lib.hg_build(keys, n, kt, ctypes.byref(opts), None, ctypes.byref(h) if out else None)
 
@@ -84,7 +84,8 @@ def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, reserved=0, out=True):
     (dict(keys=FAKE, n=10, den=0), HG_ERR_INVALID_ARG),
     (dict(keys=FAKE, n=10, V=(1 << 32) - 1), HG_ERR_INVALID_ARG),  # V too large
     (dict(keys=FAKE, n=(1 << 32) - 1, num=2), HG_ERR_INVALID_ARG),  # too many buckets
-    (dict(keys=FAKE, n=10, reserved=1), HG_ERR_INVALID_ARG),
+    (dict(keys=FAKE, n=10, flags=4), HG_ERR_INVALID_ARG),    # unknown build flag
+    (dict(keys=FAKE, n=10, flags=3), HG_ERR_INVALID_ARG),    # both strategies
     (dict(keys=FAKE, n=10, out=False), HG_ERR_INVALID_ARG),  # null out
 ])
 def test_build_rejects(lib, case, expected):
@@ -100,6 +101,9 @@ def test_build_null_opts(lib):
 def test_probe_rejects(lib):
     assert lib.hg_count(None, FAKE, 10, FAKE, None) == HG_ERR_INVALID_ARG
     assert lib.hg_query(None, FAKE, 10, FAKE, None) == HG_ERR_INVALID_ARG
+    lib.hg_count_ex.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                ctypes.c_uint32, ctypes.c_void_p]
+    assert lib.hg_count_ex(None, FAKE, 10, FAKE, 0, None) == HG_ERR_INVALID_ARG
 
 
 def test_bin_partition_rejects(lib):

@@ -43,17 +43,21 @@ def to_dev(a: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def check_table(hg, keys, P=1, num=1, den=1, V=0, queries=None):
+BUILDS = {"atomic": 1, "sorted": 2}
+PROBES = {"direct": 1, "sorted": 2}
+
+
+def check_table(hg, keys, P=1, num=1, den=1, V=0, queries=None, build="sorted"):
+    """Build with one strategy, probe with both, compare everything."""
     import torch
 
-    t = hg.hg_build(to_dev(keys), P=P, ratio=(num, den), num_buckets=V)
+    t = hg.hg_build(to_dev(keys), P=P, ratio=(num, den), num_buckets=V, flags=BUILDS[build])
     ref = oracle.build_table(keys, P=P, num=num, den=den, V=V)
     po, bb, offs, tk = t.export()
     if queries is None:
         queries = inputs.queries_hit50(keys, max(keys.size, 97), 0xC0FFEE)
     qd = to_dev(queries)
-    counts = hg.hg_count(t, qd)
-    found = hg.hg_query(t, qd)
+    probes = {name: (hg.hg_count(t, qd, flags=f), hg.hg_query(t, qd, flags=f)) for name, f in PROBES.items()}
     torch.cuda.synchronize()
     assert np.array_equal(po.cpu().numpy(), ref["part_offsets"]), "part_offsets"
     assert np.array_equal(bb.cpu().numpy(), ref["bucket_base"]), "bucket_base"
@@ -62,52 +66,77 @@ def check_table(hg, keys, P=1, num=1, den=1, V=0, queries=None):
     got_keys = oracle.canonicalize(got_offs, tk.cpu().numpy())
     assert np.array_equal(got_keys, ref["keys"]), "bucket contents"
     want = oracle.count(keys, queries)
-    got_c = counts.cpu().numpy()
-    assert np.array_equal(got_c, want), f"counts: {np.count_nonzero(got_c != want)} of {want.size} differ"
-    assert np.array_equal(found.cpu().numpy(), (want > 0).astype(np.uint8)), "found"
+    for name, (counts, found) in probes.items():
+        got_c = counts.cpu().numpy()
+        assert np.array_equal(got_c, want), f"{name} counts: {np.count_nonzero(got_c != want)} of {want.size} differ"
+        assert np.array_equal(found.cpu().numpy(), (want > 0).astype(np.uint8)), f"{name} found"
     t.free()
 
 
 SIZES = [0, 1, 2, 63, 64, 65, 4095, 4096, 4097, 3 * 4096 + 17, 65536 + 3]
 
 
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("P", [1, 16])
-def test_uniform_u32_sizes(gpu, n, P):
-    check_table(gpu, make_keys("uniform", n, np.uint32, 11 + n), P=P)
+def test_uniform_u32_sizes(gpu, n, P, build):
+    check_table(gpu, make_keys("uniform", n, np.uint32, 11 + n), P=P, build=build)
 
 
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("kind", ["uniform", "equal", "seq", "swr", "zipf", "extremes"])
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
 @pytest.mark.parametrize("P", [1, 2, 16])
-def test_distributions(gpu, kind, dtype, P):
+def test_distributions(gpu, kind, dtype, P, build):
     n = 20000 + 7
-    check_table(gpu, make_keys(kind, n, dtype, 5), P=P)
+    check_table(gpu, make_keys(kind, n, dtype, 5), P=P, build=build)
 
 
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("ratio", [(1, 2), (3, 2), (1, 7), (5, 1)])
 @pytest.mark.parametrize("P", [1, 4, 256])
-def test_ratios(gpu, ratio, P):
+def test_ratios(gpu, ratio, P, build):
     n = 50000 + 1
-    check_table(gpu, make_keys("uniform", n, np.uint32, 3), P=P, num=ratio[0], den=ratio[1])
+    check_table(gpu, make_keys("uniform", n, np.uint32, 3), P=P, num=ratio[0], den=ratio[1], build=build)
 
 
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("V", [1, 2, 3, 1000, (1 << 20) + 1, 1 << 22])
-def test_explicit_bucket_count(gpu, V):
+def test_explicit_bucket_count(gpu, V, build):
     n = 30000
-    check_table(gpu, make_keys("uniform", n, np.uint32, 17), V=V)
-    check_table(gpu, make_keys("zipf", n, np.uint64, 17), V=V)
+    check_table(gpu, make_keys("uniform", n, np.uint32, 17), V=V, build=build)
+    check_table(gpu, make_keys("zipf", n, np.uint64, 17), V=V, build=build)
 
 
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("P", [1, 2, 16, 256])
-def test_plain_2p20(gpu, P):
+def test_plain_2p20(gpu, P, build):
     keys, queries, _ = inputs.make_workload("plain_u32_2^20")
-    check_table(gpu, keys, P=P, queries=queries)
+    check_table(gpu, keys, P=P, queries=queries, build=build)
 
 
-def test_zipf_u64_small(gpu):
+@pytest.mark.parametrize("build", sorted(BUILDS))
+def test_zipf_u64_small(gpu, build):
     keys, queries, opts = inputs.make_workload("zipf_u64_2^27", n=1 << 18)
-    check_table(gpu, keys, P=opts["P"], num=opts["num"], den=opts["den"], queries=queries)
+    check_table(gpu, keys, P=opts["P"], num=opts["num"], den=opts["den"], queries=queries, build=build)
+
+
+@pytest.mark.parametrize("build", sorted(BUILDS))
+@pytest.mark.parametrize("P, num, den", [(1, 1, 1), (16, 1, 1), (2, 1, 1), (1, 1, 2), (16, 3, 1)])
+def test_multi_subbin_tables(gpu, P, num, den, build):
+    """Tables of several 2^15-bucket sub-bins per level-1 segment, with ragged
+    last sub-bins, so the sorted path's two splits and LDS stages all work."""
+    n = (1 << 21) + 12345
+    check_table(gpu, make_keys("uniform", n, np.uint32, 77), P=P, num=num, den=den, build=build)
+
+
+def test_wide_segment_uses_global_counters(gpu):
+    """All keys equal with P = 16 and table ratio 48: the one non-empty
+    partition gets 48 * 2^20 buckets, more than 2^15 x 1024, so the sorted
+    build folds its tail into one wide sub-bin that counts in global memory.
+    Checked against the oracle like every other case."""
+    n = 1 << 20
+    check_table(gpu, make_keys("equal", n, np.uint32, 0), P=16, num=48, den=1, build="sorted")
 
 
 def test_repeat_is_deterministic(gpu):
@@ -117,7 +146,7 @@ def test_repeat_is_deterministic(gpu):
     kd = to_dev(keys)
     outs = []
     for _ in range(3):
-        t = gpu.hg_build(kd, P=16)
+        t = gpu.hg_build(kd, P=16, flags=2)
         po, bb, offs, tk = t.export()
         torch.cuda.synchronize()
         o = offs.cpu().numpy()
@@ -172,4 +201,49 @@ def test_empty_table_counts_zero(gpu):
     c = gpu.hg_count(t, to_dev(np.empty(0, np.uint32)))
     torch.cuda.synchronize()
     assert c.numel() == 0
+    t.free()
+
+
+@pytest.mark.parametrize("P", [1, 16])
+def test_subbin_with_more_than_u16_keys(gpu, P):
+    """One bucket holding 70000 copies of a key: its sub-bin has more keys than
+    16-bit LDS counters can hold, so the sorted build counts it in global
+    memory.  The probe still answers every query exactly."""
+    keys = np.concatenate([np.full(70000, 12345, np.uint32), make_keys("uniform", 30000, np.uint32, 3)])
+    check_table(gpu, keys, P=P, build="sorted")
+
+
+LONG_CASES = {
+    # few distinct keys per long bucket: rewritten as ascending runs
+    "zipf_runs": lambda: (inputs.zipf_u64(1 << 18, 1000, 41), 0),
+    "one_key_100k": lambda: (np.full(100000, 7, np.uint64), 0),
+    # many distinct keys, at most 4096 per bucket: bitonic sort in LDS
+    "bitonic_V8": lambda: (make_keys("uniform", 20000, np.uint64, 8), 8),
+    # many distinct keys in buckets longer than 4096: left unsorted, scanned
+    "unsorted_V3": lambda: (make_keys("uniform", 20000, np.uint64, 9), 3),
+    "mixed_70x100_V2": lambda: (np.repeat(np.arange(70, dtype=np.uint64) * 977, 100), 2),
+}
+
+
+@pytest.mark.parametrize("build", sorted(BUILDS))
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("case", sorted(LONG_CASES))
+def test_long_buckets(gpu, case, dtype, build):
+    """Buckets longer than 64 keys: exact counts through both probes, and in
+    the raw table every long bucket the build could sort (at most 64 distinct
+    keys, or at most 4096 keys) is ascending."""
+    import torch
+
+    keys, V = LONG_CASES[case]()
+    keys = keys.astype(dtype)
+    queries = np.concatenate([keys[:: max(1, keys.size // 5000)], make_keys("uniform", 3000, dtype, 5)])
+    check_table(gpu, keys, V=V, queries=queries, build=build)
+    t = gpu.hg_build(to_dev(keys), num_buckets=V, flags=BUILDS[build])
+    _, _, offs, tk = t.export()
+    torch.cuda.synchronize()
+    offs, tk = offs.cpu().numpy().astype(np.int64), tk.cpu().numpy()
+    for g in np.nonzero(np.diff(offs) > 64)[0]:
+        seg = tk[offs[g]:offs[g + 1]]
+        if np.unique(seg).size <= 64 or seg.size <= 4096:
+            assert np.all(seg[1:] >= seg[:-1]), f"long bucket {g} of {seg.size} keys is not sorted"
     t.free()

@@ -60,3 +60,13 @@ def test_named_workloads_shapes():
         assert keys.size == 1000 and queries.size == 1000
         assert keys.dtype == queries.dtype
         assert set(opts) == {"P", "num", "den"}
+
+
+def test_torch_twin_equals_numpy():
+    import torch
+
+    for name in inputs.WORKLOADS:
+        k, q, _ = inputs.make_workload(name, n=30011, q=20011)
+        kt, qt, _ = inputs.make_workload(name, n=30011, q=20011, device=torch.device("cpu"))
+        assert np.array_equal(kt.numpy(), k), name
+        assert np.array_equal(qt.numpy(), q), name
