@@ -1,0 +1,339 @@
+"""Serving loop: continuous batching of build and probe requests.
+
+Requests arrive over time (a Poisson stream).  A request is admitted as soon
+as an execution slot is free and its device memory fits under the HBM cap,
+evicting least-recently-used tables that no in-flight request holds.  Admitted
+requests run concurrently, each on the stream of its slot, so the work of
+requests that arrived at different times overlaps on the device.  Built
+tables stay resident for later probes.  A probe whose table was evicted
+rebuilds it from the table's seed first, on the probe's own stream, so every
+result is the same whatever the mix.
+
+The executor does the work: ``GpuExecutor`` calls the HIP library on torch
+streams; tests plug in a CPU executor with a virtual clock.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import heapq
+import math
+import time
+from collections import OrderedDict
+
+import numpy as np
+
+from . import inputs
+
+KEY_BYTES = 4
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str          # "build" or "probe"
+    table: int         # table id (a build creates it, a probe reads it)
+    size: int          # keys to build, or queries to probe
+    seed: int          # build: key stream; probe: query stream
+    arrival: float     # seconds from the start of the stream
+    start: float = math.nan
+    finish: float = math.nan
+    result: object = None
+
+
+def table_bytes(n: int) -> int:
+    """Resident bytes of a table of n 32-bit keys at table ratio 1."""
+    return KEY_BYTES * n + 4 * (n + 2) + 4096
+
+
+def build_work_bytes(n: int) -> int:
+    """Transient device memory of a build of n keys: the generated keys, two
+    split buffers and the split counts."""
+    return 3 * KEY_BYTES * n + n // 2 + (1 << 20)
+
+
+def probe_work_bytes(q: int, table_n: int) -> int:
+    """Transient device memory of a probe: queries, the table's keys to draw
+    hits from, two split buffers, three count arrays."""
+    return 3 * KEY_BYTES * q + KEY_BYTES * table_n + 12 * q + (1 << 20)
+
+
+def make_trace(num: int, seed: int = 0x5EED0500, build_frac: float = 0.3, build_log2=(10, 24),
+               probe_log2=(8, 22), rate: float = 1000.0):
+    """A Poisson stream of `num` requests at `rate` per second.  Builds create
+    new tables (uint32 keys, sizes log-uniform over 2^build_log2); probes
+    (sizes log-uniform over 2^probe_log2, 50% hits) target a table chosen
+    uniformly among those created earlier.  Returns (requests, table sizes,
+    table seeds)."""
+    w = inputs.splitmix64(seed, 0, 4 * num)
+    u = (w >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    t = 0.0
+    reqs, sizes, seeds = [], [], []
+    for i in range(num):
+        u0, u1, u2, u3 = (float(x) for x in u[4 * i:4 * i + 4])
+        t += -math.log(1.0 - u0) / rate
+        if u1 < build_frac or not sizes:
+            lo, hi = build_log2
+            size = int(round(2.0 ** (lo + (hi - lo) * u2)))
+            sizes.append(size)
+            seeds.append(seed + 1 + i)
+            reqs.append(Request(i, "build", len(sizes) - 1, size, seed + 1 + i, t))
+        else:
+            lo, hi = probe_log2
+            size = int(round(2.0 ** (lo + (hi - lo) * u2)))
+            tid = min(int(u3 * len(sizes)), len(sizes) - 1)
+            reqs.append(Request(i, "probe", tid, size, seed + 1 + i, t))
+    return reqs, sizes, seeds
+
+
+class TableCache:
+    """Resident tables under a byte budget, least recently used evicted first;
+    a table pinned by an in-flight request is never evicted."""
+
+    def __init__(self, capacity: int, free_fn):
+        self.capacity = capacity
+        self.used = 0       # bytes of resident tables
+        self.reserved = 0   # bytes held by in-flight requests
+        self.entries: OrderedDict[int, list] = OrderedDict()  # tid -> [table, bytes, pins]
+        self.free_fn = free_fn
+        self.evictions = 0
+        self.peak = 0
+
+    def resident(self, tid: int) -> bool:
+        return tid in self.entries
+
+    def pin(self, tid: int):
+        self.entries[tid][2] += 1
+        self.entries.move_to_end(tid)
+
+    def unpin(self, tid: int):
+        self.entries[tid][2] -= 1
+
+    def fits(self, need: int) -> bool:
+        return self.used + self.reserved + need <= self.capacity
+
+    def make_room(self, need: int) -> bool:
+        """Evict unpinned tables, least recently used first, until `need`
+        more bytes fit."""
+        for tid in list(self.entries):
+            if self.fits(need):
+                break
+            table, nbytes, pins = self.entries[tid]
+            if pins == 0:
+                del self.entries[tid]
+                self.used -= nbytes
+                self.free_fn(table)
+                self.evictions += 1
+        return self.fits(need)
+
+    def add(self, tid: int, table, nbytes: int, pins: int = 0):
+        self.entries[tid] = [table, nbytes, pins]
+        self.used += nbytes
+        self.peak = max(self.peak, self.used + self.reserved)
+
+
+class Server:
+    """Continuous batching over `slots` concurrent requests."""
+
+    def __init__(self, executor, table_sizes, table_seeds, capacity_bytes: int, slots: int = 4):
+        self.ex = executor
+        self.sizes = table_sizes
+        self.seeds = table_seeds
+        self.cache = TableCache(capacity_bytes, executor.free)
+        self.slots = slots
+        self.inflight = []  # [token, request, reserved bytes, output]
+        self.rebuilds = 0
+
+    def _admit(self, req: Request, now: float) -> bool:
+        tid = req.table
+        if req.kind == "build":
+            need = table_bytes(req.size) + build_work_bytes(req.size)
+            if not self.cache.make_room(need):
+                return False
+            rebuild = False
+        else:
+            n = self.sizes[tid]
+            rebuild = not self.cache.resident(tid)
+            need = probe_work_bytes(req.size, n)
+            if rebuild:
+                need += table_bytes(n) + build_work_bytes(n)
+            else:
+                self.cache.pin(tid)  # never evict the probe's own table
+            if not self.cache.make_room(need):
+                if not rebuild:
+                    self.cache.unpin(tid)
+                return False
+        stream = self.ex.pick_stream()
+        if req.kind == "build":
+            out = self.ex.build(req.size, req.seed, stream)
+        else:
+            if rebuild:
+                # The rebuilt table is resident from now on: its bytes move
+                # from this request's reservation to the cache.
+                self.rebuilds += 1
+                table = self.ex.build(self.sizes[tid], self.seeds[tid], stream)
+                tb = table_bytes(self.sizes[tid])
+                self.cache.add(tid, table, tb, pins=1)
+                need -= tb
+            out = self.ex.probe(self.cache.entries[tid][0], self.sizes[tid], self.seeds[tid], req.size, req.seed,
+                                stream)
+        self.cache.reserved += need
+        self.cache.peak = max(self.cache.peak, self.cache.used + self.cache.reserved)
+        req.start = now
+        self.inflight.append([self.ex.record(stream), req, need, out])
+        return True
+
+    def _retire(self, now: float):
+        still = []
+        for token, req, need, out in self.inflight:
+            if not self.ex.done(token, now):
+                still.append([token, req, need, out])
+                continue
+            req.finish = self.ex.finish_time(token, now)
+            self.cache.reserved -= need
+            if req.kind == "build":
+                if self.cache.resident(req.table):  # rebuilt for a probe meanwhile
+                    self.ex.free(out)
+                else:
+                    self.cache.add(req.table, out, table_bytes(req.size))
+            else:
+                req.result = self.ex.fetch(out)
+                self.cache.unpin(req.table)
+        self.inflight = still
+
+    def _build_pending(self, tid: int) -> bool:
+        return any(r.kind == "build" and r.table == tid for _, r, _, _ in self.inflight)
+
+    def run(self, reqs, clock):
+        """Serve `reqs` (sorted by arrival) against `clock`."""
+        queue = []
+        i = 0
+        while i < len(reqs) or queue or self.inflight:
+            now = clock.now()
+            while i < len(reqs) and reqs[i].arrival <= now:
+                heapq.heappush(queue, (reqs[i].arrival, reqs[i].rid, reqs[i]))
+                i += 1
+            self._retire(now)
+            # Admit in arrival order while a slot and memory allow; a probe
+            # waits for the build of its table to complete.
+            while queue and len(self.inflight) < self.slots:
+                req = queue[0][2]
+                if req.kind == "probe" and self._build_pending(req.table):
+                    break
+                if not self._admit(req, now):
+                    if not self.inflight:
+                        raise MemoryError(f"request {req.rid} needs more than the HBM cap")
+                    break
+                heapq.heappop(queue)
+            clock.wait(self, reqs[i].arrival if i < len(reqs) else None)
+        return reqs
+
+
+def latency_report(reqs, wall: float) -> dict:
+    lat = np.array([r.finish - r.arrival for r in reqs])
+    keys = sum(r.size for r in reqs)
+    return {
+        "requests": len(reqs),
+        "wall_s": round(wall, 4),
+        "requests_per_s": len(reqs) / wall if wall > 0 else None,
+        "keys_per_s": keys / wall if wall > 0 else None,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+    }
+
+
+# --------------------------------------------------------------------------
+# GPU execution: the HIP library, each slot on its own torch stream (all at
+# the default priority).
+# --------------------------------------------------------------------------
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def wait(self, server, next_arrival):
+        if not server.inflight and next_arrival is not None:
+            dt = next_arrival - self.now()
+            if dt > 0:
+                time.sleep(min(dt, 0.005))
+
+
+class GpuExecutor:
+    def __init__(self, slots: int, device=None):
+        import torch
+
+        import paper_2104_00792_amd as hg
+
+        self.torch = torch
+        self.hg = hg
+        self.dev = device or torch.device("cuda:0")
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
+        self.next = 0
+
+    def pick_stream(self):
+        s = self.streams[self.next % len(self.streams)]
+        self.next += 1
+        return s
+
+    def build(self, n: int, seed: int, stream):
+        with self.torch.cuda.stream(stream):
+            keys = inputs.uniform_u32_t(n, seed, self.dev)
+            table = self.hg.hg_build(keys, stream=stream)
+            keys.record_stream(stream)
+        return table
+
+    def probe(self, table, table_n: int, table_seed: int, q: int, q_seed: int, stream):
+        with self.torch.cuda.stream(stream):
+            keys = inputs.uniform_u32_t(table_n, table_seed, self.dev)
+            queries = inputs.queries_hit50_t(keys, q, q_seed, self.dev)
+            counts = self.hg.hg_count(table, queries, stream=stream)
+            keys.record_stream(stream)
+            queries.record_stream(stream)
+        return counts
+
+    def record(self, stream):
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
+    def done(self, token, now) -> bool:
+        return token.query()
+
+    def finish_time(self, token, now: float) -> float:
+        return now
+
+    def fetch(self, out):
+        return out
+
+    def free(self, table):
+        table.free()
+
+
+def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10**9, rate: float | None = None,
+                build_log2=(10, 24), probe_log2=(8, 22), load: float = 0.8):
+    """Closed-loop capacity first (every request present at t = 0), then an
+    open-loop Poisson stream at `load` times that capacity.  Returns both
+    reports and the open-loop requests."""
+    import torch
+
+    reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=1.0)
+    for r in reqs:
+        r.arrival = 0.0
+    clock = WallClock()
+    Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots).run(reqs, clock)
+    torch.cuda.synchronize()
+    closed = latency_report(reqs, clock.now())
+    lam = rate if rate is not None else load * closed["requests_per_s"]
+    reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=lam)
+    clock = WallClock()
+    srv = Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots)
+    srv.run(reqs, clock)
+    torch.cuda.synchronize()
+    opened = latency_report(reqs, clock.now())
+    opened.update(offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,
+                  peak_reserved_bytes=srv.cache.peak)
+    return closed, opened, reqs
