@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "build+probe keys/s and % HBM peak at 2^28 u32; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2104_00792_amd", "csrc", "hg_kernels.hip")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2104_00792_amd", "csrc")
 
 DESCRIPTIONS = {
     "p16_u32_2^28": "n=2^28 uint32 keys uniform; P=16 hash-range partitions (top 4 bits of fmix32); "
@@ -42,8 +42,15 @@ def log(msg: str):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every kernel and launcher source: counter figures taken on
+    other sources are not reported."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(KERNEL_SOURCES, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> float:
@@ -61,9 +68,12 @@ def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> f
         "lds_build": 2 * ks * n + 4 * B,            # keys in, keys out, offsets out
         # probe, sorted path
         "qsplit1_count": ks * q,                    # read queries
+        "qsplit1_scatter": (2 * ks + 4) * q,        # queries in and out, permutation out
+        "qsplit2_count": ks * q,
+        "qsplit2_scatter": (2 * ks + 4) * q,
         "lds_probe": ks * q + 4 * B + ks * n + 4 * q,  # queries, offsets, table keys, counts out
-        "qgather2": ks * q + 8 * q,                 # queries, counts in, counts out
-        "qgather1": ks * q + 8 * q,
+        "qgather2": 12 * q,                         # permutation, counts in, counts out
+        "qgather1": 12 * q,
         # atomic path and direct probe
         "zero_counts": 4 * (B + 1),                 # counters written
         "bucket_hist": ks * n + 4 * B,              # keys in, counters out once

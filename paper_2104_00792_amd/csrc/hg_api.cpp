@@ -240,10 +240,23 @@ struct SplitParams {
   uint32_t log2S;  // regular sub-bins hold 2^log2S buckets
 };
 
+// Level-2 digits per segment: at most 2^L2 (L2 in 7..10, HG_SPLIT_L2_BITS,
+// default 7).  Fewer level-2 digits make the level-2 ranking cheaper and its
+// runs longer at the price of more level-1 digits.
+uint32_t split_l2_bits() {
+  static const uint32_t bits = [] {
+    const char* v = std::getenv("HG_SPLIT_L2_BITS");
+    const long b = v ? std::strtol(v, nullptr, 10) : 7;
+    return static_cast<uint32_t>(b < 7 ? 7 : (b > 10 ? 10 : b));
+  }();
+  return bits;
+}
+
 // Sub-bins of about 2^14 keys (log2S shrinks as keys per bucket grow).
-// Level-1 digits by partition when an average partition's table fits kMaxD2
-// sub-bins, the last of which may grow to 2^kLog2SLds buckets in LDS;
-// otherwise by coarse bucket ranges of at most kMaxD2 sub-bins each.
+// Level-1 digits by partition when an average partition's table fits 2^L2
+// sub-bins (the last of which may grow to 2^kLog2SLds buckets in LDS);
+// otherwise by coarse bucket ranges of 2^L2 sub-bins each (at most 256
+// ranges; ranges grow when the table needs more).
 SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound) {
   SplitParams sp;
   const uint64_t buckets = bound > P ? bound - P : 1;
@@ -253,7 +266,8 @@ SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound) {
   if (l < hg::kLog2SMin) l = hg::kLog2SMin;
   sp.log2S = l;
   const uint64_t S = 1ull << l;
-  const uint64_t fits = (hg::kMaxD2 - 1) * S + (1ull << hg::kLog2SLds) / 2;
+  const uint32_t l2 = split_l2_bits();
+  const uint64_t fits = ((1ull << l2) - 1) * S + (1ull << hg::kLog2SLds) / 2;
   if (P > 1 && (buckets + P - 1) / P <= fits) {
     sp.mode = 0;
     sp.sh1 = 0;
@@ -261,11 +275,9 @@ SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound) {
     return sp;
   }
   const uint32_t lb = ceil_log2(bound < 2 ? 2 : bound);
-  uint32_t sh = lb > 5 ? lb - 5 : 0;
-  const uint32_t lo = std::max<uint32_t>(l, lb > 8 ? lb - 8 : 0);
-  const uint32_t hi = l + 10;  // kMaxD2 sub-bins per range
-  if (sh < lo) sh = lo;
-  if (sh > hi) sh = hi;
+  uint32_t sh = l + l2;                // 2^l2 sub-bins per range
+  if (lb > 8 && sh < lb - 8) sh = lb - 8;  // at most 256 ranges
+  if (sh > l + 10) sh = l + 10;            // at most kMaxD2 sub-bins per range
   sp.mode = 1;
   sp.sh1 = sh;
   sp.nd1 = static_cast<uint32_t>((bound + (1ull << sh) - 1) >> sh);
@@ -281,10 +293,10 @@ uint32_t probe_log2W(hg_key_type kt, uint64_t n, uint64_t buckets) {
   return l;
 }
 
-// Level-1 split of n keys (or queries) against layout (log2P, desc, bb):
-// per-tile counts, scan, plan of level 2; then the level-1 scatter into buf1.
-// `layout_from_counts` (builds with mode 0) also runs the layout kernel on the
-// partition counts before the plan.
+// The two splits of n keys (or queries) against layout (log2P, desc): the
+// level-1 scatter into buf1 (level-1 counts already scanned and the plan
+// written), then level-2 counts, scan and scatter into buf2.  perm1 / perm2
+// (probes) receive each key's output position in the level it moves in.
 struct SplitBufs {
   uint32_t* counts1;
   uint32_t* bsums;
@@ -298,35 +310,30 @@ struct SplitBufs {
 };
 
 hg_status split_two_levels(const void* src, uint32_t n, hg_key_type kt, const SplitParams& sp, uint32_t log2P,
-                           uint32_t P, const hg::PartDesc* desc, const uint32_t* bb, uint32_t* offsets_or_null,
-                           const SplitBufs& w, hipStream_t s) {
+                           uint32_t P, const hg::PartDesc* desc, const SplitBufs& w, uint32_t* perm1,
+                           uint32_t* perm2, const char* const names[4], hipStream_t s) {
   const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
-  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
-  HG_LAUNCH("split1_scatter", s,
+  HG_LAUNCH(names[0], s,
             hg::launch_msplit(kt, 1, hg::OP_SCATTER, dig1, src, n, 0, nullptr, sp.nd1, log2P, P, desc, sp.sh1,
-                              w.counts1, w.buf1, nullptr, nullptr, s));
-  HG_LAUNCH("split2_count", s,
+                              w.counts1, w.buf1, perm1, s));
+  HG_LAUNCH(names[1], s,
             hg::launch_msplit(kt, 2, hg::OP_COUNT, hg::DIG_SUB, w.buf1, n, w.max_tiles2, w.plan, 0, log2P, P, desc,
-                              sp.log2S, w.counts2, nullptr, nullptr, nullptr, s));
-  HG_LAUNCH("split2_scan", s, hg::launch_scan_exclusive(w.counts2, &w.plan->total_counts, w.max_counts2, w.bsums, s));
-  HG_LAUNCH("split2_scatter", s,
+                              sp.log2S, w.counts2, nullptr, nullptr, s));
+  HG_LAUNCH(names[2], s, hg::launch_scan_exclusive(w.counts2, &w.plan->total_counts, w.max_counts2, w.bsums, s));
+  HG_LAUNCH(names[3], s,
             hg::launch_msplit(kt, 2, hg::OP_SCATTER, hg::DIG_SUB, w.buf1, n, w.max_tiles2, w.plan, 0, log2P, P, desc,
-                              sp.log2S, w.counts2, w.buf2, nullptr, nullptr, s));
-  (void)offsets_or_null;
-  (void)tile2;
-  (void)bb;
+                              sp.log2S, w.counts2, w.buf2, perm2, s));
   return HG_OK;
 }
 
-hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams& sp, uint32_t P, uint64_t bound,
-                      SplitBufs& w, uint64_t extra_scan) {
+hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams& sp, uint32_t P, SplitBufs& w,
+                      uint64_t extra_scan) {
   const size_t ks = key_bytes(kt);
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   w.tiles1 = hg::div_up(n, hg::kL1Tile);
   w.max_tiles2 = hg::div_up(n, tile2) + sp.nd1;
   w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
                                                            0xFFFFFFFFull));
-  (void)bound;
   const uint64_t len1 = static_cast<uint64_t>(std::max(sp.nd1, P)) * w.tiles1;
   const uint64_t scan_max = std::max<uint64_t>(std::max<uint64_t>(len1, w.max_counts2), extra_scan);
   void *c1 = nullptr, *bs = nullptr, *pl = nullptr, *c2 = nullptr, *b1 = nullptr, *b2 = nullptr;
@@ -351,14 +358,14 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
                        uint32_t* po, uint32_t* bb, hg::PartDesc* desc, uint32_t* offs, void* keys_out,
                        uint32_t* long_count, uint32_t* long_list, Allocs& mem, hipStream_t s) {
   SplitBufs w;
-  hg_status st = alloc_split(mem, n, kt, sp, P, bound, w, 0);
+  hg_status st = alloc_split(mem, n, kt, sp, P, w, 0);
   if (st != HG_OK) return st;
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   const uint32_t max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
   if (sp.mode == 0) {
     HG_LAUNCH("split1_count", s,
               hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_PART, keys, n, 0, nullptr, P, log2P, P, nullptr, 0,
-                                w.counts1, nullptr, nullptr, nullptr, s));
+                                w.counts1, nullptr, nullptr, s));
     HG_LAUNCH("split1_scan", s,
               hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(P) * w.tiles1, w.bsums, s));
     HG_LAUNCH("layout", s,
@@ -379,13 +386,14 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
     }
     HG_LAUNCH("split1_count", s,
               hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_COARSE, keys, n, 0, nullptr, sp.nd1, log2P, P, desc,
-                                sp.sh1, w.counts1, nullptr, nullptr, nullptr, s));
+                                sp.sh1, w.counts1, nullptr, nullptr, s));
     HG_LAUNCH("split1_scan", s,
               hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   }
   HG_LAUNCH("plan", s,
             hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, P, sp.sh1, sp.log2S, tile2, offs, w.plan, s));
-  st = split_two_levels(keys, n, kt, sp, log2P, P, desc, bb, offs, w, s);
+  static const char* const kNames[4] = {"split1_scatter", "split2_count", "split2_scan", "split2_scatter"};
+  st = split_two_levels(keys, n, kt, sp, log2P, P, desc, w, nullptr, nullptr, kNames, s);
   if (st != HG_OK) return st;
   HG_LAUNCH("lds_build", s,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, log2P, P, desc, offs, keys_out,
@@ -404,35 +412,37 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   sp.log2S = t->log2S;
   Allocs mem(s);
   SplitBufs w;
-  hg_status st = alloc_split(mem, q, kt, sp, t->P, t->buckets_bound, w, 0);
+  hg_status st = alloc_split(mem, q, kt, sp, t->P, w, 0);
   if (st != HG_OK) return st;
-  void *c2v = nullptr, *c1v = nullptr;
+  void *c2v = nullptr, *p1v = nullptr, *p2v = nullptr;
   HG_TRY(mem.get(&c2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate split-order counts");
-  HG_TRY(mem.get(&c1v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-1-order counts");
+  HG_TRY(mem.get(&p1v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-1 permutation");
+  HG_TRY(mem.get(&p2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-2 permutation");
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
   const uint32_t max_subbins = hg::div_up(t->buckets_bound, 1ull << sp.log2S) + sp.nd1;
   HG_LAUNCH("qsplit1_count", s,
             hg::launch_msplit(kt, 1, hg::OP_COUNT, dig1, queries, q, 0, nullptr, sp.nd1, t->log2P, t->P, t->d_desc,
-                              sp.sh1, w.counts1, nullptr, nullptr, nullptr, s));
+                              sp.sh1, w.counts1, nullptr, nullptr, s));
   HG_LAUNCH("qsplit1_scan", s,
             hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   HG_LAUNCH("qplan", s,
             hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->P, sp.sh1, sp.log2S, tile2,
                             nullptr, w.plan, s));
-  st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, t->d_bucket_base, nullptr, w, s);
-  if (st != HG_OK) return st;
   uint32_t* c2 = static_cast<uint32_t*>(c2v);
-  uint32_t* c1 = static_cast<uint32_t*>(c1v);
+  uint32_t* perm1 = static_cast<uint32_t*>(p1v);
+  uint32_t* perm2 = static_cast<uint32_t*>(p2v);
+  static const char* const kNames[4] = {"qsplit1_scatter", "qsplit2_count", "qsplit2_scan", "qsplit2_scatter"};
+  st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, w, perm1, perm2, kNames, s);
+  if (st != HG_OK) return st;
   HG_LAUNCH("lds_probe", s,
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, t->log2P, t->P, t->d_desc, t->d_offsets,
                                  t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
-  HG_LAUNCH("qgather2", s,
-            hg::launch_msplit(kt, 2, hg::OP_GATHER, hg::DIG_SUB, w.buf1, q, w.max_tiles2, w.plan, 0, t->log2P, t->P,
-                              t->d_desc, sp.log2S, w.counts2, nullptr, c2, c1, s));
-  HG_LAUNCH("qgather1", s,
-            hg::launch_msplit(kt, 1, count ? hg::OP_GATHER : hg::OP_GATHER_FOUND, dig1, queries, q, 0, nullptr,
-                              sp.nd1, t->log2P, t->P, t->d_desc, sp.sh1, w.counts1, nullptr, c1, out, s));
+  // The level-1 buffer is dead once the level-2 split has read it: it takes
+  // the counts in level-1 order (q words fit in q keys).
+  uint32_t* c1 = static_cast<uint32_t*>(w.buf1);
+  HG_LAUNCH("qgather2", s, hg::launch_perm_gather(perm2, c2, q, c1, false, s));
+  HG_LAUNCH("qgather1", s, hg::launch_perm_gather(perm1, c1, q, out, !count, s));
   return HG_OK;
 }
 

@@ -113,14 +113,24 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
   return __builtin_amdgcn_readlane(v, lane);
 }
 
-// Inclusive sum over the 64 lanes of a wave.
+// Inclusive sum over the 64 lanes of a wave with DPP lane moves (no LDS
+// round trip): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
+// last lane of a row is broadcast into the next row (row_bcast:15 into rows 1
+// and 3) and lane 31 into rows 2 and 3 (row_bcast:31).  Lanes with no source
+// receive 0 (the `old` operand).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), kCtrl, kRowMask, 0xF, false));
+}
+
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
-  const uint32_t l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t u = __shfl_up(v, d, kWave);
-    if (l >= static_cast<uint32_t>(d)) v += u;
-  }
+  constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  v += dpp_or_zero<kRowShr + 1, 0xF>(v);
+  v += dpp_or_zero<kRowShr + 2, 0xF>(v);
+  v += dpp_or_zero<kRowShr + 4, 0xF>(v);
+  v += dpp_or_zero<kRowShr + 8, 0xF>(v);
+  v += dpp_or_zero<kRowBcast15, 0xA>(v);
+  v += dpp_or_zero<kRowBcast31, 0xC>(v);
   return v;
 }
 

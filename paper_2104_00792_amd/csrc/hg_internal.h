@@ -74,19 +74,22 @@ struct SegPlan {
 };
 
 enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2 };
-enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1, OP_GATHER = 2, OP_GATHER_FOUND = 3 };
+enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1 };
 
-// One multisplit pass.  level 1: a single segment [0, n) with nd digits and
-// grid ceil(n / kL1Tile); level 2: segments from `plan`, grid max_tiles.
-// dig/shift: DIG_PART (partition), DIG_COARSE (global bucket >> shift, capped
-// at nd - 1), DIG_SUB (bucket offset in the segment >> shift, capped).
-// COUNT writes per-tile digit counts; SCATTER moves `in` to `out` using the
-// scanned counts; GATHER reads gsrc at the scattered positions and writes
-// gdst in the order of `in` (u32 values, or 0/1 bytes for GATHER_FOUND).
+// One split pass.  level 1: a single segment [0, n) with nd <= 256 digits and
+// grid ceil(n / kL1Tile); level 2: segments from `plan` (<= kMaxD2 digits
+// each), grid max_tiles.  dig/shift: DIG_PART (partition), DIG_COARSE (global
+// bucket >> shift, capped at nd - 1), DIG_SUB (bucket offset in the segment
+// >> shift, capped).  COUNT writes per-tile digit counts; SCATTER moves `in`
+// to `out` using the scanned counts and, when perm is not null, writes
+// perm[i] = output position of in[i].
 hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
                          const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
-                         uint32_t shift, uint32_t* counts, void* out, const uint32_t* gsrc, void* gdst,
-                         hipStream_t s);
+                         uint32_t shift, uint32_t* counts, void* out, uint32_t* perm, hipStream_t s);
+
+// out[i] = src[perm[i]] for i < n (u32), or src[perm[i]] != 0 as bytes.
+hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
+                              hipStream_t s);
 
 // Plan of the level-2 split from the scanned level-1 counts.  mode 0: the
 // level-1 digits are partitions (g0 = bucket_base); mode 1: coarse bucket

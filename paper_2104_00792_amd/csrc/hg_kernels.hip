@@ -340,14 +340,14 @@ hipError_t launch_part_count(int kt, const void* keys, uint32_t n, uint32_t log2
                              uint32_t* tile_counts, hipStream_t s) {
   (void)num_tiles;
   return launch_msplit(kt, 1, OP_COUNT, DIG_PART, keys, n, 0, nullptr, 1u << log2P, log2P, 1u << log2P, nullptr, 0,
-                       tile_counts, nullptr, nullptr, nullptr, s);
+                       tile_counts, nullptr, nullptr, s);
 }
 
 hipError_t launch_part_scatter(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t num_tiles,
                                const uint32_t* tile_base, void* out, hipStream_t s) {
   (void)num_tiles;
   return launch_msplit(kt, 1, OP_SCATTER, DIG_PART, keys, n, 0, nullptr, 1u << log2P, log2P, 1u << log2P, nullptr, 0,
-                       const_cast<uint32_t*>(tile_base), out, nullptr, nullptr, s);
+                       const_cast<uint32_t*>(tile_base), out, nullptr, s);
 }
 
 hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t len_bound, uint32_t* block_sums,

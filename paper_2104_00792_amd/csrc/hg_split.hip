@@ -5,16 +5,18 @@
 // addresses.  At 2^28 keys those random accesses miss every cache; here the
 // same result is reached with streaming passes only:
 //   level-1 split  by partition (Algorithm 2, Phase 2) or by coarse bucket
-//                  range, stable, per-tile counts + scan + scatter;
-//   level-2 split  by sub-bin of 2^15 buckets inside each level-1 segment
-//                  (the paper's second, local binning for cache locality,
-//                  Sec. 3.2, sized here for the 160 KiB LDS of a CU);
+//                  range: per-tile counts + scan + scatter;
+//   level-2 split  by sub-bin of up to 2^14 buckets inside each level-1
+//                  segment (the paper's second, local binning for cache
+//                  locality, Sec. 3.2, sized here for the LDS of a CU);
 //   LDS build      one workgroup per sub-bin: histogram, exclusive scan and
 //                  scatter of Algorithm 1, all three in LDS.
-// Queries follow the same two splits, are counted against LDS-resident
-// windows of the table, and return to their input order by two gather passes
-// that recompute the stable ranks (the inverse permutations are never
-// stored).
+// A split ranks the keys of a tile by one LDS atomic each on the tile's
+// histogram, like the atomic scatter of Algorithm 1: the order inside a
+// digit is whatever the atomics give, which the table leaves free.
+// Queries follow the same two splits, recording where each query went, are
+// counted against LDS-resident windows of the table, and return to their
+// input order by two gathers through those permutations.
 #include "hg_internal.h"
 #include "hg_tile.h"
 
@@ -71,6 +73,7 @@ __device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t e = static_cast<uint32_t>(i) * THREADS + t;
+    v[i] = K(0);  // items past the tail hold a harmless key
     if (e < tlen) {
       v[i] = in[tstart + e];
       mask |= 1u << i;
@@ -79,31 +82,49 @@ __device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_
   return mask;
 }
 
+// Workgroups reach the 8 XCDs of the chip round robin (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  Tile numbers are reassigned so
+// that every XCD walks one contiguous range of tiles in order: neighbouring
+// tiles write neighbouring pieces of each digit run and of each count row,
+// and those partial lines now meet in one L2 instead of leaving it half
+// written.  A bijection of [0, G).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t q = G / kXcd, r = G % kXcd, x = b % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
+// One split pass over a tile: per-tile digit counts (COUNT), or the move of
+// the tile's keys to their digit runs (SCATTER).  SCATTER ranks each key by
+// one LDS atomic on the tile histogram, stages the tile in LDS in digit
+// order and writes every run with consecutive lanes; when `perm` is given it
+// also records, in input order, the output position of every key.
+// Sized for two workgroups of 512 (or four of 256) threads per CU: at least
+// four waves per SIMD, so at most 128 VGPRs.
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP, int DIG>
-__global__ __launch_bounds__(THREADS) void k_msplit(const K* __restrict__ in, uint32_t n,
+__global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in, uint32_t n,
                                                     const SegPlan* __restrict__ plan, uint32_t nd, uint32_t log2P,
                                                     uint32_t P, const PartDesc* __restrict__ desc, uint32_t shift,
                                                     uint32_t* __restrict__ counts, K* __restrict__ out,
-                                                    const uint32_t* __restrict__ gsrc, void* __restrict__ gdst) {
-  constexpr int W = THREADS / kWave;
+                                                    uint32_t* __restrict__ perm) {
   constexpr int TILE = THREADS * ITEMS;
   constexpr bool kCount = OP == OP_COUNT;
-  constexpr bool kStageKeys = OP == OP_SCATTER;
-  constexpr bool kStageVals = OP == OP_GATHER || OP == OP_GATHER_FOUND;
-  __shared__ uint32_t hist[kCount ? MAXD : 1];
-  __shared__ uint32_t wcnt[kCount ? 1 : W][kCount ? 1 : MAXD / 2];
+  constexpr int kDPT = (MAXD + THREADS - 1) / THREADS;  // digits per thread in the scan
+  static_assert(TILE < 65536 && MAXD <= 65536, "digit and rank share a word");
+  __shared__ uint32_t hist[MAXD];
   __shared__ uint32_t dstart[kCount ? 1 : MAXD];
-  __shared__ uint32_t gbase[kCount ? 1 : MAXD];
-  __shared__ uint32_t wtot[W];
+  __shared__ uint32_t delta[kCount ? 1 : MAXD];  // output position of the digit's run minus dstart
+  __shared__ uint32_t wtot[THREADS / kWave];
   __shared__ PartDesc sd[DIG == DIG_PART ? 1 : kMaxP];
-  __shared__ K stage_k[kStageKeys ? TILE : 1];
-  __shared__ uint32_t stage_v[kStageVals ? TILE : 1];
+  __shared__ K stage_k[kCount ? 1 : TILE];
   __shared__ uint16_t sdig[kCount ? 1 : TILE];
 
-  const uint32_t t = threadIdx.x, w = t / kWave, b = blockIdx.x;
-  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl = b;
+  const uint32_t t = threadIdx.x;
+  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl;
   if (plan != nullptr) {
-    if (b >= plan->total_tiles) return;  // whole workgroup
+    const uint32_t G = plan->total_tiles;
+    if (blockIdx.x >= G) return;  // whole workgroup
+    const uint32_t b = xcd_tile(blockIdx.x, G);
     const uint32_t seg = find_segment(plan->tile_first, plan->nseg, b);
     tl = b - plan->tile_first[seg];
     D = plan->D[seg];
@@ -112,6 +133,8 @@ __global__ __launch_bounds__(THREADS) void k_msplit(const K* __restrict__ in, ui
     k1 = plan->key0[seg + 1];
     cb = plan->cbase[seg];
     gs = plan->g0[seg];
+  } else {
+    tl = xcd_tile(blockIdx.x, gridDim.x);
   }
   const uint32_t tstart = k0 + tl * TILE;
   const uint32_t tlen = min(static_cast<uint32_t>(TILE), k1 - tstart);
@@ -119,31 +142,27 @@ __global__ __launch_bounds__(THREADS) void k_msplit(const K* __restrict__ in, ui
 
   if (DIG != DIG_PART)
     for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
-  if (kCount) {
-    for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
-  } else {
-    for (uint32_t i = t; i < static_cast<uint32_t>(W * MAXD / 2); i += THREADS) (&wcnt[0][0])[i] = 0;
-  }
+  for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
   __syncthreads();
 
+  // Per-item values are computed for every item, valid or not (an invalid
+  // item's key is 0, its digit in range); only memory effects are masked.
+  // Conditional assignments to these arrays would make the compiler carry
+  // them as whole vectors through every branch.
   K v[ITEMS];
   uint32_t d[ITEMS];
   const uint32_t mask = load_items<K, THREADS, ITEMS>(in, tstart, tlen, vec, v);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    d[i] = 0;
-    if ((mask >> i) & 1u) {
-      if (DIG == DIG_PART) {
-        d[i] = part_of(KeyTraits<K>::hash(v[i]), log2P);
-      } else {
-        const uint32_t g = bucket_of(v[i], log2P, sd);
-        d[i] = min((g - gs) >> shift, D - 1);
-      }
+    if (DIG == DIG_PART) {
+      d[i] = part_of(KeyTraits<K>::hash(v[i]), log2P);
+    } else {
+      const uint32_t g = bucket_of(v[i], log2P, sd);
+      d[i] = min((g - gs) >> shift, D - 1);
     }
   }
 
   if (kCount) {
-    // Order does not matter for counts: one LDS atomic per key.
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
       if ((mask >> i) & 1u) atomicAdd(&hist[d[i]], 1u);
@@ -152,73 +171,109 @@ __global__ __launch_bounds__(THREADS) void k_msplit(const K* __restrict__ in, ui
     return;
   }
 
-  uint32_t r[ITEMS];
-  wave_multisplit<ITEMS>(d, mask, digit_bits(D), wcnt[w], r);
+  // Rank of each key among the tile's keys of its digit (invalid items add 0).
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) d[i] |= atomicAdd(&hist[d[i]], (mask >> i) & 1u) << 16;
   __syncthreads();
 
-  // Thread t owns digits 2t and 2t+1 (one packed word per wave): it turns
-  // the waves' counts into exclusive prefixes over the waves in place, then
-  // the digit totals give each digit's start in the tile and its output base.
-  static_assert(MAXD <= 2 * THREADS, "two digits per thread");
-  uint32_t tlo = 0, thi = 0;
-  if (2 * t < D) {
+  // Digit starts in the tile (exclusive scan of the histogram; thread t
+  // takes digits kDPT*t ..), and each run's output position.
+  uint32_t c[kDPT], sum = 0;
 #pragma unroll
-    for (int x = 0; x < W; ++x) {
-      const uint32_t c = wcnt[x][t];
-      wcnt[x][t] = tlo | (thi << 16);
-      tlo += c & 0xFFFFu;
-      thi += c >> 16;
-    }
+  for (int x = 0; x < kDPT; ++x) {
+    const uint32_t dd = kDPT * t + x;
+    c[x] = dd < D ? hist[dd] : 0u;
+    sum += c[x];
   }
   uint32_t total;
-  const uint32_t ex = block_exclusive_sum<THREADS>(tlo + thi, wtot, total);
-  if (2 * t < D) {
-    dstart[2 * t] = ex;
-    gbase[2 * t] = counts[cb + (2 * t) * T + tl];
-  }
-  if (2 * t + 1 < D) {
-    dstart[2 * t + 1] = ex + tlo;
-    gbase[2 * t + 1] = counts[cb + (2 * t + 1) * T + tl];
+  uint32_t ex = block_exclusive_sum<THREADS>(sum, wtot, total);
+#pragma unroll
+  for (int x = 0; x < kDPT; ++x) {
+    const uint32_t dd = kDPT * t + x;
+    if (dd < D) {
+      dstart[dd] = ex;
+      delta[dd] = counts[cb + dd * T + tl] - ex;
+    }
+    ex += c[x];
   }
   __syncthreads();
 
-  uint32_t pos[ITEMS];
+  // Stage the tile in digit order; d[i] becomes the key's output position.
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    pos[i] = 0;
+    const uint32_t dig = d[i] & 0xFFFFu;
+    const uint32_t pos = dstart[dig] + (d[i] >> 16);
     if ((mask >> i) & 1u) {
-      pos[i] = dstart[d[i]] + get_half(wcnt[w], d[i]) + r[i];
-      if (kStageKeys) stage_k[pos[i]] = v[i];
-      sdig[pos[i]] = static_cast<uint16_t>(d[i]);
+      stage_k[pos] = v[i];
+      sdig[pos] = static_cast<uint16_t>(dig);
+    }
+    d[i] = delta[dig] + pos;
+  }
+  if (perm != nullptr) {
+    constexpr int kVec = 16 / sizeof(K);
+    if (vec) {
+      // kVec consecutive keys per thread and load: one 16- or 8-byte store.
+#pragma unroll
+      for (int i = 0; i < ITEMS; i += kVec) {
+        uint32_t* dst = perm + tstart + elem_of<K, THREADS>(true, i, t);
+        if (kVec == 4)
+          *reinterpret_cast<uint4*>(dst) = make_uint4(d[i], d[i + 1], d[i + 2], d[i + 3]);
+        else
+          *reinterpret_cast<uint2*>(dst) = make_uint2(d[i], d[i + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i)
+        if ((mask >> i) & 1u) perm[tstart + elem_of<K, THREADS>(false, i, t)] = d[i];
     }
   }
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t j = static_cast<uint32_t>(i) * THREADS + t;
+    if (j < tlen) out[delta[sdig[j]] + j] = stage_k[j];
+  }
+}
 
-  if (OP == OP_SCATTER) {
-    for (uint32_t j = t; j < tlen; j += THREADS) {
-      const uint32_t dd = sdig[j];
-      out[gbase[dd] + (j - dstart[dd])] = stage_k[j];
+// out[i] = src[perm[i]] (u32 values), or (src[perm[i]] != 0) as bytes: the
+// inverse of a split applied to per-key values.  Four elements per thread.
+template <bool FOUND>
+__global__ __launch_bounds__(256) void k_perm_gather(const uint32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ src, uint32_t n,
+                                                     void* __restrict__ out) {
+  const uint32_t i0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
+  if (i0 >= n) return;
+  if (i0 + 4 <= n) {
+    const uint4 p = *reinterpret_cast<const uint4*>(perm + i0);
+    const uint32_t a = src[p.x], b = src[p.y], c = src[p.z], e = src[p.w];
+    if (FOUND) {
+      uint8_t* o = static_cast<uint8_t*>(out) + i0;
+      const uint32_t packed = (a != 0 ? 1u : 0u) | (b != 0 ? 0x100u : 0u) | (c != 0 ? 0x10000u : 0u) |
+                              (e != 0 ? 0x1000000u : 0u);
+      if ((reinterpret_cast<uintptr_t>(o) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(o) = packed;
+      } else {
+        for (int x = 0; x < 4; ++x) o[x] = static_cast<uint8_t>(packed >> (8 * x));
+      }
+    } else {
+      uint32_t* o = static_cast<uint32_t*>(out) + i0;
+      if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+        *reinterpret_cast<uint4*>(o) = make_uint4(a, b, c, e);
+      } else {
+        o[0] = a;
+        o[1] = b;
+        o[2] = c;
+        o[3] = e;
+      }
     }
     return;
   }
-
-  // Gather: the values of this tile's keys sit in digit runs of gsrc, at the
-  // positions the scatter gave them; read the runs in order, then hand each
-  // value back to its key's original place.
-  for (uint32_t j = t; j < tlen; j += THREADS) {
-    const uint32_t dd = sdig[j];
-    stage_v[j] = gsrc[gbase[dd] + (j - dstart[dd])];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    if ((mask >> i) & 1u) {
-      const uint32_t e = tstart + elem_of<K, THREADS>(vec, i, t);
-      if (OP == OP_GATHER)
-        static_cast<uint32_t*>(gdst)[e] = stage_v[pos[i]];
-      else
-        static_cast<uint8_t*>(gdst)[e] = stage_v[pos[i]] != 0 ? 1 : 0;
-    }
+  for (uint32_t i = i0; i < n; ++i) {
+    const uint32_t x = src[perm[i]];
+    if (FOUND)
+      static_cast<uint8_t*>(out)[i] = x != 0 ? 1 : 0;
+    else
+      static_cast<uint32_t*>(out)[i] = x;
   }
 }
 
@@ -350,8 +405,9 @@ __device__ __forceinline__ void note_long(uint32_t* long_count, uint32_t* long_l
   long_list[atomicAdd(long_count, 1u)] = g;
 }
 
-template <typename K, int THREADS, int REG, int MINB>
-__global__ __launch_bounds__(THREADS, MINB) void k_lds_build(const K* __restrict__ in,
+// MINW: waves per SIMD to fit (8: two workgroups of 1024 threads per CU).
+template <typename K, int THREADS, int REG, int MINW>
+__global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict__ in,
                                                              const SegPlan* __restrict__ plan,
                                                              const uint32_t* __restrict__ scan2, uint32_t log2P,
                                                              uint32_t P, const PartDesc* __restrict__ desc,
@@ -485,10 +541,30 @@ __global__ __launch_bounds__(THREADS, MINB) void k_lds_build(const K* __restrict
 }
 
 // ------------------------------------------------------------- LDS probe
+// dst[0 .. len) = src[0 .. len), U loads in flight per thread before their
+// LDS stores (one wait per batch instead of one per element).
+template <int THREADS, int U, typename T>
+__device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __restrict__ src, uint32_t len) {
+  const uint32_t t = threadIdx.x;
+  for (uint32_t b = 0; b < len; b += THREADS * U) {
+    T x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = b + static_cast<uint32_t>(u) * THREADS + t;
+      if (i < len) x[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = b + static_cast<uint32_t>(u) * THREADS + t;
+      if (i < len) dst[i] = x[u];
+    }
+  }
+}
+
 constexpr uint32_t kProbeKeyBytes = 40 * 1024;
 
-template <typename K, int THREADS, int REG, int MINB>
-__global__ __launch_bounds__(THREADS, MINB) void k_lds_probe(const K* __restrict__ q2,
+template <typename K, int THREADS, int REG, int MINW>
+__global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict__ q2,
                                                              const SegPlan* __restrict__ qplan,
                                                              const uint32_t* __restrict__ qscan2, uint32_t log2P,
                                                              uint32_t P, const PartDesc* __restrict__ desc,
@@ -511,21 +587,26 @@ __global__ __launch_bounds__(THREADS, MINB) void k_lds_probe(const K* __restrict
 
   for (uint32_t c0 = 0; c0 < m; c0 += THREADS * REG) {  // one pass unless the sub-bin is oversized
     K qv[REG];
+    // Two 16-bit counts per word, saturated at 0xFFFF (such a query is
+    // counted again from global memory when the counts are written).
+    uint32_t cnt[(REG + 1) / 2];
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
       if (e < m) qv[j] = q2[sb.kA + e];
     }
-    // Each query's bucket lies in exactly one window: its count is written
-    // when that window is in LDS.
+#pragma unroll
+    for (int j = 0; j < (REG + 1) / 2; ++j) cnt[j] = 0;
+    // Each query's bucket lies in exactly one window: its count is taken
+    // when that window is in LDS and written once, after the last window, so
+    // every output line leaves whole.
     for (uint32_t w0 = 0; w0 < R; w0 += Wb) {
       const uint32_t wl = min(Wb, R - w0);
-      for (uint32_t i = t; i <= wl; i += THREADS) soff[i] = offsets[sb.gA + w0 + i];
+      copy_to_lds<THREADS, 8>(soff, offsets + sb.gA + w0, wl + 1);
       __syncthreads();
       const uint32_t ka = soff[0], nk = soff[wl] - ka;
       const bool in_lds = nk <= KCAP;
-      if (in_lds)
-        for (uint32_t i = t; i < nk; i += THREADS) skeys[i] = tkeys[ka + i];
+      if (in_lds) copy_to_lds<THREADS, 8>(skeys, tkeys + ka, nk);
       __syncthreads();
       // Output addresses are rebuilt in every window from one register (the
       // empty asm keeps REG 64-bit addresses from being hoisted and spilled).
@@ -542,12 +623,28 @@ __global__ __launch_bounds__(THREADS, MINB) void k_lds_probe(const K* __restrict
           if (lb >= w0 && lb < w0 + wl) {
             const uint32_t lo = soff[lb - w0], hi = soff[lb - w0 + 1];
             const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-            c2[sb.kA + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[j], srt)
-                                   : count_equal(tkeys, lo, hi, qv[j], srt);
+            const uint32_t c = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[j], srt)
+                                      : count_equal(tkeys, lo, hi, qv[j], srt);
+            cnt[j >> 1] |= min(c, 0xFFFFu) << ((j & 1) << 4);
           }
         }
       }
       __syncthreads();
+    }
+    uint32_t fbase = c0 + t;  // (not hoisted above the windows: see ebase)
+    asm volatile("" : "+v"(fbase));
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = fbase + static_cast<uint32_t>(j) * THREADS;
+      if (e < m) {
+        uint32_t c = (cnt[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu;
+        if (c == 0xFFFFu) {  // a bucket of 65535 keys or more
+          const uint32_t g = bucket_of(qv[j], log2P, sd);
+          const uint32_t lo = offsets[g], hi = offsets[g + 1];
+          c = count_equal(tkeys, lo, hi, qv[j], long_bucket_sorted(unsorted, nuns, g, kMaxUnsorted));
+        }
+        c2[sb.kA + e] = c;
+      }
     }
   }
 }
@@ -732,67 +829,69 @@ __global__ __launch_bounds__(256) void k_find_long(const uint32_t* __restrict__ 
 
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP>
 hipError_t msplit_dig(int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd, uint32_t log2P,
-                      uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out,
-                      const uint32_t* gsrc, void* gdst, hipStream_t s) {
+                      uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out, uint32_t* perm,
+                      hipStream_t s) {
   if (dig == DIG_PART)
     k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_PART><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
-                                                                            counts, out, gsrc, gdst);
+                                                                            counts, out, perm);
   else if (dig == DIG_COARSE)
     k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_COARSE><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
-                                                                              counts, out, gsrc, gdst);
+                                                                              counts, out, perm);
   else
     k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_SUB><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
-                                                                           counts, out, gsrc, gdst);
+                                                                           counts, out, perm);
   return hipGetLastError();
 }
 
 template <typename K, int THREADS, int ITEMS, int MAXD>
 hipError_t msplit_op(int op, int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd,
                      uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out,
-                     const uint32_t* gsrc, void* gdst, hipStream_t s) {
-  switch (op) {
-    case OP_COUNT:
-      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_COUNT>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
-                                                          out, gsrc, gdst, s);
-    case OP_SCATTER:
-      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_SCATTER>(dig, grid, in, n, plan, nd, log2P, P, desc, shift,
-                                                            counts, out, gsrc, gdst, s);
-    case OP_GATHER:
-      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_GATHER>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
-                                                           out, gsrc, gdst, s);
-    default:
-      return msplit_dig<K, THREADS, ITEMS, MAXD, OP_GATHER_FOUND>(dig, grid, in, n, plan, nd, log2P, P, desc, shift,
-                                                                 counts, out, gsrc, gdst, s);
-  }
+                     uint32_t* perm, hipStream_t s) {
+  if (op == OP_COUNT)
+    return msplit_dig<K, THREADS, ITEMS, MAXD, OP_COUNT>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
+                                                        out, perm, s);
+  return msplit_dig<K, THREADS, ITEMS, MAXD, OP_SCATTER>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
+                                                        out, perm, s);
 }
 
 template <typename K>
 hipError_t msplit_level(int level, int op, int dig, const K* in, uint32_t n, uint32_t max_tiles, const SegPlan* plan,
                         uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift,
-                        uint32_t* counts, K* out, const uint32_t* gsrc, void* gdst, hipStream_t s) {
+                        uint32_t* counts, K* out, uint32_t* perm, hipStream_t s) {
   if (level == 1) {
     const uint32_t tiles = div_up(n, kL1Tile);
     if (tiles == 0) return hipSuccess;
+    if (nd > 256) return hipErrorInvalidValue;
     return msplit_op<K, kL1Threads, 16, 256>(op, dig, dim3(tiles), in, n, nullptr, nd, log2P, P, desc, shift, counts,
-                                              out, gsrc, gdst, s);
+                                              out, perm, s);
   }
   if (max_tiles == 0) return hipSuccess;
   constexpr int kItems2 = sizeof(K) == 4 ? 16 : 8;
   return msplit_op<K, kL2Threads, kItems2, kMaxD2>(op, dig, dim3(max_tiles), in, n, plan, nd, log2P, P, desc, shift,
-                                                    counts, out, gsrc, gdst, s);
+                                                    counts, out, perm, s);
 }
 
 }  // namespace
 
 hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
                          const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
-                         uint32_t shift, uint32_t* counts, void* out, const uint32_t* gsrc, void* gdst,
-                         hipStream_t s) {
+                         uint32_t shift, uint32_t* counts, void* out, uint32_t* perm, hipStream_t s) {
   if (kt == 0)
     return msplit_level<uint32_t>(level, op, dig, static_cast<const uint32_t*>(in), n, max_tiles, plan, nd, log2P, P,
-                                  desc, shift, counts, static_cast<uint32_t*>(out), gsrc, gdst, s);
+                                  desc, shift, counts, static_cast<uint32_t*>(out), perm, s);
   return msplit_level<uint64_t>(level, op, dig, static_cast<const uint64_t*>(in), n, max_tiles, plan, nd, log2P, P,
-                                desc, shift, counts, static_cast<uint64_t*>(out), gsrc, gdst, s);
+                                desc, shift, counts, static_cast<uint64_t*>(out), perm, s);
+}
+
+hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t blocks = div_up(n, 1024);
+  if (found)
+    k_perm_gather<true><<<blocks, 256, 0, s>>>(perm, src, n, out);
+  else
+    k_perm_gather<false><<<blocks, 256, 0, s>>>(perm, src, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
@@ -807,11 +906,11 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
                             uint32_t* long_count, uint32_t* long_list, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   if (kt == 0)
-    k_lds_build<uint32_t, kLdsThreads, 20, 2><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_build<uint32_t, kLdsThreads, 20, 8><<<max_subbins, kLdsThreads, 0, s>>>(
         static_cast<const uint32_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint32_t*>(out),
         long_count, long_list);
   else
-    k_lds_build<uint64_t, kLdsThreads, 20, 1><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_build<uint64_t, kLdsThreads, 20, 4><<<max_subbins, kLdsThreads, 0, s>>>(
         static_cast<const uint64_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint64_t*>(out),
         long_count, long_list);
   return hipGetLastError();
@@ -823,11 +922,11 @@ hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const 
                             uint32_t* c2, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   if (kt == 0)
-    k_lds_probe<uint32_t, kLdsThreads, 20, 2><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_probe<uint32_t, kLdsThreads, 20, 8><<<max_subbins, kLdsThreads, 0, s>>>(
         static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint32_t*>(tkeys),
         unsorted, log2W, c2);
   else
-    k_lds_probe<uint64_t, kLdsThreads, 20, 1><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_probe<uint64_t, kLdsThreads, 20, 4><<<max_subbins, kLdsThreads, 0, s>>>(
         static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint64_t*>(tkeys),
         unsorted, log2W, c2);
   return hipGetLastError();

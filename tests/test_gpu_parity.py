@@ -131,12 +131,13 @@ def test_multi_subbin_tables(gpu, P, num, den, build):
 
 
 def test_wide_segment_uses_global_counters(gpu):
-    """All keys equal with P = 16 and table ratio 48: the one non-empty
-    partition gets 48 * 2^20 buckets, more than 2^15 x 1024, so the sorted
+    """All keys equal with P = 16 and table ratio 24: the average partition
+    is small enough for partition segments, but the one non-empty partition
+    gets 24 * 2^20 buckets, more than 1024 sub-bins of 2^14, so the sorted
     build folds its tail into one wide sub-bin that counts in global memory.
     Checked against the oracle like every other case."""
     n = 1 << 20
-    check_table(gpu, make_keys("equal", n, np.uint32, 0), P=16, num=48, den=1, build="sorted")
+    check_table(gpu, make_keys("equal", n, np.uint32, 0), P=16, num=24, den=1, build="sorted")
 
 
 def test_repeat_is_deterministic(gpu):
@@ -246,4 +247,25 @@ def test_long_buckets(gpu, case, dtype, build):
         seg = tk[offs[g]:offs[g + 1]]
         if np.unique(seg).size <= 64 or seg.size <= 4096:
             assert np.all(seg[1:] >= seg[:-1]), f"long bucket {g} of {seg.size} keys is not sorted"
+    t.free()
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("shift", [0, 1, 3])
+def test_sorted_probe_output_alignment(gpu, dtype, shift):
+    """The last gather of the sorted probe stores whole vectors when the
+    output allows it; an output that starts `shift` u32 elements into an
+    allocation (not 16-byte aligned) takes the element-wise stores.  Both
+    give the oracle's counts."""
+    import torch
+
+    keys = make_keys("uniform", 50000, dtype, 21)
+    queries = inputs.queries_hit50(keys, 3 * 4096 * 4 + 1234, 0xA11)
+    t = gpu.hg_build(to_dev(keys), P=16)
+    buf = torch.full((queries.size + shift,), 0xFFFFFFFF, dtype=torch.uint32, device="cuda")
+    out = buf[shift:]
+    gpu.hg_count(t, to_dev(queries), out=out, flags=PROBES["sorted"])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.count(keys, queries))
+    assert np.all(buf[:shift].cpu().numpy() == 0xFFFFFFFF)
     t.free()
