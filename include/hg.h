@@ -148,6 +148,37 @@ hg_status hg_count_ex(const hg_table* table, const void* d_queries, uint64_t q,
 hg_status hg_query_ex(const hg_table* table, const void* d_queries, uint64_t q,
                       uint8_t* d_found, uint32_t flags, hipStream_t stream);
 
+/* hg_build_batched -- T independent tables in one call: table t holds keys
+ * d_keys[o[t] .. o[t+1]) with o = d_table_offsets (device, T + 1 uint32,
+ * o[0] = 0, non-decreasing, o[T] = n) and V_t = max(1, floor(n_t * num /
+ * den)) buckets (opts->ratio_num / ratio_den; opts->P must be 1,
+ * opts->num_buckets 0).  Each table is the HashGraph of Algorithm 1 over its
+ * own keys; the batch is stored as one CSR over sum(V_t) buckets, in which
+ * table t is "partition" t: hg_table_info reports P = T, part_offsets = o
+ * and bucket_base[t] = first bucket of table t.  Offsets that break the
+ * contract are clamped on the device to a non-decreasing sequence from 0 to
+ * n (no fault; the tables then cover the clamped ranges).  Probe the result
+ * with hg_count_batched / hg_query_batched only.  Errors: as hg_build, plus
+ * HG_ERR_INVALID_ARG for T = 0, T > 2^22, null d_table_offsets, P != 1,
+ * num_buckets != 0; HG_ERR_UNSUPPORTED for HG_BUILD_ATOMIC. */
+hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt,
+                           uint32_t num_tables, const uint32_t* d_table_offsets,
+                           const hg_build_opts* opts, hipStream_t stream,
+                           hg_table** out);
+
+/* hg_count_batched / hg_query_batched -- probe a batched table: queries
+ * d_queries[qo[t] .. qo[t+1]) go to table t (qo = d_query_offsets, device,
+ * T + 1 uint32, same contract and clamping as the table offsets, qo[T] =
+ * q).  Outputs as hg_count / hg_query, in query order.  Errors: as
+ * hg_count, plus HG_ERR_INVALID_ARG for a table that is not batched or a
+ * null d_query_offsets. */
+hg_status hg_count_batched(const hg_table* table, const void* d_queries,
+                           uint64_t q, const uint32_t* d_query_offsets,
+                           uint32_t* d_counts, hipStream_t stream);
+hg_status hg_query_batched(const hg_table* table, const void* d_queries,
+                           uint64_t q, const uint32_t* d_query_offsets,
+                           uint8_t* d_found, hipStream_t stream);
+
 /* hg_bin_partition -- the hash-range split alone (Algorithm 2, Phase 2:
  * count per destination, prefix sum, scatter into a buffer), with P equal
  * hash ranges.  Writes d_out_keys[n] grouped by partition (order inside a

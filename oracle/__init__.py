@@ -181,3 +181,45 @@ def canonicalize(offsets: np.ndarray, keys: np.ndarray) -> np.ndarray:
     seg = np.repeat(np.arange(lengths.size, dtype=np.int64), lengths)
     order = np.lexsort((keys, seg))
     return keys[order]
+
+
+def clamp_offsets(offsets: np.ndarray, n: int) -> np.ndarray:
+    """Segment offsets as the batched calls read them: entry 0 is 0, entry T
+    is n, every other entry min(o[x], n), then the running maximum (a
+    non-decreasing sequence from 0 to n)."""
+    o = np.asarray(offsets, dtype=np.int64).copy()
+    o[0] = 0
+    o[-1] = n
+    o = np.minimum(o, n)
+    return np.maximum.accumulate(o).astype(np.uint32)
+
+
+def build_batched(keys: np.ndarray, table_offsets: np.ndarray, num: int = 1, den: int = 1):
+    """A batch of tables: table t is build_table(keys[o[t]:o[t+1]]) with P = 1,
+    its buckets placed after those of tables 0..t-1 (one CSR over all
+    buckets).  Returns dict(part_offsets = o, bucket_base, offsets, keys)."""
+    keys = np.ascontiguousarray(keys)
+    o = clamp_offsets(table_offsets, keys.size)
+    bb = [0]
+    offs = []
+    out = []
+    for t in range(o.size - 1):
+        r = build_table(keys[int(o[t]):int(o[t + 1])], P=1, num=num, den=den)
+        offs.append(r["offsets"][:-1].astype(np.int64) + int(o[t]))
+        out.append(r["keys"])
+        bb.append(bb[-1] + int(r["bucket_base"][1]))
+    offsets = np.concatenate(offs + [np.array([keys.size], np.int64)]).astype(np.uint32)
+    kk = np.concatenate(out) if out else keys[:0].copy()
+    return {"part_offsets": o, "bucket_base": np.array(bb, np.uint32), "offsets": offsets, "keys": kk}
+
+
+def count_batched(keys: np.ndarray, table_offsets: np.ndarray, queries: np.ndarray,
+                  query_offsets: np.ndarray) -> np.ndarray:
+    """Multiplicity of every query of segment t among the keys of table t."""
+    o = clamp_offsets(table_offsets, keys.size)
+    qo = clamp_offsets(query_offsets, queries.size)
+    out = np.empty(queries.size, np.uint32)
+    for t in range(o.size - 1):
+        a, b = int(qo[t]), int(qo[t + 1])
+        out[a:b] = count(keys[int(o[t]):int(o[t + 1])], queries[a:b])
+    return out

@@ -6,7 +6,9 @@ build and the probe runs in the library's HIP kernels.  If ``libhg.so`` has
 not been built the first call raises; there is no fallback path.
 
 Entry points mirror ``include/hg.h``: :func:`hg_build`, :func:`hg_count`,
-:func:`hg_query`, :func:`hg_bin_partition`, :func:`hg_hash_bucket`.
+:func:`hg_query`, :func:`hg_bin_partition`, :func:`hg_hash_bucket`, and the
+batched forms :func:`hg_build_batched`, :func:`hg_count_batched`,
+:func:`hg_query_batched`.
 """
 
 from __future__ import annotations
@@ -16,7 +18,8 @@ import os
 
 __all__ = [
     "HGError", "Table", "hg_build", "hg_count", "hg_query", "hg_bin_partition",
-    "hg_hash_bucket", "lib", "lib_path", "profile",
+    "hg_hash_bucket", "hg_build_batched", "hg_count_batched", "hg_query_batched",
+    "lib", "lib_path", "profile",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -94,6 +97,12 @@ def lib() -> ctypes.CDLL:
     L.hg_count_ex.restype = i32
     L.hg_query_ex.argtypes = [vp, vp, u64, vp, u32, vp]
     L.hg_query_ex.restype = i32
+    L.hg_build_batched.argtypes = [vp, u64, i32, u32, vp, ctypes.POINTER(_BuildOpts), vp, ctypes.POINTER(vp)]
+    L.hg_build_batched.restype = i32
+    L.hg_count_batched.argtypes = [vp, vp, u64, vp, vp, vp]
+    L.hg_count_batched.restype = i32
+    L.hg_query_batched.argtypes = [vp, vp, u64, vp, vp, vp]
+    L.hg_query_batched.restype = i32
     L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
     L.hg_bin_partition.restype = i32
     L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
@@ -246,6 +255,46 @@ def hg_query(table: Table, queries, out=None, stream=None, flags: int = 0):
         out = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
     _check(lib().hg_query_ex(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(out), flags,
                              _stream(stream)), "hg_query")
+    return out
+
+
+def hg_build_batched(keys, table_offsets, ratio=(1, 1), stream=None) -> Table:
+    """Build T tables at once: table t holds keys[table_offsets[t] ..
+    table_offsets[t+1]) (``table_offsets``: uint32 device tensor of T + 1
+    entries from 0 to n) with V_t = max(1, n_t * ratio[0] // ratio[1])."""
+    kt = _key_type(keys)
+    T = table_offsets.numel() - 1
+    if table_offsets.dtype not in (_torch().uint32, _torch().int32):
+        raise TypeError("table_offsets must be 32-bit")
+    opts = _BuildOpts(1, ratio[0], ratio[1], 0, 0)
+    h = ctypes.c_void_p()
+    _check(lib().hg_build_batched(_dev_ptr(keys), keys.numel(), kt, max(T, 0), _dev_ptr(table_offsets),
+                                  ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hg_build_batched")
+    return Table(h.value, kt, keys.numel(), T)
+
+
+def hg_count_batched(table: Table, queries, query_offsets, out=None, stream=None):
+    """Exact multiplicity of each query in its own table: queries[qo[t] ..
+    qo[t+1]) go to table t (``query_offsets`` = qo, uint32 device tensor)."""
+    torch = _torch()
+    if _key_type(queries) != table.key_type:
+        raise TypeError("queries and table keys differ in width")
+    if out is None:
+        out = torch.empty(queries.numel(), dtype=torch.uint32, device=queries.device)
+    _check(lib().hg_count_batched(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(query_offsets),
+                                  _dev_ptr(out), _stream(stream)), "hg_count_batched")
+    return out
+
+
+def hg_query_batched(table: Table, queries, query_offsets, out=None, stream=None):
+    """Existence of each query in its own table (uint8 0/1)."""
+    torch = _torch()
+    if _key_type(queries) != table.key_type:
+        raise TypeError("queries and table keys differ in width")
+    if out is None:
+        out = torch.empty(queries.numel(), dtype=torch.uint8, device=queries.device)
+    _check(lib().hg_query_batched(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(query_offsets),
+                                  _dev_ptr(out), _stream(stream)), "hg_query_batched")
     return out
 
 

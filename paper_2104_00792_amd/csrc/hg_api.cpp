@@ -36,6 +36,7 @@ struct hg_table {
   uint32_t sh1;             // coarse range 2^sh1 buckets (mode 1)
   uint32_t nd1;             // level-1 digits
   uint32_t log2S;           // sub-bins of 2^log2S buckets
+  bool batched;             // P caller-defined tables (hg_build_batched)
   std::mutex mu;
   bool have_num_buckets;
   uint64_t num_buckets;
@@ -339,7 +340,7 @@ hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams
   void *c1 = nullptr, *bs = nullptr, *pl = nullptr, *c2 = nullptr, *b1 = nullptr, *b2 = nullptr;
   HG_TRY(mem.get(&c1, std::max<uint64_t>(len1, 1) * sizeof(uint32_t)), "allocate level-1 counts");
   HG_TRY(mem.get(&bs, (hg::div_up(scan_max, hg::kScanChunk) + 1) * sizeof(uint32_t)), "allocate scan workspace");
-  HG_TRY(mem.get(&pl, sizeof(hg::SegPlan)), "allocate split plan");
+  HG_TRY(mem.get(&pl, hg::plan_bytes(sp.nd1)), "allocate split plan");
   HG_TRY(mem.get(&c2, std::max<uint64_t>(w.max_counts2, 1) * sizeof(uint32_t)), "allocate level-2 counts");
   HG_TRY(mem.get(&b1, std::max<uint64_t>(n, 1) * ks), "allocate level-1 buffer");
   HG_TRY(mem.get(&b2, std::max<uint64_t>(n, 1) * ks), "allocate level-2 buffer");
@@ -391,7 +392,8 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
               hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   }
   HG_LAUNCH("plan", s,
-            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, P, sp.sh1, sp.log2S, tile2, offs, w.plan, s));
+            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, bb + P, nullptr, sp.sh1, sp.log2S, tile2, offs,
+                            w.plan, s));
   static const char* const kNames[4] = {"split1_scatter", "split2_count", "split2_scan", "split2_scatter"};
   st = split_two_levels(keys, n, kt, sp, log2P, P, desc, w, nullptr, nullptr, kNames, s);
   if (st != HG_OK) return st;
@@ -427,8 +429,8 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   HG_LAUNCH("qsplit1_scan", s,
             hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   HG_LAUNCH("qplan", s,
-            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->P, sp.sh1, sp.log2S, tile2,
-                            nullptr, w.plan, s));
+            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->d_bucket_base + t->P, nullptr,
+                            sp.sh1, sp.log2S, tile2, nullptr, w.plan, s));
   uint32_t* c2 = static_cast<uint32_t*>(c2v);
   uint32_t* perm1 = static_cast<uint32_t*>(p1v);
   uint32_t* perm2 = static_cast<uint32_t*>(p2v);
@@ -455,6 +457,7 @@ bool use_sorted_probe(const hg_table* t, uint64_t q, uint32_t flags) {
 hg_status probe(const hg_table* t, const void* d_queries, uint64_t q, void* d_out, bool count, uint32_t flags,
                 hipStream_t s) {
   if (t == nullptr) return fail(HG_ERR_INVALID_ARG, "null table");
+  if (t->batched) return fail(HG_ERR_INVALID_ARG, "a batched table is probed with hg_count_batched / hg_query_batched");
   if (q >= (1ull << 32)) return fail(HG_ERR_INVALID_ARG, "q = %llu is not below 2^32", (unsigned long long)q);
   if (q > 0 && (d_queries == nullptr || d_out == nullptr)) return fail(HG_ERR_INVALID_ARG, "null queries or output");
   if ((flags & ~(HG_PROBE_DIRECT | HG_PROBE_SORTED)) != 0 || flags == (HG_PROBE_DIRECT | HG_PROBE_SORTED))
@@ -464,6 +467,85 @@ hg_status probe(const hg_table* t, const void* d_queries, uint64_t q, void* d_ou
   HG_LAUNCH(count ? "probe_count" : "probe_found", s,
             hg::launch_probe(t->kt, count, t->d_keys, t->d_offsets, t->d_desc, t->log2P, t->P, t->d_unsorted,
                              d_queries, static_cast<uint32_t>(q), d_out, s));
+  return HG_OK;
+}
+
+// Level-2 split, sub-bin builds and long-bucket sorting of keys already
+// grouped into segments by `plan` (batched tables).
+struct L2Bufs {
+  hg::SegPlan* plan;
+  uint32_t* counts2;
+  uint32_t* bsums;
+  void* buf2;
+  uint32_t max_tiles2;
+  uint32_t max_counts2;
+};
+
+hg_status alloc_l2(Allocs& mem, uint64_t n, hg_key_type kt, uint32_t nseg, L2Bufs& w) {
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  w.max_tiles2 = hg::div_up(n, tile2) + nseg;
+  w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
+                                                           0xFFFFFFFFull));
+  void *pl = nullptr, *c2 = nullptr, *bs = nullptr, *b2 = nullptr;
+  HG_TRY(mem.get(&pl, hg::plan_bytes(nseg)), "allocate split plan");
+  HG_TRY(mem.get(&c2, std::max<uint64_t>(w.max_counts2, 1) * sizeof(uint32_t)), "allocate level-2 counts");
+  HG_TRY(mem.get(&bs, (hg::div_up(w.max_counts2, hg::kScanChunk) + 1) * sizeof(uint32_t)), "allocate scan workspace");
+  HG_TRY(mem.get(&b2, std::max<uint64_t>(n, 1) * key_bytes(kt)), "allocate level-2 buffer");
+  w.plan = static_cast<hg::SegPlan*>(pl);
+  w.counts2 = static_cast<uint32_t*>(c2);
+  w.bsums = static_cast<uint32_t*>(bs);
+  w.buf2 = b2;
+  return HG_OK;
+}
+
+// Count, scan and scatter of the segments of w.plan (one descriptor per
+// segment) from src into w.buf2; perm (probes) receives output positions.
+hg_status split_segments(const void* src, uint32_t n, hg_key_type kt, uint32_t log2S, const hg::PartDesc* desc,
+                         const L2Bufs& w, uint32_t* perm, const char* const names[3], hipStream_t s) {
+  HG_LAUNCH(names[0], s,
+            hg::launch_msplit(kt, 2, hg::OP_COUNT, hg::DIG_SUB, src, n, w.max_tiles2, w.plan, 0, 0, 1, desc, log2S,
+                              w.counts2, nullptr, nullptr, s));
+  HG_LAUNCH(names[1], s, hg::launch_scan_exclusive(w.counts2, &w.plan->total_counts, w.max_counts2, w.bsums, s));
+  HG_LAUNCH(names[2], s,
+            hg::launch_msplit(kt, 2, hg::OP_SCATTER, hg::DIG_SUB, src, n, w.max_tiles2, w.plan, 0, 0, 1, desc, log2S,
+                              w.counts2, w.buf2, perm, s));
+  return HG_OK;
+}
+
+hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, const uint32_t* d_qo, void* d_out,
+                        bool count, hipStream_t s) {
+  if (t == nullptr) return fail(HG_ERR_INVALID_ARG, "null table");
+  if (!t->batched) return fail(HG_ERR_INVALID_ARG, "not a batched table (probe it with hg_count / hg_query)");
+  if (q >= (1ull << 32)) return fail(HG_ERR_INVALID_ARG, "q = %llu is not below 2^32", (unsigned long long)q);
+  if (d_qo == nullptr) return fail(HG_ERR_INVALID_ARG, "null query offsets");
+  if (q > 0 && (d_queries == nullptr || d_out == nullptr)) return fail(HG_ERR_INVALID_ARG, "null queries or output");
+  if (q == 0) return HG_OK;
+  const hg_key_type kt = t->kt;
+  const uint32_t T = t->P, q32 = static_cast<uint32_t>(q);
+  Allocs mem(s);
+  L2Bufs w;
+  hg_status st = alloc_l2(mem, q, kt, T, w);
+  if (st != HG_OK) return st;
+  void *qov = nullptr, *pv = nullptr, *c2v = nullptr;
+  HG_TRY(mem.get(&qov, (static_cast<uint64_t>(T) + 1) * sizeof(uint32_t)), "allocate query offsets");
+  HG_TRY(mem.get(&pv, q * sizeof(uint32_t)), "allocate permutation");
+  HG_TRY(mem.get(&c2v, q * sizeof(uint32_t)), "allocate split-order counts");
+  uint32_t* qo = static_cast<uint32_t*>(qov);
+  uint32_t* perm = static_cast<uint32_t*>(pv);
+  uint32_t* c2 = static_cast<uint32_t*>(c2v);
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  HG_LAUNCH("bq_offsets", s, hg::launch_batch_layout(d_qo, T, q32, 1, 1, qo, nullptr, nullptr, s));
+  HG_LAUNCH("bq_plan", s,
+            hg::launch_plan(nullptr, 0, T, q32, 2, t->d_bucket_base, t->d_bucket_base + T, qo, 0, t->log2S, tile2,
+                            nullptr, w.plan, s));
+  static const char* const kNames[3] = {"bqsplit_count", "bqsplit_scan", "bqsplit_scatter"};
+  st = split_segments(d_queries, q32, kt, t->log2S, t->d_desc, w, perm, kNames, s);
+  if (st != HG_OK) return st;
+  const uint32_t max_subbins = hg::div_up(t->buckets_bound, 1ull << t->log2S) + T;
+  HG_LAUNCH("blds_probe", s,
+            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, t->d_desc, t->d_offsets, t->d_keys,
+                                 t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
+  HG_LAUNCH("bqgather", s, hg::launch_perm_gather(perm, c2, q32, d_out, !count, s));
   return HG_OK;
 }
 
@@ -583,6 +665,7 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   t->sh1 = sp.sh1;
   t->nd1 = sp.nd1;
   t->log2S = sp.log2S;
+  t->batched = false;
   t->have_num_buckets = false;
   t->num_buckets = 0;
   mem.release(keys_out);
@@ -608,6 +691,110 @@ hg_status hg_count_ex(const hg_table* table, const void* d_queries, uint64_t q, 
 hg_status hg_query_ex(const hg_table* table, const void* d_queries, uint64_t q, uint8_t* d_found, uint32_t flags,
                       hipStream_t stream) {
   return probe(table, d_queries, q, d_found, false, flags, stream);
+}
+
+hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t num_tables,
+                           const uint32_t* d_table_offsets, const hg_build_opts* opts, hipStream_t stream,
+                           hg_table** out) {
+  if (out == nullptr || opts == nullptr) return fail(HG_ERR_INVALID_ARG, "null opts or out");
+  hg_status st = check_n_P(n, kt, 1);
+  if (st != HG_OK) return st;
+  const uint32_t T = num_tables;
+  if (T == 0 || T > hg::kMaxTables) return fail(HG_ERR_INVALID_ARG, "num_tables = %u outside [1, 2^22]", T);
+  if (d_table_offsets == nullptr) return fail(HG_ERR_INVALID_ARG, "null table offsets");
+  if (n > 0 && d_keys == nullptr) return fail(HG_ERR_INVALID_ARG, "null keys");
+  if (opts->P != 1) return fail(HG_ERR_INVALID_ARG, "batched tables take P = 1 (got %u)", opts->P);
+  if (opts->num_buckets != 0) return fail(HG_ERR_INVALID_ARG, "batched tables take their size from the ratio");
+  if ((opts->flags & ~(HG_BUILD_ATOMIC | HG_BUILD_SORTED)) != 0)
+    return fail(HG_ERR_INVALID_ARG, "unknown build flags 0x%x", opts->flags);
+  if (opts->flags & HG_BUILD_ATOMIC) return fail(HG_ERR_UNSUPPORTED, "batched tables use the sorted build");
+  if (opts->ratio_num == 0 || opts->ratio_den == 0) return fail(HG_ERR_INVALID_ARG, "zero table ratio");
+  // sum_t max(1, floor(n_t * num / den)) <= floor(n * num / den) + T.
+  const uint64_t bound = n * static_cast<uint64_t>(opts->ratio_num) / opts->ratio_den + T;
+  if (bound > 0xFFFFFFFEull) return fail(HG_ERR_INVALID_ARG, "table ratio gives more than 2^32 - 2 buckets");
+
+  const uint32_t n32 = static_cast<uint32_t>(n);
+  const size_t ks = key_bytes(kt);
+  int device = 0;
+  HG_TRY(hipGetDevice(&device), "hipGetDevice");
+  Allocs mem(stream);
+  void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr, *longv = nullptr;
+  const size_t meta_bytes =
+      2 * sizeof(uint32_t) * (static_cast<size_t>(T) + 1) + 8 + sizeof(hg::PartDesc) * T +
+      sizeof(uint32_t) * (1 + hg::kMaxUnsorted);
+  HG_TRY(mem.get(&keys_out, std::max<uint64_t>(n, 1) * ks), "allocate table keys");
+  HG_TRY(mem.get(&offsets, (bound + 1) * sizeof(uint32_t)), "allocate table offsets");
+  HG_TRY(mem.get(&meta, meta_bytes), "allocate table metadata");
+  uint32_t* po = static_cast<uint32_t*>(meta);
+  uint32_t* bb = po + (T + 1);
+  uintptr_t dp = reinterpret_cast<uintptr_t>(bb + (T + 1));
+  dp = (dp + 7) & ~static_cast<uintptr_t>(7);
+  hg::PartDesc* desc = reinterpret_cast<hg::PartDesc*>(dp);
+  uint32_t* unsorted = reinterpret_cast<uint32_t*>(desc + T);
+  const uint64_t long_cap = n / (hg::kLongT + 1) + 1;
+  HG_TRY(mem.get(&longv, (2 + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
+  uint32_t* long_ctr = static_cast<uint32_t*>(longv);
+  uint32_t* long_list = long_ctr + 2;
+  uint32_t* offs = static_cast<uint32_t*>(offsets);
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, 2, 0u, stream));
+  HG_LAUNCH("zero_unsorted", stream, hg::launch_fill_u32(unsorted, 1, 0u, stream));
+  HG_LAUNCH("batch_layout", stream,
+            hg::launch_batch_layout(d_table_offsets, T, n32, opts->ratio_num, opts->ratio_den, po, bb, desc, stream));
+
+  const SplitParams sp = split_params(1, n, bound);  // sub-bin size from the batch's keys per bucket
+  L2Bufs w;
+  st = alloc_l2(mem, n, kt, T, w);
+  if (st != HG_OK) return st;
+  const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
+  HG_LAUNCH("bplan", stream,
+            hg::launch_plan(nullptr, 0, T, n32, 2, bb, bb + T, po, 0, sp.log2S, tile2, offs, w.plan, stream));
+  static const char* const kNames[3] = {"bsplit_count", "bsplit_scan", "bsplit_scatter"};
+  st = split_segments(d_keys, n32, kt, sp.log2S, desc, w, nullptr, kNames, stream);
+  if (st != HG_OK) return st;
+  const uint32_t max_subbins = hg::div_up(bound, 1ull << sp.log2S) + T;
+  HG_LAUNCH("blds_build", stream,
+            hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, desc, offs, keys_out, long_ctr,
+                                 long_list, stream));
+  HG_LAUNCH("long_sort", stream,
+            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted, stream));
+
+  hg_table* t = new hg_table();
+  t->device = device;
+  t->stream = stream;
+  t->kt = kt;
+  t->n = n;
+  t->P = T;
+  t->log2P = 0;
+  t->buckets_bound = bound;
+  t->d_keys = keys_out;
+  t->d_offsets = offs;
+  t->d_meta = meta;
+  t->d_part_offsets = po;
+  t->d_bucket_base = bb;
+  t->d_desc = desc;
+  t->d_unsorted = unsorted;
+  t->split_mode = 2;
+  t->sh1 = 0;
+  t->nd1 = T;
+  t->log2S = sp.log2S;
+  t->batched = true;
+  t->have_num_buckets = false;
+  t->num_buckets = 0;
+  mem.release(keys_out);
+  mem.release(offsets);
+  mem.release(meta);
+  *out = t;
+  return HG_OK;
+}
+
+hg_status hg_count_batched(const hg_table* table, const void* d_queries, uint64_t q, const uint32_t* d_query_offsets,
+                           uint32_t* d_counts, hipStream_t stream) {
+  return probe_batched(table, d_queries, q, d_query_offsets, d_counts, true, stream);
+}
+
+hg_status hg_query_batched(const hg_table* table, const void* d_queries, uint64_t q, const uint32_t* d_query_offsets,
+                           uint8_t* d_found, hipStream_t stream) {
+  return probe_batched(table, d_queries, q, d_query_offsets, d_found, false, stream);
 }
 
 hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t P, void* d_out_keys,

@@ -24,7 +24,6 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a
 // level-1 segment (<= kMaxD2 digits, kL2Threads x 16 (32-bit) or x 8 (64-bit)
 // key tiles).  The LDS stages then sort (build) or probe one sub-bin per
 // workgroup.
-constexpr int kMaxSeg = 256;
 constexpr uint32_t kLog2SMax = 14;  // regular sub-bins: 2^log2S <= 2^14 buckets
 constexpr uint32_t kLog2SMin = 10;
 constexpr uint32_t kLog2SLds = 15;  // a segment's last sub-bin may grow to 2^15 in LDS
@@ -60,18 +59,30 @@ inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 16 : 8); }
 // the device (no host round trip).  Segment s holds keys key0[s] .. key0[s+1]
 // of the level-1 output and global buckets g0[s] .. g0[s+1]; it has T[s]
 // level-2 tiles and D[s] sub-bins; its per-tile digit counts start at
-// cbase[s] and are laid out [digit][tile].
+// cbase[s] and are laid out [digit][tile].  The seven arrays (nseg + 1
+// entries each) live in device memory next to the header, which k_plan
+// fills in.  desc_by_seg: the segments are separate tables (batched build)
+// and segment s maps hashes to buckets with descriptor s; otherwise a key's
+// descriptor is its hash partition's.
 struct SegPlan {
   uint32_t nseg, total_tiles, total_counts, total_subbins;
   uint32_t num_buckets, n, tile_keys, log2S;
-  uint32_t key0[kMaxSeg + 1];
-  uint32_t g0[kMaxSeg + 1];
-  uint32_t D[kMaxSeg + 1];
-  uint32_t T[kMaxSeg + 1];
-  uint32_t tile_first[kMaxSeg + 1];
-  uint32_t cbase[kMaxSeg + 1];
-  uint32_t sb_first[kMaxSeg + 1];
+  uint32_t desc_by_seg, pad;
+  uint32_t* key0;
+  uint32_t* g0;
+  uint32_t* D;
+  uint32_t* T;
+  uint32_t* tile_first;
+  uint32_t* cbase;
+  uint32_t* sb_first;
 };
+constexpr uint32_t kPlanArrays = 7;
+constexpr uint32_t kMaxTables = 1u << 22;  // batched tables per call
+
+// Bytes of a plan with room for max_seg segments.
+inline size_t plan_bytes(uint32_t max_seg) {
+  return (sizeof(SegPlan) + 255) / 256 * 256 + sizeof(uint32_t) * kPlanArrays * (static_cast<size_t>(max_seg) + 1);
+}
 
 enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2 };
 enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1 };
@@ -91,12 +102,23 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
                               hipStream_t s);
 
-// Plan of the level-2 split from the scanned level-1 counts.  mode 0: the
-// level-1 digits are partitions (g0 = bucket_base); mode 1: coarse bucket
-// ranges of 2^sh1.  Writes offsets[num_buckets] = n when offsets is not null.
+// Plan of the level-2 split, written into `plan` (plan_bytes(nseg) bytes).
+// mode 0: segments are the level-1 partition digits (key0 from the scanned
+// level-1 counts scan1 [digit][tile], g0 = bucket_base); mode 1: coarse
+// bucket ranges of 2^sh1; mode 2: batched tables (key0 = seg_keys, g0 =
+// bucket_base, one descriptor per segment).  *nb_total is the number of
+// buckets.  Writes offsets[num_buckets] = n when offsets is not null.
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
-                       const uint32_t* bucket_base, uint32_t P, uint32_t sh1, uint32_t log2S, uint32_t tile2,
-                       uint32_t* offsets, SegPlan* plan, hipStream_t s);
+                       const uint32_t* bucket_base, const uint32_t* nb_total, const uint32_t* seg_keys, uint32_t sh1,
+                       uint32_t log2S, uint32_t tile2, uint32_t* offsets, SegPlan* plan, hipStream_t s);
+
+// Table layout of a batch of T tables with keys table_keys[t] ..
+// table_keys[t+1] (n keys in all): part_offsets[0..T] = the offsets clamped
+// to a non-decreasing sequence from 0 to n; with bucket_base not null also
+// V_t = max(1, floor(n_t * num / den)), bucket_base[0..T] and desc[0..T).
+// One workgroup.
+hipError_t launch_batch_layout(const uint32_t* table_keys, uint32_t T, uint32_t n, uint32_t num, uint32_t den,
+                               uint32_t* part_offsets, uint32_t* bucket_base, PartDesc* desc, hipStream_t s);
 
 // One workgroup per sub-bin: LDS counting sort of its keys by bucket; writes
 // the sub-bin's CSR offsets and keys.  grid = max_subbins.

@@ -120,12 +120,12 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
   __shared__ uint16_t sdig[kCount ? 1 : TILE];
 
   const uint32_t t = threadIdx.x;
-  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl;
+  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl, seg = 0;
   if (plan != nullptr) {
     const uint32_t G = plan->total_tiles;
     if (blockIdx.x >= G) return;  // whole workgroup
     const uint32_t b = xcd_tile(blockIdx.x, G);
-    const uint32_t seg = find_segment(plan->tile_first, plan->nseg, b);
+    seg = find_segment(plan->tile_first, plan->nseg, b);
     tl = b - plan->tile_first[seg];
     D = plan->D[seg];
     T = plan->T[seg];
@@ -140,8 +140,11 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
   const uint32_t tlen = min(static_cast<uint32_t>(TILE), k1 - tstart);
   const bool vec = tlen == static_cast<uint32_t>(TILE) && (reinterpret_cast<uintptr_t>(in + tstart) & 15) == 0;
 
-  if (DIG != DIG_PART)
-    for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+  if (DIG != DIG_PART) {
+    // A batched table's segment brings its own descriptor (P == 1 there).
+    const PartDesc* dsrc = (plan != nullptr && plan->desc_by_seg) ? desc + seg : desc;
+    for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
+  }
   for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
   __syncthreads();
 
@@ -236,39 +239,51 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
 }
 
 // out[i] = src[perm[i]] (u32 values), or (src[perm[i]] != 0) as bytes: the
-// inverse of a split applied to per-key values.  Four elements per thread.
+// inverse of a split applied to per-key values.  A workgroup takes 8192
+// consecutive elements, in XCD order like the split tiles: the values of
+// neighbouring split tiles sit side by side in every digit run, so the
+// workgroups reading them share each line in one L2.
+constexpr uint32_t kGatherThreads = 256, kGatherPer = 32, kGatherElems = kGatherThreads * kGatherPer;
+
 template <bool FOUND>
-__global__ __launch_bounds__(256) void k_perm_gather(const uint32_t* __restrict__ perm,
-                                                     const uint32_t* __restrict__ src, uint32_t n,
-                                                     void* __restrict__ out) {
-  const uint32_t i0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
-  if (i0 >= n) return;
-  if (i0 + 4 <= n) {
-    const uint4 p = *reinterpret_cast<const uint4*>(perm + i0);
-    const uint32_t a = src[p.x], b = src[p.y], c = src[p.z], e = src[p.w];
-    if (FOUND) {
-      uint8_t* o = static_cast<uint8_t*>(out) + i0;
-      const uint32_t packed = (a != 0 ? 1u : 0u) | (b != 0 ? 0x100u : 0u) | (c != 0 ? 0x10000u : 0u) |
-                              (e != 0 ? 0x1000000u : 0u);
-      if ((reinterpret_cast<uintptr_t>(o) & 3) == 0) {
-        *reinterpret_cast<uint32_t*>(o) = packed;
+__global__ __launch_bounds__(kGatherThreads) void k_perm_gather(const uint32_t* __restrict__ perm,
+                                                                const uint32_t* __restrict__ src, uint32_t n,
+                                                                void* __restrict__ out) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t base = xcd_tile(blockIdx.x, gridDim.x) * kGatherElems;
+  const uint32_t end = min(n, base + kGatherElems);
+  const bool aligned = FOUND ? (reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + base) & 3) == 0
+                             : (reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + base) & 15) == 0;
+  if (end - base == kGatherElems && aligned) {
+    // Round r covers elements base + r * 1024 + 4t .. + 3.
+    constexpr int R = kGatherPer / 4;
+    uint4 p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      p[r] = *reinterpret_cast<const uint4*>(perm + base + r * (kGatherThreads * 4) + 4 * t);
+    uint32_t v[kGatherPer];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[4 * r] = src[p[r].x];
+      v[4 * r + 1] = src[p[r].y];
+      v[4 * r + 2] = src[p[r].z];
+      v[4 * r + 3] = src[p[r].w];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = base + r * (kGatherThreads * 4) + 4 * t;
+      if (FOUND) {
+        const uint32_t packed = (v[4 * r] != 0 ? 1u : 0u) | (v[4 * r + 1] != 0 ? 0x100u : 0u) |
+                                (v[4 * r + 2] != 0 ? 0x10000u : 0u) | (v[4 * r + 3] != 0 ? 0x1000000u : 0u);
+        *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + i) = packed;
       } else {
-        for (int x = 0; x < 4; ++x) o[x] = static_cast<uint8_t>(packed >> (8 * x));
-      }
-    } else {
-      uint32_t* o = static_cast<uint32_t*>(out) + i0;
-      if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
-        *reinterpret_cast<uint4*>(o) = make_uint4(a, b, c, e);
-      } else {
-        o[0] = a;
-        o[1] = b;
-        o[2] = c;
-        o[3] = e;
+        *reinterpret_cast<uint4*>(static_cast<uint32_t*>(out) + i) =
+            make_uint4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
       }
     }
     return;
   }
-  for (uint32_t i = i0; i < n; ++i) {
+  for (uint32_t i = base + t; i < end; i += kGatherThreads) {
     const uint32_t x = src[perm[i]];
     if (FOUND)
       static_cast<uint8_t*>(out)[i] = x != 0 ? 1 : 0;
@@ -278,68 +293,169 @@ __global__ __launch_bounds__(256) void k_perm_gather(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ plan
-__global__ __launch_bounds__(kMaxSeg) void k_plan(const uint32_t* __restrict__ scan1, uint32_t tiles1,
-                                                  uint32_t nseg, uint32_t n, int mode,
-                                                  const uint32_t* __restrict__ bb, uint32_t P, uint32_t sh1,
-                                                  uint32_t log2S, uint32_t tile2, uint32_t* __restrict__ offsets,
-                                                  SegPlan* __restrict__ plan) {
-  __shared__ uint32_t wtot[kMaxSeg / kWave];
+constexpr int kPlanThreads = 1024;
+
+// One workgroup walks the segments in chunks of kPlanThreads, carrying the
+// three running prefix sums (tiles, counts, sub-bins) across chunks.
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restrict__ scan1, uint32_t tiles1,
+                                                       uint32_t nseg, uint32_t n, int mode,
+                                                       const uint32_t* __restrict__ bb,
+                                                       const uint32_t* __restrict__ nb_total,
+                                                       const uint32_t* __restrict__ seg_keys, uint32_t sh1,
+                                                       uint32_t log2S, uint32_t tile2, uint32_t* __restrict__ offsets,
+                                                       SegPlan* __restrict__ plan) {
+  __shared__ uint32_t wtot[kPlanThreads / kWave];
   const uint32_t t = threadIdx.x;
-  const uint32_t NB = bb[P];
-  uint32_t key0 = 0, g0 = 0, T = 0, D = 0;
-  if (t < nseg) {
-    key0 = tiles1 != 0 ? scan1[t * tiles1] : 0u;
-    const uint32_t key1 = (t + 1 < nseg) ? (tiles1 != 0 ? scan1[(t + 1) * tiles1] : 0u) : n;
-    uint32_t g1;
-    if (mode == 0) {
-      g0 = bb[t];
-      g1 = bb[t + 1];
-    } else {
-      g0 = static_cast<uint32_t>(min(static_cast<uint64_t>(t) << sh1, static_cast<uint64_t>(NB)));
-      g1 = (t + 1 < nseg) ? static_cast<uint32_t>(min(static_cast<uint64_t>(t + 1) << sh1, static_cast<uint64_t>(NB)))
-                          : NB;
+  const uint32_t NB = *nb_total;
+  uint32_t* arr = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(plan) + (sizeof(SegPlan) + 255) / 256 * 256);
+  const size_t stride = static_cast<size_t>(nseg) + 1;
+  uint32_t* key0a = arr;
+  uint32_t* g0a = arr + stride;
+  uint32_t* Da = arr + 2 * stride;
+  uint32_t* Ta = arr + 3 * stride;
+  uint32_t* tfa = arr + 4 * stride;
+  uint32_t* cba = arr + 5 * stride;
+  uint32_t* sba = arr + 6 * stride;
+  auto key_start = [&](uint32_t x) -> uint32_t {
+    if (x >= nseg) return n;
+    if (mode == 2) return seg_keys[x];
+    return tiles1 != 0 ? scan1[static_cast<size_t>(x) * tiles1] : 0u;
+  };
+  auto bucket_start = [&](uint32_t x) -> uint32_t {
+    if (x >= nseg) return NB;
+    if (mode == 1) return static_cast<uint32_t>(min(static_cast<uint64_t>(x) << sh1, static_cast<uint64_t>(NB)));
+    return bb[x];
+  };
+  uint32_t cT = 0, cC = 0, cD = 0;
+  for (uint32_t c0 = 0; c0 < nseg; c0 += kPlanThreads) {
+    const uint32_t x = c0 + t;
+    uint32_t key0 = 0, g0 = 0, T = 0, D = 0;
+    if (x < nseg) {
+      key0 = key_start(x);
+      g0 = bucket_start(x);
+      const uint32_t key1 = key_start(x + 1), g1 = bucket_start(x + 1);
+      T = (key1 - key0 + tile2 - 1) / tile2;
+      const uint64_t R = g1 - g0;
+      D = R == 0 ? 0u
+                 : static_cast<uint32_t>(min((R + (1ull << log2S) - 1) >> log2S, static_cast<uint64_t>(kMaxD2)));
     }
-    T = (key1 - key0 + tile2 - 1) / tile2;
-    const uint64_t R = g1 - g0;
-    D = R == 0 ? 0u : static_cast<uint32_t>(min((R + (1ull << log2S) - 1) >> log2S, static_cast<uint64_t>(kMaxD2)));
-  }
-  uint32_t tot_T, tot_C, tot_D;
-  const uint32_t tf = block_exclusive_sum<kMaxSeg>(T, wtot, tot_T);
-  const uint32_t cbv = block_exclusive_sum<kMaxSeg>(D * T, wtot, tot_C);
-  const uint32_t sbf = block_exclusive_sum<kMaxSeg>(D, wtot, tot_D);
-  if (t < nseg) {
-    plan->key0[t] = key0;
-    plan->g0[t] = g0;
-    plan->D[t] = D;
-    plan->T[t] = T;
-    plan->tile_first[t] = tf;
-    plan->cbase[t] = cbv;
-    plan->sb_first[t] = sbf;
+    uint32_t sT, sC, sD;
+    const uint32_t tf = block_exclusive_sum<kPlanThreads>(T, wtot, sT);
+    const uint32_t cbv = block_exclusive_sum<kPlanThreads>(D * T, wtot, sC);
+    const uint32_t sbf = block_exclusive_sum<kPlanThreads>(D, wtot, sD);
+    if (x < nseg) {
+      key0a[x] = key0;
+      g0a[x] = g0;
+      Da[x] = D;
+      Ta[x] = T;
+      tfa[x] = cT + tf;
+      cba[x] = cC + cbv;
+      sba[x] = cD + sbf;
+    }
+    cT += sT;
+    cC += sC;
+    cD += sD;
   }
   if (t == 0) {
-    plan->key0[nseg] = n;
-    plan->g0[nseg] = NB;
-    plan->D[nseg] = 0;
-    plan->T[nseg] = 0;
-    plan->tile_first[nseg] = tot_T;
-    plan->cbase[nseg] = tot_C;
-    plan->sb_first[nseg] = tot_D;
+    key0a[nseg] = n;
+    g0a[nseg] = NB;
+    Da[nseg] = 0;
+    Ta[nseg] = 0;
+    tfa[nseg] = cT;
+    cba[nseg] = cC;
+    sba[nseg] = cD;
     plan->nseg = nseg;
-    plan->total_tiles = tot_T;
-    plan->total_counts = tot_C;
-    plan->total_subbins = tot_D;
+    plan->total_tiles = cT;
+    plan->total_counts = cC;
+    plan->total_subbins = cD;
     plan->num_buckets = NB;
     plan->n = n;
     plan->tile_keys = tile2;
     plan->log2S = log2S;
+    plan->desc_by_seg = mode == 2 ? 1u : 0u;
+    plan->pad = 0;
+    plan->key0 = key0a;
+    plan->g0 = g0a;
+    plan->D = Da;
+    plan->T = Ta;
+    plan->tile_first = tfa;
+    plan->cbase = cba;
+    plan->sb_first = sba;
     if (offsets != nullptr) offsets[NB] = n;
   }
+}
+
+// Layout of a batch of tables (see launch_batch_layout).  Thread t owns the
+// contiguous entries [x0, x1) of the offsets 0..T and walks them three times:
+// (1) the largest clamped offset, then a max-scan over the threads in LDS;
+// (2) the sum of its tables' sizes V_x, then an exclusive sum over the
+// threads; (3) the clamped offsets, bucket bases and descriptors.  With
+// bb == nullptr only the clamped offsets are written.
+__global__ __launch_bounds__(kPlanThreads) void k_batch_layout(const uint32_t* __restrict__ tk, uint32_t T,
+                                                               uint32_t n, uint32_t num, uint32_t den,
+                                                               uint32_t* __restrict__ po, uint32_t* __restrict__ bb,
+                                                               PartDesc* __restrict__ desc) {
+  __shared__ uint32_t smax[kPlanThreads];
+  __shared__ uint32_t wtot[kPlanThreads / kWave];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (T + 1 + kPlanThreads - 1) / kPlanThreads;
+  const uint32_t x0 = min(T + 1, t * per), x1 = min(T + 1, x0 + per);
+  // Entry x clamped: 0 at x = 0, n at x = T, otherwise at most n.
+  auto val = [&](uint32_t x) -> uint32_t { return x == 0 ? 0u : (x == T ? n : min(tk[x], n)); };
+  uint32_t m = 0;
+  for (uint32_t x = x0; x < x1; ++x) m = max(m, val(x));
+  smax[t] = m;
+  __syncthreads();
+  for (uint32_t off = 1; off < kPlanThreads; off <<= 1) {
+    const uint32_t o = t >= off ? smax[t - off] : 0u;
+    __syncthreads();
+    smax[t] = max(smax[t], o);
+    __syncthreads();
+  }
+  const uint32_t before = t == 0 ? 0u : smax[t - 1];
+  const uint32_t xe = min(x1, T);  // tables owned: [x0, xe)
+  auto size_of = [&](uint32_t nt) -> uint32_t {
+    const uint64_t v = static_cast<uint64_t>(nt) * num / den;
+    return static_cast<uint32_t>(v < 1 ? 1 : v);
+  };
+  uint32_t sumV = 0;
+  if (bb != nullptr && x0 < xe) {
+    uint32_t cur = max(before, val(x0));
+    for (uint32_t x = x0; x < xe; ++x) {
+      const uint32_t nxt = max(cur, val(x + 1));
+      sumV += size_of(nxt - cur);
+      cur = nxt;
+    }
+  }
+  uint32_t total = 0;
+  uint32_t base = bb != nullptr ? block_exclusive_sum<kPlanThreads>(sumV, wtot, total) : 0u;
+  uint32_t cur = x0 < x1 ? max(before, val(x0)) : 0u;
+  for (uint32_t x = x0; x < x1; ++x) {
+    po[x] = cur;
+    if (bb != nullptr && x < T) {
+      const uint32_t nxt = max(cur, val(x + 1));
+      const uint32_t V = size_of(nxt - cur);
+      PartDesc pd;
+      pd.V = V;
+      pd.base = base;
+      pd.m32 = recip32(V);
+      pd.pad = 0;
+      pd.m64 = recip64(V);
+      desc[x] = pd;
+      bb[x] = base;
+      base += V;
+      cur = nxt;
+    } else if (x < T) {
+      cur = max(cur, val(x + 1));
+    }
+  }
+  if (bb != nullptr && t == 0) bb[T] = total;
 }
 
 // Sub-bin `b` of a plan: its segment, bucket range [gA, gB) and key range
 // [kA, kB) in the level-2 output (scan2 = scanned level-2 counts).
 struct SubBin {
-  uint32_t gA, gB, kA, kB;
+  uint32_t gA, gB, kA, kB, seg;
 };
 
 __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* scan2, uint32_t b) {
@@ -351,6 +467,7 @@ __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* s
   s.gB = (d + 1 == D) ? plan->g0[seg + 1] : s.gA + (1u << plan->log2S);
   s.kA = T != 0 ? scan2[plan->cbase[seg] + d * T] : plan->key0[seg];
   s.kB = (d + 1 < D) ? (T != 0 ? scan2[plan->cbase[seg] + (d + 1) * T] : plan->key0[seg]) : plan->key0[seg + 1];
+  s.seg = seg;
   return s;
 }
 
@@ -422,7 +539,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   if (blockIdx.x >= plan->total_subbins) return;  // whole workgroup
   const SubBin sb = sub_bin(plan, scan2, blockIdx.x);
   const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
-  for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+  {
+    const PartDesc* dsrc = plan->desc_by_seg ? desc + sb.seg : desc;
+    for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
+  }
 
   if (R <= kSMax && m <= 0xFFFFu) {
     for (uint32_t i = t; i < (R + 1) / 2; i += THREADS) lds[i] = 0;
@@ -582,7 +702,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
   const uint32_t Wb = 1u << log2W;
   const uint32_t nuns = unsorted[0];
-  for (uint32_t i = t; i < P; i += THREADS) sd[i] = desc[i];
+  {
+    const PartDesc* dsrc = qplan->desc_by_seg ? desc + sb.seg : desc;
+    for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
+  }
   __syncthreads();
 
   for (uint32_t c0 = 0; c0 < m; c0 += THREADS * REG) {  // one pass unless the sub-bin is oversized
@@ -886,18 +1009,25 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
                               hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint32_t blocks = div_up(n, 1024);
+  const uint32_t blocks = div_up(n, kGatherElems);
   if (found)
-    k_perm_gather<true><<<blocks, 256, 0, s>>>(perm, src, n, out);
+    k_perm_gather<true><<<blocks, kGatherThreads, 0, s>>>(perm, src, n, out);
   else
-    k_perm_gather<false><<<blocks, 256, 0, s>>>(perm, src, n, out);
+    k_perm_gather<false><<<blocks, kGatherThreads, 0, s>>>(perm, src, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
-                       const uint32_t* bucket_base, uint32_t P, uint32_t sh1, uint32_t log2S, uint32_t tile2,
-                       uint32_t* offsets, SegPlan* plan, hipStream_t s) {
-  k_plan<<<1, kMaxSeg, 0, s>>>(scan1, tiles1, nseg, n, mode, bucket_base, P, sh1, log2S, tile2, offsets, plan);
+                       const uint32_t* bucket_base, const uint32_t* nb_total, const uint32_t* seg_keys, uint32_t sh1,
+                       uint32_t log2S, uint32_t tile2, uint32_t* offsets, SegPlan* plan, hipStream_t s) {
+  k_plan<<<1, kPlanThreads, 0, s>>>(scan1, tiles1, nseg, n, mode, bucket_base, nb_total, seg_keys, sh1, log2S, tile2,
+                                    offsets, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_layout(const uint32_t* table_keys, uint32_t T, uint32_t n, uint32_t num, uint32_t den,
+                               uint32_t* part_offsets, uint32_t* bucket_base, PartDesc* desc, hipStream_t s) {
+  k_batch_layout<<<1, kPlanThreads, 0, s>>>(table_keys, T, n, num, den, part_offsets, bucket_base, desc);
   return hipGetLastError();
 }
 

@@ -43,13 +43,17 @@ def lib():
     L.hg_last_error.restype = ctypes.c_char_p
     L.hg_table_free.argtypes = [vp]
     L.hg_table_free.restype = None
+    L.hg_build_batched.argtypes = [vp, u64, i32, u32, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.hg_count_batched.argtypes = [vp, vp, u64, vp, vp, vp]
+    L.hg_query_batched.argtypes = [vp, vp, u64, vp, vp, vp]
     return L
 
 
 def test_header_declares_the_core_calls():
     fns = declared_functions()
     for name in ["hg_build", "hg_count", "hg_query", "hg_bin_partition", "hg_hash_bucket", "hg_table_info",
-                 "hg_table_export", "hg_table_free", "hg_status_string", "hg_last_error"]:
+                 "hg_table_export", "hg_table_free", "hg_status_string", "hg_last_error", "hg_build_batched",
+                 "hg_count_batched", "hg_query_batched"]:
         assert name in fns
 
 
@@ -127,3 +131,37 @@ def test_table_calls_reject_null(lib):
     assert lib.hg_table_info(None, FAKE) == HG_ERR_INVALID_ARG
     assert lib.hg_table_export(None, None, None, None, None, None) == HG_ERR_INVALID_ARG
     lib.hg_table_free(None)  # no-op
+
+
+def build_batched(lib, keys=FAKE, n=10, kt=0, T=3, offs=FAKE, P=1, num=1, den=1, V=0, flags=0, out=True,
+                  opts=True):
+    o = Opts(P, num, den, flags, V)
+    h = ctypes.c_void_p()
+    return lib.hg_build_batched(keys, n, kt, T, offs, ctypes.byref(o) if opts else None, None,
+                                ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("case, expected", [
+    (dict(T=0), HG_ERR_INVALID_ARG),                        # no tables
+    (dict(T=(1 << 22) + 1), HG_ERR_INVALID_ARG),            # too many tables
+    (dict(offs=None), HG_ERR_INVALID_ARG),                  # null offsets
+    (dict(keys=None), HG_ERR_INVALID_ARG),                  # null keys
+    (dict(n=1 << 32), HG_ERR_INVALID_ARG),
+    (dict(kt=5), HG_ERR_INVALID_ARG),
+    (dict(P=16), HG_ERR_INVALID_ARG),                       # partitions are the tables
+    (dict(V=100), HG_ERR_INVALID_ARG),                      # sizes come from the ratio
+    (dict(num=0), HG_ERR_INVALID_ARG),
+    (dict(flags=1), HG_ERR_UNSUPPORTED),                    # atomic build
+    (dict(flags=8), HG_ERR_INVALID_ARG),
+    (dict(n=(1 << 32) - 1, num=2), HG_ERR_INVALID_ARG),     # too many buckets
+    (dict(out=False), HG_ERR_INVALID_ARG),
+    (dict(opts=False), HG_ERR_INVALID_ARG),
+])
+def test_build_batched_rejects(lib, case, expected):
+    assert build_batched(lib, **case) == expected
+    assert lib.hg_last_error().decode() != ""
+
+
+def test_batched_probe_rejects(lib):
+    assert lib.hg_count_batched(None, FAKE, 10, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert lib.hg_query_batched(None, FAKE, 10, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
