@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the key count (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy 256 MiB once (device to device) so that a counter "
+                         "run of this command also measures a plain copy of known size")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -216,6 +219,13 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "kernels": kernels,
     }
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         log(f"cpu baseline on a sample of {args.cpu_sample}")
         result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
