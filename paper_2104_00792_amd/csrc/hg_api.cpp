@@ -308,6 +308,7 @@ struct SplitBufs {
   uint32_t tiles1;
   uint32_t max_tiles2;
   uint32_t max_counts2;
+  uint32_t max_subbins;
 };
 
 hg_status split_two_levels(const void* src, uint32_t n, hg_key_type kt, const SplitParams& sp, uint32_t log2P,
@@ -327,12 +328,13 @@ hg_status split_two_levels(const void* src, uint32_t n, hg_key_type kt, const Sp
   return HG_OK;
 }
 
-hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams& sp, uint32_t P, SplitBufs& w,
-                      uint64_t extra_scan) {
+hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams& sp, uint32_t P, uint64_t bound,
+                      SplitBufs& w, uint64_t extra_scan) {
   const size_t ks = key_bytes(kt);
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   w.tiles1 = hg::div_up(n, hg::kL1Tile);
   w.max_tiles2 = hg::div_up(n, tile2) + sp.nd1;
+  w.max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
   w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
                                                            0xFFFFFFFFull));
   const uint64_t len1 = static_cast<uint64_t>(std::max(sp.nd1, P)) * w.tiles1;
@@ -340,7 +342,7 @@ hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams
   void *c1 = nullptr, *bs = nullptr, *pl = nullptr, *c2 = nullptr, *b1 = nullptr, *b2 = nullptr;
   HG_TRY(mem.get(&c1, std::max<uint64_t>(len1, 1) * sizeof(uint32_t)), "allocate level-1 counts");
   HG_TRY(mem.get(&bs, (hg::div_up(scan_max, hg::kScanChunk) + 1) * sizeof(uint32_t)), "allocate scan workspace");
-  HG_TRY(mem.get(&pl, hg::plan_bytes(sp.nd1)), "allocate split plan");
+  HG_TRY(mem.get(&pl, hg::plan_bytes(sp.nd1, w.max_tiles2, w.max_subbins)), "allocate split plan");
   HG_TRY(mem.get(&c2, std::max<uint64_t>(w.max_counts2, 1) * sizeof(uint32_t)), "allocate level-2 counts");
   HG_TRY(mem.get(&b1, std::max<uint64_t>(n, 1) * ks), "allocate level-1 buffer");
   HG_TRY(mem.get(&b2, std::max<uint64_t>(n, 1) * ks), "allocate level-2 buffer");
@@ -359,10 +361,10 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
                        uint32_t* po, uint32_t* bb, hg::PartDesc* desc, uint32_t* offs, void* keys_out,
                        uint32_t* long_count, uint32_t* long_list, Allocs& mem, hipStream_t s) {
   SplitBufs w;
-  hg_status st = alloc_split(mem, n, kt, sp, P, w, 0);
+  hg_status st = alloc_split(mem, n, kt, sp, P, bound, w, 0);
   if (st != HG_OK) return st;
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
-  const uint32_t max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
+  const uint32_t max_subbins = w.max_subbins;
   if (sp.mode == 0) {
     HG_LAUNCH("split1_count", s,
               hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_PART, keys, n, 0, nullptr, P, log2P, P, nullptr, 0,
@@ -392,8 +394,8 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
               hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   }
   HG_LAUNCH("plan", s,
-            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, bb + P, nullptr, sp.sh1, sp.log2S, tile2, offs,
-                            w.plan, s));
+            hg::launch_plan(w.counts1, w.tiles1, sp.nd1, n, sp.mode, bb, bb + P, nullptr, sp.sh1, sp.log2S, tile2,
+                            w.max_tiles2, w.max_subbins, offs, w.plan, s));
   static const char* const kNames[4] = {"split1_scatter", "split2_count", "split2_scan", "split2_scatter"};
   st = split_two_levels(keys, n, kt, sp, log2P, P, desc, w, nullptr, nullptr, kNames, s);
   if (st != HG_OK) return st;
@@ -412,9 +414,15 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   sp.sh1 = t->sh1;
   sp.nd1 = t->nd1;
   sp.log2S = t->log2S;
+  // The queries' sub-bins may be narrower than the table's: at most one LDS
+  // window each (every query then hashes and is counted once), as long as a
+  // coarse range keeps at most kMaxD2 of them.
+  const uint32_t log2W = probe_log2W(kt, t->n, t->buckets_bound);
+  if (sp.mode == 1)
+    while (sp.log2S > log2W && sp.log2S > hg::kLog2SMin && sp.sh1 - (sp.log2S - 1) <= 10) --sp.log2S;
   Allocs mem(s);
   SplitBufs w;
-  hg_status st = alloc_split(mem, q, kt, sp, t->P, w, 0);
+  hg_status st = alloc_split(mem, q, kt, sp, t->P, t->buckets_bound, w, 0);
   if (st != HG_OK) return st;
   void *c2v = nullptr, *p1v = nullptr, *p2v = nullptr;
   HG_TRY(mem.get(&c2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate split-order counts");
@@ -422,7 +430,7 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   HG_TRY(mem.get(&p2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-2 permutation");
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
-  const uint32_t max_subbins = hg::div_up(t->buckets_bound, 1ull << sp.log2S) + sp.nd1;
+  const uint32_t max_subbins = w.max_subbins;
   HG_LAUNCH("qsplit1_count", s,
             hg::launch_msplit(kt, 1, hg::OP_COUNT, dig1, queries, q, 0, nullptr, sp.nd1, t->log2P, t->P, t->d_desc,
                               sp.sh1, w.counts1, nullptr, nullptr, s));
@@ -430,7 +438,7 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
             hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(sp.nd1) * w.tiles1, w.bsums, s));
   HG_LAUNCH("qplan", s,
             hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->d_bucket_base + t->P, nullptr,
-                            sp.sh1, sp.log2S, tile2, nullptr, w.plan, s));
+                            sp.sh1, sp.log2S, tile2, w.max_tiles2, w.max_subbins, nullptr, w.plan, s));
   uint32_t* c2 = static_cast<uint32_t*>(c2v);
   uint32_t* perm1 = static_cast<uint32_t*>(p1v);
   uint32_t* perm2 = static_cast<uint32_t*>(p2v);
@@ -439,7 +447,7 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   if (st != HG_OK) return st;
   HG_LAUNCH("lds_probe", s,
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, t->log2P, t->P, t->d_desc, t->d_offsets,
-                                 t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
+                                 t->d_keys, t->d_unsorted, log2W, c2, s));
   // The level-1 buffer is dead once the level-2 split has read it: it takes
   // the counts in level-1 order (q words fit in q keys).
   uint32_t* c1 = static_cast<uint32_t*>(w.buf1);
@@ -479,15 +487,18 @@ struct L2Bufs {
   void* buf2;
   uint32_t max_tiles2;
   uint32_t max_counts2;
+  uint32_t max_subbins;
 };
 
-hg_status alloc_l2(Allocs& mem, uint64_t n, hg_key_type kt, uint32_t nseg, L2Bufs& w) {
+hg_status alloc_l2(Allocs& mem, uint64_t n, hg_key_type kt, uint32_t nseg, uint64_t bound, uint32_t log2S,
+                   L2Bufs& w) {
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   w.max_tiles2 = hg::div_up(n, tile2) + nseg;
+  w.max_subbins = hg::div_up(bound, 1ull << log2S) + nseg;
   w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
                                                            0xFFFFFFFFull));
   void *pl = nullptr, *c2 = nullptr, *bs = nullptr, *b2 = nullptr;
-  HG_TRY(mem.get(&pl, hg::plan_bytes(nseg)), "allocate split plan");
+  HG_TRY(mem.get(&pl, hg::plan_bytes(nseg, w.max_tiles2, w.max_subbins)), "allocate split plan");
   HG_TRY(mem.get(&c2, std::max<uint64_t>(w.max_counts2, 1) * sizeof(uint32_t)), "allocate level-2 counts");
   HG_TRY(mem.get(&bs, (hg::div_up(w.max_counts2, hg::kScanChunk) + 1) * sizeof(uint32_t)), "allocate scan workspace");
   HG_TRY(mem.get(&b2, std::max<uint64_t>(n, 1) * key_bytes(kt)), "allocate level-2 buffer");
@@ -524,7 +535,7 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   const uint32_t T = t->P, q32 = static_cast<uint32_t>(q);
   Allocs mem(s);
   L2Bufs w;
-  hg_status st = alloc_l2(mem, q, kt, T, w);
+  hg_status st = alloc_l2(mem, q, kt, T, t->buckets_bound, t->log2S, w);
   if (st != HG_OK) return st;
   void *qov = nullptr, *pv = nullptr, *c2v = nullptr;
   HG_TRY(mem.get(&qov, (static_cast<uint64_t>(T) + 1) * sizeof(uint32_t)), "allocate query offsets");
@@ -537,11 +548,11 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   HG_LAUNCH("bq_offsets", s, hg::launch_batch_layout(d_qo, T, q32, 1, 1, qo, nullptr, nullptr, s));
   HG_LAUNCH("bq_plan", s,
             hg::launch_plan(nullptr, 0, T, q32, 2, t->d_bucket_base, t->d_bucket_base + T, qo, 0, t->log2S, tile2,
-                            nullptr, w.plan, s));
+                            w.max_tiles2, w.max_subbins, nullptr, w.plan, s));
   static const char* const kNames[3] = {"bqsplit_count", "bqsplit_scan", "bqsplit_scatter"};
   st = split_segments(d_queries, q32, kt, t->log2S, t->d_desc, w, perm, kNames, s);
   if (st != HG_OK) return st;
-  const uint32_t max_subbins = hg::div_up(t->buckets_bound, 1ull << t->log2S) + T;
+  const uint32_t max_subbins = w.max_subbins;
   HG_LAUNCH("blds_probe", s,
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, t->d_desc, t->d_offsets, t->d_keys,
                                  t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
@@ -743,15 +754,16 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
 
   const SplitParams sp = split_params(1, n, bound);  // sub-bin size from the batch's keys per bucket
   L2Bufs w;
-  st = alloc_l2(mem, n, kt, T, w);
+  st = alloc_l2(mem, n, kt, T, bound, sp.log2S, w);
   if (st != HG_OK) return st;
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   HG_LAUNCH("bplan", stream,
-            hg::launch_plan(nullptr, 0, T, n32, 2, bb, bb + T, po, 0, sp.log2S, tile2, offs, w.plan, stream));
+            hg::launch_plan(nullptr, 0, T, n32, 2, bb, bb + T, po, 0, sp.log2S, tile2, w.max_tiles2, w.max_subbins,
+                            offs, w.plan, stream));
   static const char* const kNames[3] = {"bsplit_count", "bsplit_scan", "bsplit_scatter"};
   st = split_segments(d_keys, n32, kt, sp.log2S, desc, w, nullptr, kNames, stream);
   if (st != HG_OK) return st;
-  const uint32_t max_subbins = hg::div_up(bound, 1ull << sp.log2S) + T;
+  const uint32_t max_subbins = w.max_subbins;
   HG_LAUNCH("blds_build", stream,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, desc, offs, keys_out, long_ctr,
                                  long_list, stream));

@@ -59,15 +59,16 @@ inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 16 : 8); }
 // the device (no host round trip).  Segment s holds keys key0[s] .. key0[s+1]
 // of the level-1 output and global buckets g0[s] .. g0[s+1]; it has T[s]
 // level-2 tiles and D[s] sub-bins; its per-tile digit counts start at
-// cbase[s] and are laid out [digit][tile].  The seven arrays (nseg + 1
-// entries each) live in device memory next to the header, which k_plan
-// fills in.  desc_by_seg: the segments are separate tables (batched build)
-// and segment s maps hashes to buckets with descriptor s; otherwise a key's
-// descriptor is its hash partition's.
+// cbase[s] and are laid out [digit][tile].  tile_seg[b] / sb_seg[b] name
+// the segment of level-2 tile b / sub-bin b.  The arrays live in device
+// memory after the header, which the plan kernels fill in.  desc_by_seg: the
+// segments are separate tables (batched build) and segment s maps hashes to
+// buckets with descriptor s; otherwise a key's descriptor is its hash
+// partition's.
 struct SegPlan {
   uint32_t nseg, total_tiles, total_counts, total_subbins;
   uint32_t num_buckets, n, tile_keys, log2S;
-  uint32_t desc_by_seg, pad;
+  uint32_t desc_by_seg, max_tiles, max_subbins, pad;
   uint32_t* key0;
   uint32_t* g0;
   uint32_t* D;
@@ -75,13 +76,17 @@ struct SegPlan {
   uint32_t* tile_first;
   uint32_t* cbase;
   uint32_t* sb_first;
+  uint32_t* tile_seg;
+  uint32_t* sb_seg;
 };
 constexpr uint32_t kPlanArrays = 7;
 constexpr uint32_t kMaxTables = 1u << 22;  // batched tables per call
 
-// Bytes of a plan with room for max_seg segments.
-inline size_t plan_bytes(uint32_t max_seg) {
-  return (sizeof(SegPlan) + 255) / 256 * 256 + sizeof(uint32_t) * kPlanArrays * (static_cast<size_t>(max_seg) + 1);
+// Bytes of a plan with room for max_seg segments, max_tiles level-2 tiles
+// and max_subbins sub-bins.
+inline size_t plan_bytes(uint32_t max_seg, uint32_t max_tiles, uint32_t max_subbins) {
+  return (sizeof(SegPlan) + 255) / 256 * 256 +
+         sizeof(uint32_t) * (kPlanArrays * (static_cast<size_t>(max_seg) + 1) + max_tiles + max_subbins);
 }
 
 enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2 };
@@ -102,7 +107,9 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
                               hipStream_t s);
 
-// Plan of the level-2 split, written into `plan` (plan_bytes(nseg) bytes).
+// Plan of the level-2 split, written into `plan` (plan_bytes(nseg,
+// max_tiles, max_subbins) bytes; the level-2 grid is max_tiles, the sub-bin
+// grid max_subbins).
 // mode 0: segments are the level-1 partition digits (key0 from the scanned
 // level-1 counts scan1 [digit][tile], g0 = bucket_base); mode 1: coarse
 // bucket ranges of 2^sh1; mode 2: batched tables (key0 = seg_keys, g0 =
@@ -110,7 +117,8 @@ hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_
 // buckets.  Writes offsets[num_buckets] = n when offsets is not null.
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
                        const uint32_t* bucket_base, const uint32_t* nb_total, const uint32_t* seg_keys, uint32_t sh1,
-                       uint32_t log2S, uint32_t tile2, uint32_t* offsets, SegPlan* plan, hipStream_t s);
+                       uint32_t log2S, uint32_t tile2, uint32_t max_tiles, uint32_t max_subbins, uint32_t* offsets,
+                       SegPlan* plan, hipStream_t s);
 
 // Table layout of a batch of T tables with keys table_keys[t] ..
 // table_keys[t+1] (n keys in all): part_offsets[0..T] = the offsets clamped

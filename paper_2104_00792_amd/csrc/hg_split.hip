@@ -125,7 +125,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
     const uint32_t G = plan->total_tiles;
     if (blockIdx.x >= G) return;  // whole workgroup
     const uint32_t b = xcd_tile(blockIdx.x, G);
-    seg = find_segment(plan->tile_first, plan->nseg, b);
+    seg = plan->tile_seg[b];
     tl = b - plan->tile_first[seg];
     D = plan->D[seg];
     T = plan->T[seg];
@@ -302,7 +302,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
                                                        const uint32_t* __restrict__ bb,
                                                        const uint32_t* __restrict__ nb_total,
                                                        const uint32_t* __restrict__ seg_keys, uint32_t sh1,
-                                                       uint32_t log2S, uint32_t tile2, uint32_t* __restrict__ offsets,
+                                                       uint32_t log2S, uint32_t tile2, uint32_t max_tiles,
+                                                       uint32_t max_subbins, uint32_t* __restrict__ offsets,
                                                        SegPlan* __restrict__ plan) {
   __shared__ uint32_t wtot[kPlanThreads / kWave];
   const uint32_t t = threadIdx.x;
@@ -373,7 +374,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
     plan->tile_keys = tile2;
     plan->log2S = log2S;
     plan->desc_by_seg = mode == 2 ? 1u : 0u;
+    plan->max_tiles = max_tiles;
+    plan->max_subbins = max_subbins;
     plan->pad = 0;
+    plan->tile_seg = arr + kPlanArrays * stride;
+    plan->sb_seg = arr + kPlanArrays * stride + max_tiles;
     plan->key0 = key0a;
     plan->g0 = g0a;
     plan->D = Da;
@@ -383,6 +388,16 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
     plan->sb_first = sba;
     if (offsets != nullptr) offsets[NB] = n;
   }
+}
+
+// tile_seg / sb_seg: the segment of every level-2 tile and sub-bin (one
+// binary search per entry, all in parallel, instead of one per workgroup in
+// every later pass).  Entries past the totals are left unwritten.
+__global__ __launch_bounds__(256) void k_seg_map(const SegPlan* __restrict__ plan) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t nt = plan->total_tiles, ns = plan->total_subbins;
+  if (i < nt) plan->tile_seg[i] = find_segment(plan->tile_first, plan->nseg, i);
+  if (i < ns) plan->sb_seg[i] = find_segment(plan->sb_first, plan->nseg, i);
 }
 
 // Layout of a batch of tables (see launch_batch_layout).  Thread t owns the
@@ -459,7 +474,7 @@ struct SubBin {
 };
 
 __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* scan2, uint32_t b) {
-  const uint32_t seg = find_segment(plan->sb_first, plan->nseg, b);
+  const uint32_t seg = plan->sb_seg[b];
   const uint32_t d = b - plan->sb_first[seg];
   const uint32_t D = plan->D[seg], T = plan->T[seg];
   SubBin s;
@@ -549,16 +564,21 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     __syncthreads();
     const bool regs = m <= static_cast<uint32_t>(THREADS * REG);
     K v[REG];
+    // Two 16-bit values per word: first each key's bucket in the sub-bin
+    // (R <= 2^15), then its position (m <= 65535).
     uint32_t pos[(REG + 1) / 2];
     if (regs) {
 #pragma unroll
       for (int j = 0; j < REG; ++j) {
         const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+        v[j] = K(0);
+        uint32_t lb = 0;
         if (e < m) {
           v[j] = in[sb.kA + e];
-          const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
+          lb = bucket_of(v[j], log2P, sd) - sb.gA;
           atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
         }
+        if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
       }
     } else {
       for (uint32_t e = t; e < m; e += THREADS) {
@@ -588,12 +608,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+      const uint32_t lb = (pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu, sh = (lb & 1u) << 4;
       uint32_t p = 0;
-      if (e < m) {
-        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA, sh = (lb & 1u) << 4;
-        p = (atomicAdd(&lds[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
-      }
-      if (j & 1) pos[j >> 1] |= p << 16; else pos[j >> 1] = p;
+      if (e < m) p = (atomicAdd(&lds[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
+      pos[j >> 1] = (pos[j >> 1] & ~(0xFFFFu << ((j & 1) << 4))) | (p << ((j & 1) << 4));
     }
     __syncthreads();  // every position is known: the counters are dead
     K* stage = reinterpret_cast<K*>(lds);
@@ -707,6 +725,39 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
     for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
   }
   __syncthreads();
+
+  if (R <= Wb) {
+    // The whole sub-bin is one window: load it, then stream the queries
+    // through it (kU loads in flight per thread), each counted and written
+    // once.
+    copy_to_lds<THREADS, 8>(soff, offsets + sb.gA, R + 1);
+    __syncthreads();
+    const uint32_t ka = soff[0], nk = soff[R] - ka;
+    const bool in_lds = nk <= KCAP;
+    if (in_lds) copy_to_lds<THREADS, 8>(skeys, tkeys + ka, nk);
+    __syncthreads();
+    constexpr int kU = 8;
+    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
+      K qv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        qv[u] = e < m ? q2[sb.kA + e] : K(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        if (e < m) {
+          const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
+          const uint32_t lo = soff[lb], hi = soff[lb + 1];
+          const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
+          c2[sb.kA + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
+                                 : count_equal(tkeys, lo, hi, qv[u], srt);
+        }
+      }
+    }
+    return;
+  }
 
   for (uint32_t c0 = 0; c0 < m; c0 += THREADS * REG) {  // one pass unless the sub-bin is oversized
     K qv[REG];
@@ -1019,9 +1070,14 @@ hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
                        const uint32_t* bucket_base, const uint32_t* nb_total, const uint32_t* seg_keys, uint32_t sh1,
-                       uint32_t log2S, uint32_t tile2, uint32_t* offsets, SegPlan* plan, hipStream_t s) {
+                       uint32_t log2S, uint32_t tile2, uint32_t max_tiles, uint32_t max_subbins, uint32_t* offsets,
+                       SegPlan* plan, hipStream_t s) {
   k_plan<<<1, kPlanThreads, 0, s>>>(scan1, tiles1, nseg, n, mode, bucket_base, nb_total, seg_keys, sh1, log2S, tile2,
-                                    offsets, plan);
+                                    max_tiles, max_subbins, offsets, plan);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t m = max_tiles > max_subbins ? max_tiles : max_subbins;
+  if (m > 0) k_seg_map<<<div_up(m, 256), 256, 0, s>>>(plan);
   return hipGetLastError();
 }
 
