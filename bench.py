@@ -34,6 +34,12 @@ DESCRIPTIONS = {
     "plain_u32_2^28": "n=2^28 uint32 keys uniform; plain table V=n; 2^28 queries at 50% hit",
     "plain_u32_2^20": "n=2^20 uint32 keys uniform; plain table V=n; 2^20 queries at 50% hit",
     "zipf_u64_2^27": "n=2^27 uint64 keys Zipf(1.0) over 2^20 values; fmix64; V=n/2; 2^27 Zipf queries",
+    "batched_u32_4096": "4096 uint32 tables, sizes log-uniform in [2^10, 2^20] (622M keys), per-table seeds, "
+                        "V_t = n_t; each probed by n_t queries at 50% hit; one hg_build_batched + "
+                        "hg_count_batched per step",
+    "serving": "Poisson stream of requests, 30% builds (uint32, sizes log-uniform in [2^10, 2^24]) and 70% probes "
+               "(sizes log-uniform in [2^8, 2^22], 50% hits) against earlier tables; 200 GB HBM cap with LRU "
+               "eviction; 4 concurrent slots; open loop at 0.8 of the closed-loop capacity",
 }
 
 
@@ -74,6 +80,14 @@ def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> f
         "lds_probe": ks * q + 4 * B + ks * n + 4 * q,  # queries, offsets, table keys, counts out
         "qgather2": 12 * q,                         # permutation, counts in, counts out
         "qgather1": 12 * q,
+        # batched tables
+        "bsplit_count": ks * n,
+        "bsplit_scatter": 2 * ks * n,
+        "blds_build": 2 * ks * n + 4 * B,
+        "bqsplit_count": ks * q,
+        "bqsplit_scatter": (2 * ks + 4) * q,
+        "blds_probe": ks * q + 4 * B + ks * n + 4 * q,
+        "bqgather": 12 * q,
         # atomic path and direct probe
         "zero_counts": 4 * (B + 1),                 # counters written
         "bucket_hist": ks * n + 4 * B,              # keys in, counters out once
@@ -130,6 +144,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the key count (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    ap.add_argument("--requests", type=int, default=100000, help="serving: requests in the stream")
+    ap.add_argument("--tables", type=int, default=4096, help="batched: number of tables")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 256 MiB once (device to device) so that a counter "
                          "run of this command also measures a plain copy of known size")
@@ -151,6 +167,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hg.lib()
+    if args.workload == "batched_u32_4096":
+        return run_batched(args, dev)
+    if args.workload == "serving":
+        return run_serving(args, dev)
 
     w = inputs.WORKLOADS[args.workload]
     n = w["n"] if args.n is None else args.n
@@ -229,6 +249,129 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline on a sample of {args.cpu_sample}")
         result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+def roofline_of(kernels: dict, sizes: dict, workload: str) -> dict:
+    """Roofline entry of the kernel with the most time per step among those
+    with algorithmic bytes."""
+    dom = max((k for k in kernels if algorithmic_bytes(k, **sizes) > 0), key=lambda k: kernels[k]["ms_per_step"])
+    achieved = algorithmic_bytes(dom, **sizes) / (kernels[dom]["avg_ms"] / 1000.0) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(workload, dom)}
+
+
+def kernel_table(prof_results: dict, steps: int, sizes: dict) -> dict:
+    out = {}
+    for name, (launches, total_ms) in prof_results.items():
+        avg = total_ms / launches
+        ab = algorithmic_bytes(name, **sizes)
+        out[name] = {"launches_per_step": launches // steps, "avg_ms": round(avg, 5),
+                     "ms_per_step": round(total_ms / steps, 5),
+                     "alg_GBs": round(ab / (avg / 1000.0) / 1e9, 1) if avg > 0 and ab else None}
+    return out
+
+
+def timed(fn, steps: int, warmup: int):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_batched(args, dev):
+    """4096 tables built and probed in one call each, against the same keys
+    as one plain table and against one hg_build + hg_count per table."""
+    import numpy as np
+    import torch
+
+    import paper_2104_00792_amd as hg
+    from paper_2104_00792_amd import inputs
+
+    sizes = inputs.batch_sizes(args.tables)
+    total = int(sizes.sum())
+    log(f"generating {args.tables} tables, {total} keys")
+    keys = inputs.batch_keys_t(sizes, dev)
+    queries = inputs.batch_queries_t(keys, sizes, sizes, dev)
+    koff = torch.from_numpy(inputs.segment_offsets(sizes)).to(dev)
+    counts = torch.empty(total, dtype=torch.uint32, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        t = hg.hg_build_batched(keys, koff)
+        hg.hg_count_batched(t, queries, koff, out=counts)
+        t.free()
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    t = hg.hg_build_batched(keys, koff)
+    B = t.info()["num_buckets"]
+    t.free()
+    log(f"timing {args.steps} steps")
+    with hg.profile() as prof:
+        sec = timed(step, args.steps, 0)
+    sz = dict(n=total, q=total, B=B, ks=4, P=1)
+    kernels = kernel_table(prof.results, args.steps, sz)
+
+    def plain():
+        t1 = hg.hg_build(keys)
+        hg.hg_count(t1, queries, out=counts)
+        t1.free()
+
+    log("plain single table over the same keys")
+    sec_plain = timed(plain, max(1, args.steps // 2), 1)
+    o = inputs.segment_offsets(sizes).astype(np.int64)
+
+    def loop():
+        for i in range(args.tables):
+            a, b = int(o[i]), int(o[i + 1])
+            t1 = hg.hg_build(keys[a:b])
+            hg.hg_count(t1, queries[a:b], out=counts[a:b])
+            t1.free()
+
+    log("one build + count per table")
+    sec_loop = timed(loop, 1, 1)
+    result = {
+        "metric": "batched build+probe keys/s (4096 tables of 2^10..2^20 keys)",
+        "value": total / sec, "unit": "keys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1000.0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched_u32_4096: {DESCRIPTIONS['batched_u32_4096']}", "tables": args.tables,
+                   "keys": total, "queries": total, "num_buckets": B},
+        "vs_plain_path": {"single_table_same_keys_keys_per_s": total / sec_plain,
+                          "one_call_per_table_keys_per_s": total / sec_loop,
+                          "speedup_over_one_call_per_table": sec_loop / sec},
+        "roofline": roofline_of(kernels, sz, "batched_u32_4096"),
+        "kernels": kernels,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def run_serving(args, dev):
+    """Closed loop (every request present at t = 0) for capacity, then the
+    open-loop Poisson stream at 0.8 of it; latencies from arrival to
+    completion."""
+    from paper_2104_00792_amd import serve
+
+    log(f"serving {args.requests} requests")
+    closed, opened, _ = serve.run_serving(num=args.requests, slots=4, capacity_bytes=200 * 10**9, load=0.8,
+                                          progress=lambda m: log(m))
+    result = {
+        "metric": "serving p50/p99 latency and throughput (open loop at 0.8 of capacity)",
+        "value": opened["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": opened["wall_s"] * 1000.0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"serving: {DESCRIPTIONS['serving']}", "requests": args.requests},
+        "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
+        "open_loop": opened, "closed_loop": closed,
+    }
     print(json.dumps(result), flush=True)
 
 

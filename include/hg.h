@@ -76,8 +76,8 @@ typedef struct hg_build_opts {
 
 /* Build strategies (same table, different kernels).  ATOMIC: histogram and
  * scatter with global atomics, as written in Algorithm 1 (fast while the
- * counters fit in cache).  SORTED: two stable splits down to sub-bins of
- * 2^15 buckets, then histogram, scan and scatter inside LDS (the paper's
+ * counters fit in cache).  SORTED: two splits down to sub-bins of at most
+ * 2^13 buckets, then histogram, scan and scatter inside LDS (the paper's
  * local binning of Sec. 3.2 carried down to LDS size). */
 #define HG_BUILD_ATOMIC 1u
 #define HG_BUILD_SORTED 2u

@@ -234,6 +234,13 @@ uint32_t ceil_log2(uint64_t x) {
   return l;
 }
 
+// Level-2 tiles of n keys in nseg segments: a segment of n_s keys whose
+// tiles start up to kTileAlign - 1 keys early has at most
+// (n_s + kTileAlign - 2) / tile + 1 of them.
+uint32_t max_l2_tiles(uint64_t n, uint32_t tile, uint32_t nseg) {
+  return hg::div_up(n + static_cast<uint64_t>(hg::kTileAlign - 2) * nseg, tile) + nseg;
+}
+
 struct SplitParams {
   int mode;        // 0: partitions, 1: coarse bucket ranges
   uint32_t sh1;    // mode 1: 2^sh1 buckets per range
@@ -242,18 +249,18 @@ struct SplitParams {
 };
 
 // Level-2 digits per segment: at most 2^L2 (L2 in 7..10, HG_SPLIT_L2_BITS,
-// default 7).  Fewer level-2 digits make the level-2 ranking cheaper and its
+// default 8).  Fewer level-2 digits make the level-2 ranking cheaper and its
 // runs longer at the price of more level-1 digits.
 uint32_t split_l2_bits() {
   static const uint32_t bits = [] {
     const char* v = std::getenv("HG_SPLIT_L2_BITS");
-    const long b = v ? std::strtol(v, nullptr, 10) : 7;
+    const long b = v ? std::strtol(v, nullptr, 10) : 8;
     return static_cast<uint32_t>(b < 7 ? 7 : (b > 10 ? 10 : b));
   }();
   return bits;
 }
 
-// Sub-bins of about 2^14 keys (log2S shrinks as keys per bucket grow).
+// Sub-bins of about 2^13 keys (log2S shrinks as keys per bucket grow).
 // Level-1 digits by partition when an average partition's table fits 2^L2
 // sub-bins (the last of which may grow to 2^kLog2SLds buckets in LDS);
 // otherwise by coarse bucket ranges of 2^L2 sub-bins each (at most 256
@@ -333,7 +340,7 @@ hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams
   const size_t ks = key_bytes(kt);
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   w.tiles1 = hg::div_up(n, hg::kL1Tile);
-  w.max_tiles2 = hg::div_up(n, tile2) + sp.nd1;
+  w.max_tiles2 = max_l2_tiles(n, tile2, sp.nd1);
   w.max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
   w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
                                                            0xFFFFFFFFull));
@@ -445,9 +452,11 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   static const char* const kNames[4] = {"qsplit1_scatter", "qsplit2_count", "qsplit2_scan", "qsplit2_scatter"};
   st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, w, perm1, perm2, kNames, s);
   if (st != HG_OK) return st;
+  void* qv = nullptr;
+  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys() + 1)) * sizeof(uint32_t)), "allocate probe queue");
   HG_LAUNCH("lds_probe", s,
-            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, t->log2P, t->P, t->d_desc, t->d_offsets,
-                                 t->d_keys, t->d_unsorted, log2W, c2, s));
+            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q, t->log2P, t->P, t->d_desc,
+                                 t->d_offsets, t->d_keys, t->d_unsorted, log2W, static_cast<uint32_t*>(qv), c2, s));
   // The level-1 buffer is dead once the level-2 split has read it: it takes
   // the counts in level-1 order (q words fit in q keys).
   uint32_t* c1 = static_cast<uint32_t*>(w.buf1);
@@ -493,7 +502,7 @@ struct L2Bufs {
 hg_status alloc_l2(Allocs& mem, uint64_t n, hg_key_type kt, uint32_t nseg, uint64_t bound, uint32_t log2S,
                    L2Bufs& w) {
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
-  w.max_tiles2 = hg::div_up(n, tile2) + nseg;
+  w.max_tiles2 = max_l2_tiles(n, tile2, nseg);
   w.max_subbins = hg::div_up(bound, 1ull << log2S) + nseg;
   w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
                                                            0xFFFFFFFFull));
@@ -553,9 +562,12 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   st = split_segments(d_queries, q32, kt, t->log2S, t->d_desc, w, perm, kNames, s);
   if (st != HG_OK) return st;
   const uint32_t max_subbins = w.max_subbins;
+  void* qv = nullptr;
+  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys() + 1)) * sizeof(uint32_t)), "allocate probe queue");
   HG_LAUNCH("blds_probe", s,
-            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, t->d_desc, t->d_offsets, t->d_keys,
-                                 t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound), c2, s));
+            hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q32, 0, 1, t->d_desc, t->d_offsets,
+                                 t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound),
+                                 static_cast<uint32_t*>(qv), c2, s));
   HG_LAUNCH("bqgather", s, hg::launch_perm_gather(perm, c2, q32, d_out, !count, s));
   return HG_OK;
 }

@@ -24,14 +24,15 @@ inline uint32_t div_up(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a
 // level-1 segment (<= kMaxD2 digits, kL2Threads x 16 (32-bit) or x 8 (64-bit)
 // key tiles).  The LDS stages then sort (build) or probe one sub-bin per
 // workgroup.
-constexpr uint32_t kLog2SMax = 14;  // regular sub-bins: 2^log2S <= 2^14 buckets
+constexpr uint32_t kLog2SMax = 13;  // regular sub-bins: 2^log2S <= 2^13 buckets
 constexpr uint32_t kLog2SMin = 10;
-constexpr uint32_t kLog2SLds = 15;  // a segment's last sub-bin may grow to 2^15 in LDS
+constexpr uint32_t kLog2SLds = 14;  // a segment's last sub-bin may grow to 2^14 in LDS
 constexpr uint32_t kMaxD2 = 1024;
 constexpr int kL1Threads = 256;
 constexpr int kL1Tile = kL1Threads * 16;
 constexpr int kL2Threads = 512;
-constexpr int kLdsThreads = 1024;
+constexpr int kLdsThreads = 1024;      // LDS probe workgroup
+constexpr int kBuildThreads = 512;     // LDS build workgroup
 constexpr uint32_t kMaxLog2W = 13;  // probe window: at most 2^13 buckets in LDS
 constexpr uint32_t kProbeKeyCapBytes = 40 * 1024;  // table keys of one window in LDS
 
@@ -54,6 +55,9 @@ hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* lon
                             uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s);
 
 inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 16 : 8); }
+// Level-2 tiles of a segment start at its first key rounded down to this
+// many keys (16 bytes or more), so interior tiles take vector loads.
+constexpr uint32_t kTileAlign = 4;
 
 // Segments of the level-2 split and sub-bins of the LDS stages, computed on
 // the device (no host round trip).  Segment s holds keys key0[s] .. key0[s+1]
@@ -134,12 +138,16 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
                             uint32_t* long_count, uint32_t* long_list, hipStream_t s);
 
-// One workgroup per sub-bin of queries: windows of 2^log2W buckets of the
-// table (offsets and keys) in LDS; counts in the split order.
+// Queries of one sub-bin, at most probe_chunk_keys() per workgroup (a
+// sub-bin with more is shared through a queue): windows of 2^log2W buckets
+// of the table (offsets and keys) in LDS; counts in the split order.
+// Workspace: queue[1 + 2 * (q / probe_chunk_keys() + 1)].
+constexpr int kProbeReg = 20;
+uint32_t probe_chunk_keys();
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
-                            uint32_t max_subbins, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                            uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
-                            uint32_t* c2, hipStream_t s);
+                            uint32_t* queue, uint32_t* c2, hipStream_t s);
 
 // kt: 0 = 32-bit keys, 1 = 64-bit keys.
 hipError_t launch_fill_u32(uint32_t* p, uint64_t len, uint32_t value, hipStream_t s);

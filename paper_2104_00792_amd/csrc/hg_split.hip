@@ -6,7 +6,7 @@
 // same result is reached with streaming passes only:
 //   level-1 split  by partition (Algorithm 2, Phase 2) or by coarse bucket
 //                  range: per-tile counts + scan + scatter;
-//   level-2 split  by sub-bin of up to 2^14 buckets inside each level-1
+//   level-2 split  by sub-bin of up to 2^13 buckets inside each level-1
 //                  segment (the paper's second, local binning for cache
 //                  locality, Sec. 3.2, sized here for the LDS of a CU);
 //   LDS build      one workgroup per sub-bin: histogram, exclusive scan and
@@ -52,13 +52,16 @@ __device__ __forceinline__ uint32_t elem_of(bool vec, int i, uint32_t t) {
              : static_cast<uint32_t>(i) * THREADS + t;
 }
 
+// Loads the keys of a tile: elements base + e for head <= e < tail.  With
+// `vec` (a whole tile at a 16-byte aligned base) thread t reads kVec
+// consecutive keys per load.  Items outside the tile hold key 0.
 template <typename K, int THREADS, int ITEMS>
-__device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_t tstart, uint32_t tlen, bool vec,
-                                               K (&v)[ITEMS]) {
+__device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_t base, uint32_t head, uint32_t tail,
+                                               bool vec, K (&v)[ITEMS]) {
   constexpr int kVec = 16 / sizeof(K);
   const uint32_t t = threadIdx.x;
   if (vec) {
-    const uint4* p = reinterpret_cast<const uint4*>(in + tstart);
+    const uint4* p = reinterpret_cast<const uint4*>(in + base);
 #pragma unroll
     for (int j = 0; j < ITEMS / kVec; ++j) {
       const uint4 x = p[j * THREADS + t];
@@ -73,9 +76,9 @@ __device__ __forceinline__ uint32_t load_items(const K* __restrict__ in, uint32_
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t e = static_cast<uint32_t>(i) * THREADS + t;
-    v[i] = K(0);  // items past the tail hold a harmless key
-    if (e < tlen) {
-      v[i] = in[tstart + e];
+    v[i] = K(0);  // items past the tile hold a harmless key
+    if (e >= head && e < tail) {
+      v[i] = in[base + e];
       mask |= 1u << i;
     }
   }
@@ -136,9 +139,15 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
   } else {
     tl = xcd_tile(blockIdx.x, gridDim.x);
   }
-  const uint32_t tstart = k0 + tl * TILE;
-  const uint32_t tlen = min(static_cast<uint32_t>(TILE), k1 - tstart);
-  const bool vec = tlen == static_cast<uint32_t>(TILE) && (reinterpret_cast<uintptr_t>(in + tstart) & 15) == 0;
+  // The tiles of a segment start at its first key rounded down to
+  // kTileAlign keys, so that every interior tile takes 16-byte loads; the
+  // first and last tiles mask what lies outside the segment.
+  const uint32_t base = (k0 & ~(kTileAlign - 1)) + tl * TILE;
+  const uint32_t head = base < k0 ? k0 - base : 0u;
+  const uint32_t tail = min(static_cast<uint32_t>(TILE), k1 - base);
+  const uint32_t cnt = tail - head;  // keys of this tile
+  const bool vec = head == 0 && tail == static_cast<uint32_t>(TILE) &&
+                   (reinterpret_cast<uintptr_t>(in + base) & 15) == 0;
 
   if (DIG != DIG_PART) {
     // A batched table's segment brings its own descriptor (P == 1 there).
@@ -154,7 +163,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
   // them as whole vectors through every branch.
   K v[ITEMS];
   uint32_t d[ITEMS];
-  const uint32_t mask = load_items<K, THREADS, ITEMS>(in, tstart, tlen, vec, v);
+  const uint32_t mask = load_items<K, THREADS, ITEMS>(in, base, head, tail, vec, v);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     if (DIG == DIG_PART) {
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
       // kVec consecutive keys per thread and load: one 16- or 8-byte store.
 #pragma unroll
       for (int i = 0; i < ITEMS; i += kVec) {
-        uint32_t* dst = perm + tstart + elem_of<K, THREADS>(true, i, t);
+        uint32_t* dst = perm + base + elem_of<K, THREADS>(true, i, t);
         if (kVec == 4)
           *reinterpret_cast<uint4*>(dst) = make_uint4(d[i], d[i + 1], d[i + 2], d[i + 3]);
         else
@@ -227,14 +236,14 @@ __global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in,
     } else {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i)
-        if ((mask >> i) & 1u) perm[tstart + elem_of<K, THREADS>(false, i, t)] = d[i];
+        if ((mask >> i) & 1u) perm[base + elem_of<K, THREADS>(false, i, t)] = d[i];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t j = static_cast<uint32_t>(i) * THREADS + t;
-    if (j < tlen) out[delta[sdig[j]] + j] = stage_k[j];
+    if (j < cnt) out[delta[sdig[j]] + j] = stage_k[j];
   }
 }
 
@@ -335,7 +344,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
       key0 = key_start(x);
       g0 = bucket_start(x);
       const uint32_t key1 = key_start(x + 1), g1 = bucket_start(x + 1);
-      T = (key1 - key0 + tile2 - 1) / tile2;
+      T = key1 > key0 ? (key1 - (key0 & ~(kTileAlign - 1)) + tile2 - 1) / tile2 : 0u;
       const uint64_t R = g1 - g0;
       D = R == 0 ? 0u
                  : static_cast<uint32_t>(min((R + (1ull << log2S) - 1) >> log2S, static_cast<uint64_t>(kMaxD2)));
@@ -490,8 +499,12 @@ __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* s
 // A sub-bin of R <= kSMax buckets and m <= 65535 keys is sorted in LDS with
 // 16-bit counters, two per word (bucket i in half i & 1 of word i >> 1).  The
 // same LDS then stages the sorted keys so that they leave in whole lines.
-constexpr uint32_t kSMax = 1u << 15;
-constexpr uint32_t kBuildWords = 18432;  // 72 KiB: the counters, then the staging area
+constexpr uint32_t kBuildWords = 8448;  // 33 KiB: the counters, then the staging area (four
+                                        // workgroups per CU with the descriptors)
+constexpr uint32_t kSMax = 1u << 14;     // 16-bit counters for up to this many buckets
+constexpr uint32_t kWideR = 8192;        // 32-bit counters for up to this many buckets
+static_assert(kSMax <= 2 * kBuildWords, "16-bit counters fit the LDS block");
+static_assert(kWideR <= kBuildWords, "32-bit counters fit the LDS block");
 
 // Exclusive scan in place of the R 16-bit counters packed in c[0 .. (R+1)/2).
 // Each wave scans one contiguous chunk of words in rounds of 64, then adds the
@@ -523,6 +536,59 @@ __device__ __forceinline__ void lds_exclusive_scan16(uint32_t* c, uint32_t R, ui
     if (idx < words) c[idx] += add;
   }
   __syncthreads();
+}
+
+// Exclusive scan in place of R 32-bit counters c[0 .. R): each wave scans
+// one contiguous chunk in rounds of 64, then adds the totals of the chunks
+// before it.
+template <int THREADS>
+__device__ __forceinline__ void lds_exclusive_scan32(uint32_t* c, uint32_t R, uint32_t* wsum) {
+  constexpr int W = THREADS / kWave;
+  const uint32_t ch = ((R + W - 1) / W + kWave - 1) / kWave * kWave;
+  const uint32_t w = threadIdx.x / kWave, l = lane_id();
+  uint32_t carry = 0;
+  for (uint32_t r0 = 0; r0 < ch; r0 += kWave) {
+    const uint32_t idx = w * ch + r0 + l;
+    const uint32_t x = idx < R ? c[idx] : 0u;
+    const uint32_t inc = wave_inclusive_sum(x);
+    if (idx < R) c[idx] = carry + inc - x;
+    carry += readlane(inc, kWave - 1);
+  }
+  if (l == 0) wsum[w] = carry;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int x = 0; x < W; ++x) base += (x < static_cast<int>(w)) ? wsum[x] : 0u;
+  for (uint32_t r0 = 0; r0 < ch; r0 += kWave) {
+    const uint32_t idx = w * ch + r0 + l;
+    if (idx < R) c[idx] += base;
+  }
+  __syncthreads();
+}
+
+// LDS counter add for every valid lane; the lanes whose index equals the
+// first valid lane's share one atomic (a bucket holding one heavy key then
+// costs one atomic per wave).  With kReturn, each lane gets a distinct old
+// value (its position).
+template <bool kReturn>
+__device__ __forceinline__ uint32_t lds_agg_add(uint32_t* ctr, uint32_t idx, bool valid) {
+  const uint64_t act = ballot(valid);
+  if (act == 0) return 0;
+  const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(act)) - 1);
+  const uint32_t li = readlane(idx, leader);
+  const bool in = valid && idx == li;
+  const uint64_t same = ballot(in);
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&ctr[li], popc64(same));
+  uint32_t pos = 0;
+  if (kReturn) {
+    base = readlane(base, leader);
+    if (in) pos = base + popc64(same & lanemask_lt());
+    else if (valid) pos = atomicAdd(&ctr[idx], 1u);
+  } else if (valid && !in) {
+    atomicAdd(&ctr[idx], 1u);
+  }
+  return pos;
 }
 
 __device__ __forceinline__ uint32_t ld_l2(const uint32_t* p) {
@@ -565,7 +631,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     const bool regs = m <= static_cast<uint32_t>(THREADS * REG);
     K v[REG];
     // Two 16-bit values per word: first each key's bucket in the sub-bin
-    // (R <= 2^15), then its position (m <= 65535).
+    // (R <= kSMax), then its position (m <= 65535).
     uint32_t pos[(REG + 1) / 2];
     if (regs) {
 #pragma unroll
@@ -630,10 +696,57 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     return;
   }
 
+  if (R <= kWideR) {
+    // More than 65535 keys (heavy keys): 32-bit LDS counters, the keys
+    // streamed from memory twice (kU loads in flight per thread), adds
+    // combined per wave for lanes in the same bucket, positions written
+    // straight to the output.
+    constexpr int kU = 16 / (sizeof(K) / 4);
+    for (uint32_t i = t; i < R; i += THREADS) lds[i] = 0;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
+      K kv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        kv[u] = e < m ? in[sb.kA + e] : K(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        lds_agg_add<false>(lds, bucket_of(kv[u], log2P, sd) - sb.gA, e < m);
+      }
+    }
+    __syncthreads();
+    lds_exclusive_scan32<THREADS>(lds, R, wsum);
+    for (uint32_t i = t; i < R; i += THREADS) {
+      const uint32_t e0 = lds[i];
+      offsets[sb.gA + i] = sb.kA + e0;
+      const uint32_t e1 = i + 1 < R ? lds[i + 1] : m;
+      if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
+      K kv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        kv[u] = e < m ? in[sb.kA + e] : K(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+        const uint32_t p = lds_agg_add<true>(lds, bucket_of(kv[u], log2P, sd) - sb.gA, e < m);
+        if (e < m) out[sb.kA + p] = kv[u];
+      }
+    }
+    return;
+  }
+
   // A sub-bin wider than LDS (a level-1 segment with more buckets than its
-  // sub-bins can hold folds its tail into the last one) or with more than
-  // 65535 keys: the same three steps with the counters in global memory,
-  // offsets[gA + i] serving as the counter of bucket i.
+  // sub-bins can hold folds its tail into the last one): the same three
+  // steps with the counters in global memory, offsets[gA + i] serving as the
+  // counter of bucket i.
   __syncthreads();
   for (uint32_t i = t; i < R; i += THREADS) st_l2(&offsets[sb.gA + i], 0u);
   __threadfence();
@@ -709,15 +822,39 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
                                                              const uint32_t* __restrict__ offsets,
                                                              const K* __restrict__ tkeys,
                                                              const uint32_t* __restrict__ unsorted, uint32_t log2W,
+                                                             uint32_t* __restrict__ queue, bool from_queue,
                                                              uint32_t* __restrict__ c2) {
   constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);
   __shared__ uint32_t soff[(1u << kMaxLog2W) + 1];
   __shared__ K skeys[KCAP];
   __shared__ PartDesc sd[kMaxP];
   const uint32_t t = threadIdx.x;
-  if (blockIdx.x >= qplan->total_subbins) return;  // whole workgroup
-  const SubBin sb = sub_bin(qplan, qscan2, blockIdx.x);
-  const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
+  // A workgroup takes at most CH of a sub-bin's queries.  First launch:
+  // workgroup b takes chunk 0 of sub-bin b and queues chunks 1.. of a sub-bin
+  // with more queries (queue[0] = count, then (sub-bin, chunk) pairs).
+  // Second launch (from_queue): workgroup w takes queued item w.
+  constexpr uint32_t CH = THREADS * REG;
+  uint32_t b, chunk;
+  if (from_queue) {
+    if (blockIdx.x >= queue[0]) return;  // whole workgroup
+    b = queue[1 + 2 * blockIdx.x];
+    chunk = queue[2 + 2 * blockIdx.x];
+  } else {
+    if (blockIdx.x >= qplan->total_subbins) return;  // whole workgroup
+    b = blockIdx.x;
+    chunk = 0;
+  }
+  const SubBin sb = sub_bin(qplan, qscan2, b);
+  if (!from_queue && t == 0 && sb.kB - sb.kA > CH) {
+    const uint32_t extra = (sb.kB - sb.kA - 1) / CH;  // chunks after the first
+    const uint32_t at = atomicAdd(&queue[0], extra);
+    for (uint32_t k = 0; k < extra; ++k) {
+      queue[1 + 2 * (at + k)] = b;
+      queue[2 + 2 * (at + k)] = k + 1;
+    }
+  }
+  const uint32_t qa = sb.kA + min(chunk * CH, sb.kB - sb.kA);
+  const uint32_t R = sb.gB - sb.gA, m = min(CH, sb.kB - qa);
   const uint32_t Wb = 1u << log2W;
   const uint32_t nuns = unsorted[0];
   {
@@ -742,7 +879,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        qv[u] = e < m ? q2[sb.kA + e] : K(0);
+        qv[u] = e < m ? q2[qa + e] : K(0);
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
@@ -751,7 +888,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
           const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
           const uint32_t lo = soff[lb], hi = soff[lb + 1];
           const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-          c2[sb.kA + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
+          c2[qa + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
                                  : count_equal(tkeys, lo, hi, qv[u], srt);
         }
       }
@@ -767,7 +904,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
-      if (e < m) qv[j] = q2[sb.kA + e];
+      if (e < m) qv[j] = q2[qa + e];
     }
 #pragma unroll
     for (int j = 0; j < (REG + 1) / 2; ++j) cnt[j] = 0;
@@ -817,7 +954,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
           const uint32_t lo = offsets[g], hi = offsets[g + 1];
           c = count_equal(tkeys, lo, hi, qv[j], long_bucket_sorted(unsorted, nuns, g, kMaxUnsorted));
         }
-        c2[sb.kA + e] = c;
+        c2[qa + e] = c;
       }
     }
   }
@@ -896,23 +1033,52 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
     const uint32_t g = long_list[idx];
     const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
 
-    // 1. distinct keys with multiplicities
-    for (uint32_t c0 = w * kWave; c0 < L; c0 += kLongThreads) {
-      if (soverflow) break;
-      const uint32_t i = c0 + l;
-      const bool valid = i < L;
-      const K key = valid ? keys[lo + i] : K(0);
-      uint64_t active = ballot(valid);
-      while (active != 0) {
-        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(active)) - 1);
-        const K v = readlane_key(key, leader);
-        const uint64_t match = ballot(valid && key == v) & active;
-        active &= ~match;
-        if (!set_add(sval[w], scnt[w], &ssize[w], v, popc64(match))) {
-          if (l == 0) soverflow = 1;
-          break;
+    // 1. distinct keys with multiplicities.  The wave keeps the last key it
+    // met and that key's pending count in registers, and touches the set
+    // only when the key changes (a bucket of one heavy key costs a ballot
+    // per 64 keys).
+    {
+      // Each wave reads kGroups groups of 64 keys per round (all loads in
+      // flight before the first is used).
+      constexpr int kGroups = 8;
+      K last = K(0);
+      uint32_t pend = 0;
+      bool ok = true;
+      for (uint32_t c0 = w * kWave * kGroups; c0 < L && ok; c0 += kLongThreads * kGroups) {
+        if (soverflow) break;
+        K kv[kGroups];
+#pragma unroll
+        for (int gi = 0; gi < kGroups; ++gi) {
+          const uint32_t i = c0 + gi * kWave + l;
+          kv[gi] = i < L ? keys[lo + i] : K(0);
+        }
+#pragma unroll
+        for (int gi = 0; gi < kGroups; ++gi) {
+          const uint32_t i = c0 + gi * kWave + l;
+          const bool valid = i < L;
+          const K key = kv[gi];
+          uint64_t active = ballot(valid);
+          if (pend != 0) {
+            const uint64_t same = ballot(valid && key == last);
+            pend += popc64(same);
+            active &= ~same;
+          }
+          while (active != 0 && ok) {
+            const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(active)) - 1);
+            const K v = readlane_key(key, leader);
+            const uint64_t match = ballot(valid && key == v) & active;
+            active &= ~match;
+            if (pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) {
+              ok = false;
+              break;
+            }
+            last = v;
+            pend = popc64(match);
+          }
         }
       }
+      if (ok && pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) ok = false;
+      if (!ok && l == 0) soverflow = 1;
     }
     __syncthreads();
     if (w == 0 && !soverflow) {
@@ -954,12 +1120,10 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
         run0[nd] = run;
       }
       __syncthreads();
+      // Positions only grow along a thread's loop: walk the run index.
+      uint32_t a = 0;
       for (uint32_t i = t; i < L; i += kLongThreads) {
-        uint32_t a = 0, b = nd;  // last run with run0[r] <= i
-        while (b - a > 1) {
-          const uint32_t mid = (a + b) >> 1;
-          if (run0[mid] <= i) a = mid; else b = mid;
-        }
+        while (a + 1 < nd && run0[a + 1] <= i) ++a;
         keys[lo + i] = sval[1][a];
       }
     } else if (L <= kSortCap) {
@@ -1092,30 +1256,40 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
                             uint32_t* long_count, uint32_t* long_list, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   if (kt == 0)
-    k_lds_build<uint32_t, kLdsThreads, 20, 8><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_build<uint32_t, kBuildThreads, 20, 8><<<max_subbins, kBuildThreads, 0, s>>>(
         static_cast<const uint32_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint32_t*>(out),
         long_count, long_list);
   else
-    k_lds_build<uint64_t, kLdsThreads, 20, 4><<<max_subbins, kLdsThreads, 0, s>>>(
+    k_lds_build<uint64_t, kBuildThreads, 20, 4><<<max_subbins, kBuildThreads, 0, s>>>(
         static_cast<const uint64_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint64_t*>(out),
         long_count, long_list);
   return hipGetLastError();
 }
 
+uint32_t probe_chunk_keys() { return kLdsThreads * kProbeReg; }
+
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
-                            uint32_t max_subbins, uint32_t log2P, uint32_t P, const PartDesc* desc,
+                            uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
-                            uint32_t* c2, hipStream_t s) {
+                            uint32_t* queue, uint32_t* c2, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
-  if (kt == 0)
-    k_lds_probe<uint32_t, kLdsThreads, 20, 8><<<max_subbins, kLdsThreads, 0, s>>>(
-        static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint32_t*>(tkeys),
-        unsorted, log2W, c2);
-  else
-    k_lds_probe<uint64_t, kLdsThreads, 20, 4><<<max_subbins, kLdsThreads, 0, s>>>(
-        static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint64_t*>(tkeys),
-        unsorted, log2W, c2);
-  return hipGetLastError();
+  const uint32_t max_queued = q / probe_chunk_keys() + 1;
+  hipError_t e = launch_fill_u32(queue, 1, 0u, s);
+  if (e != hipSuccess) return e;
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint32_t grid = pass == 0 ? max_subbins : max_queued;
+    if (kt == 0)
+      k_lds_probe<uint32_t, kLdsThreads, kProbeReg, 8><<<grid, kLdsThreads, 0, s>>>(
+          static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
+          static_cast<const uint32_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
+    else
+      k_lds_probe<uint64_t, kLdsThreads, kProbeReg, 4><<<grid, kLdsThreads, 0, s>>>(
+          static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
+          static_cast<const uint64_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,

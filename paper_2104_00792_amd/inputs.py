@@ -232,3 +232,86 @@ def make_workload(name: str, n: int | None = None, q: int | None = None, device=
         keys = zipf_u64(n, 1 << 20, ks)
         queries = zipf_u64(q, 1 << 20, qs)
     return keys, queries, opts
+
+
+# --------------------------------------------------------------------------
+# Batched tables: T tables with sizes log-uniform in [2^lo, 2^hi]; table t
+# draws its keys from stream BATCH_KEY_SEED + t and its queries (as many as
+# keys, 50% hits, as queries_hit50) from stream BATCH_QUERY_SEED + t.
+# --------------------------------------------------------------------------
+
+BATCH_SIZE_SEED = 0x5EED0300
+BATCH_KEY_SEED = 0x5EED0400
+BATCH_QUERY_SEED = 0x5EED0600
+
+
+def batch_sizes(T: int, lo_log2: float = 10, hi_log2: float = 20, seed: int = BATCH_SIZE_SEED) -> np.ndarray:
+    """T table sizes, round(2^(lo + (hi - lo) u)) with u uniform in [0, 1)."""
+    u = (splitmix64(seed, 0, T) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.round(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u)).astype(np.int64)
+
+
+def segment_offsets(sizes) -> np.ndarray:
+    return np.concatenate([[0], np.cumsum(np.asarray(sizes, np.int64))]).astype(np.uint32)
+
+
+def batch_keys(sizes, seed: int = BATCH_KEY_SEED) -> np.ndarray:
+    """Concatenated uint32 keys of the tables (table t: uniform_u32(n_t, seed + t))."""
+    parts = [uniform_u32(int(s), seed + t) for t, s in enumerate(sizes)]
+    return np.concatenate(parts) if parts else np.empty(0, np.uint32)
+
+
+def batch_queries(keys: np.ndarray, sizes, qsizes, seed: int = BATCH_QUERY_SEED) -> np.ndarray:
+    """Concatenated queries: segment t is queries_hit50(keys of table t,
+    qsizes[t], seed + t)."""
+    o = segment_offsets(sizes)
+    parts = [queries_hit50(keys[int(o[t]):int(o[t + 1])], int(q), seed + t) for t, q in enumerate(qsizes)]
+    return np.concatenate(parts) if parts else np.empty(0, keys.dtype)
+
+
+def _segments_t(offsets, start: int, count: int, device):
+    """(segment id, index inside the segment) of elements start .. start+count-1."""
+    import torch
+
+    idx = torch.arange(start, start + count, dtype=torch.int64, device=device)
+    seg = torch.searchsorted(offsets[1:], idx, right=True)
+    return seg, idx - offsets[seg]
+
+
+def batch_keys_t(sizes, device, seed: int = BATCH_KEY_SEED, chunk: int = 1 << 26):
+    """Device twin of batch_keys, drawn in chunks of ``chunk`` keys."""
+    import torch
+
+    offsets = torch.from_numpy(segment_offsets(sizes).astype(np.int64)).to(device)
+    total = int(offsets[-1])
+    out = torch.empty(total, dtype=torch.uint32, device=device)
+    for c0 in range(0, total, chunk):
+        c = min(chunk, total - c0)
+        seg, local = _segments_t(offsets, c0, c, device)
+        z = _mix_t((local + 1) * _s64(int(GAMMA)) + (seg + seed))
+        out[c0:c0 + c] = _to_u32(z)
+    return out
+
+
+def batch_queries_t(keys, sizes, qsizes, device, seed: int = BATCH_QUERY_SEED, chunk: int = 1 << 26):
+    """Device twin of batch_queries (keys: the device tensor of batch_keys_t)."""
+    import torch
+
+    koff = torch.from_numpy(segment_offsets(sizes).astype(np.int64)).to(device)
+    qoff = torch.from_numpy(segment_offsets(qsizes).astype(np.int64)).to(device)
+    total = int(qoff[-1])
+    out = torch.empty(total, dtype=torch.uint32, device=device)
+    kv = keys.view(torch.int32)
+    for c0 in range(0, total, chunk):
+        c = min(chunk, total - c0)
+        seg, local = _segments_t(qoff, c0, c, device)
+        sd = seg + seed
+        wa = _mix_t((2 * local + 1) * _s64(int(GAMMA)) + sd)
+        wb = _mix_t((2 * local + 2) * _s64(int(GAMMA)) + sd)
+        n_t = koff[seg + 1] - koff[seg]
+        pos = koff[seg] + _lsr((wa & 0xFFFFFFFF) * n_t, 32)
+        hit = (wa < 0) & (n_t > 0)
+        picked = kv[torch.clamp(pos, max=max(kv.numel() - 1, 0))] if kv.numel() else torch.zeros_like(pos, dtype=torch.int32)
+        miss = _to_u32(wb).view(torch.int32)
+        out[c0:c0 + c] = torch.where(hit, picked, miss).view(torch.uint32)
+    return out

@@ -204,10 +204,12 @@ class Server:
     def _build_pending(self, tid: int) -> bool:
         return any(r.kind == "build" and r.table == tid for _, r, _, _ in self.inflight)
 
-    def run(self, reqs, clock):
-        """Serve `reqs` (sorted by arrival) against `clock`."""
+    def run(self, reqs, clock, progress=None, every: int = 5000):
+        """Serve `reqs` (sorted by arrival) against `clock`; `progress(msg)`
+        is called each time `every` more requests have been admitted."""
         queue = []
         i = 0
+        admitted = 0
         while i < len(reqs) or queue or self.inflight:
             now = clock.now()
             while i < len(reqs) and reqs[i].arrival <= now:
@@ -225,6 +227,9 @@ class Server:
                         raise MemoryError(f"request {req.rid} needs more than the HBM cap")
                     break
                 heapq.heappop(queue)
+                admitted += 1
+                if progress is not None and admitted % every == 0:
+                    progress(f"admitted {admitted} of {len(reqs)}")
             clock.wait(self, reqs[i].arrival if i < len(reqs) else None)
         return reqs
 
@@ -314,7 +319,7 @@ class GpuExecutor:
 
 
 def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10**9, rate: float | None = None,
-                build_log2=(10, 24), probe_log2=(8, 22), load: float = 0.8):
+                build_log2=(10, 24), probe_log2=(8, 22), load: float = 0.8, progress=None):
     """Closed-loop capacity first (every request present at t = 0), then an
     open-loop Poisson stream at `load` times that capacity.  Returns both
     reports and the open-loop requests."""
@@ -324,14 +329,16 @@ def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10*
     for r in reqs:
         r.arrival = 0.0
     clock = WallClock()
-    Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots).run(reqs, clock)
+    srv = Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots)
+    srv.run(reqs, clock, progress)
     torch.cuda.synchronize()
     closed = latency_report(reqs, clock.now())
+    closed.update(evictions=srv.cache.evictions, rebuilds=srv.rebuilds, peak_reserved_bytes=srv.cache.peak)
     lam = rate if rate is not None else load * closed["requests_per_s"]
     reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=lam)
     clock = WallClock()
     srv = Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots)
-    srv.run(reqs, clock)
+    srv.run(reqs, clock, progress)
     torch.cuda.synchronize()
     opened = latency_report(reqs, clock.now())
     opened.update(offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,

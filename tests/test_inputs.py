@@ -70,3 +70,27 @@ def test_torch_twin_equals_numpy():
         kt, qt, _ = inputs.make_workload(name, n=30011, q=20011, device=torch.device("cpu"))
         assert np.array_equal(kt.numpy(), k), name
         assert np.array_equal(qt.numpy(), q), name
+
+
+def test_batch_generators_match_their_torch_twins():
+    import torch
+
+    sizes = inputs.batch_sizes(40, 0, 9, seed=77)
+    sizes[3] = 0
+    keys = inputs.batch_keys(sizes)
+    qsizes = sizes + 3
+    queries = inputs.batch_queries(keys, sizes, qsizes)
+    kt = inputs.batch_keys_t(sizes, "cpu", chunk=1000)
+    qt = inputs.batch_queries_t(kt, sizes, qsizes, "cpu", chunk=777)
+    assert np.array_equal(kt.numpy(), keys)
+    assert np.array_equal(qt.numpy(), queries)
+    o = inputs.segment_offsets(sizes)
+    for t in (0, 5, 39):
+        assert np.array_equal(keys[o[t]:o[t + 1]], inputs.uniform_u32(int(sizes[t]), inputs.BATCH_KEY_SEED + t))
+
+
+def test_batch_sizes_are_log_uniform():
+    s = inputs.batch_sizes(4096)
+    assert s.min() >= 1 << 10 and s.max() <= 1 << 20
+    lg = np.log2(s)
+    assert abs(lg.mean() - 15) < 0.2 and abs((lg < 12.5).mean() - 0.25) < 0.03
