@@ -234,6 +234,22 @@ uint32_t ceil_log2(uint64_t x) {
   return l;
 }
 
+// Workspace of the heavy sub-bin passes for n keys (see launch_lds_build).
+struct HeavyWork {
+  uint32_t* words = nullptr;
+  uint32_t max_chunks = 0;
+};
+
+hg_status alloc_heavy(Allocs& mem, uint64_t n, HeavyWork& h) {
+  const uint64_t max_heavy = n / 65536 + 1;
+  const uint64_t max_chunks = n / hg::heavy_chunk_keys() + max_heavy + 1;
+  void* p = nullptr;
+  HG_TRY(mem.get(&p, (2 + 2 * max_chunks + max_heavy) * sizeof(uint32_t)), "allocate heavy sub-bin queue");
+  h.words = static_cast<uint32_t*>(p);
+  h.max_chunks = static_cast<uint32_t>(max_chunks);
+  return HG_OK;
+}
+
 // Level-2 tiles of n keys in nseg segments: a segment of n_s keys whose
 // tiles start up to kTileAlign - 1 keys early has at most
 // (n_s + kTileAlign - 2) / tile + 1 of them.
@@ -406,9 +422,12 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
   static const char* const kNames[4] = {"split1_scatter", "split2_count", "split2_scan", "split2_scatter"};
   st = split_two_levels(keys, n, kt, sp, log2P, P, desc, w, nullptr, nullptr, kNames, s);
   if (st != HG_OK) return st;
+  HeavyWork hw;
+  st = alloc_heavy(mem, n, hw);
+  if (st != HG_OK) return st;
   HG_LAUNCH("lds_build", s,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, log2P, P, desc, offs, keys_out,
-                                 long_count, long_list, s));
+                                 long_count, long_list, hw.words, hw.max_chunks, s));
   return HG_OK;
 }
 
@@ -776,9 +795,12 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   st = split_segments(d_keys, n32, kt, sp.log2S, desc, w, nullptr, kNames, stream);
   if (st != HG_OK) return st;
   const uint32_t max_subbins = w.max_subbins;
+  HeavyWork hw;
+  st = alloc_heavy(mem, n, hw);
+  if (st != HG_OK) return st;
   HG_LAUNCH("blds_build", stream,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, desc, offs, keys_out, long_ctr,
-                                 long_list, stream));
+                                 long_list, hw.words, hw.max_chunks, stream));
   HG_LAUNCH("long_sort", stream,
             hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted, stream));
 

@@ -29,8 +29,9 @@ constexpr uint32_t kLog2SMin = 10;
 constexpr uint32_t kLog2SLds = 14;  // a segment's last sub-bin may grow to 2^14 in LDS
 constexpr uint32_t kMaxD2 = 1024;
 constexpr int kL1Threads = 256;
-constexpr int kL1Tile = kL1Threads * 16;
-constexpr int kL2Threads = 512;
+constexpr int kL1Items = 16;
+constexpr int kL1Tile = kL1Threads * kL1Items;
+constexpr int kL2Threads = 1024;      // level-2 scatter; counting takes half the threads, twice the items
 constexpr int kLdsThreads = 1024;      // LDS probe workgroup
 constexpr int kBuildThreads = 512;     // LDS build workgroup
 constexpr uint32_t kMaxLog2W = 13;  // probe window: at most 2^13 buckets in LDS
@@ -54,7 +55,7 @@ hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets
 hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
                             uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s);
 
-inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 16 : 8); }
+inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 8 : 4); }
 // Level-2 tiles of a segment start at its first key rounded down to this
 // many keys (16 bytes or more), so interior tiles take vector loads.
 constexpr uint32_t kTileAlign = 4;
@@ -134,9 +135,15 @@ hipError_t launch_batch_layout(const uint32_t* table_keys, uint32_t T, uint32_t 
 
 // One workgroup per sub-bin: LDS counting sort of its keys by bucket; writes
 // the sub-bin's CSR offsets and keys.  grid = max_subbins.
+// Sub-bins of more than 65535 keys are shared by several workgroups
+// (heavy passes); their workspace `heavy` holds 2 + 2 * max_chunks +
+// max_heavy words, max_chunks = n / heavy_chunk_keys() + max_heavy + 1 and
+// max_heavy = n / 65536 + 1.
+uint32_t heavy_chunk_keys();
 hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
-                            uint32_t* long_count, uint32_t* long_list, hipStream_t s);
+                            uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
+                            hipStream_t s);
 
 // Queries of one sub-bin, at most probe_chunk_keys() per workgroup (a
 // sub-bin with more is shared through a queue): windows of 2^log2W buckets

@@ -102,10 +102,10 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
 // one LDS atomic on the tile histogram, stages the tile in LDS in digit
 // order and writes every run with consecutive lanes; when `perm` is given it
 // also records, in input order, the output position of every key.
-// Sized for two workgroups of 512 (or four of 256) threads per CU: at least
-// four waves per SIMD, so at most 128 VGPRs.
+// 1024-thread workgroups are sized for two per CU (eight waves per SIMD, so
+// at most 64 VGPRs), smaller ones for at least four waves per SIMD.
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP, int DIG>
-__global__ __launch_bounds__(THREADS, 4) void k_msplit(const K* __restrict__ in, uint32_t n,
+__global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(const K* __restrict__ in, uint32_t n,
                                                     const SegPlan* __restrict__ plan, uint32_t nd, uint32_t log2P,
                                                     uint32_t P, const PartDesc* __restrict__ desc, uint32_t shift,
                                                     uint32_t* __restrict__ counts, K* __restrict__ out,
@@ -503,6 +503,7 @@ constexpr uint32_t kBuildWords = 8448;  // 33 KiB: the counters, then the stagin
                                         // workgroups per CU with the descriptors)
 constexpr uint32_t kSMax = 1u << 14;     // 16-bit counters for up to this many buckets
 constexpr uint32_t kWideR = 8192;        // 32-bit counters for up to this many buckets
+constexpr uint32_t kHeavyChunk = kBuildThreads * 20;  // keys per workgroup of the heavy passes
 static_assert(kSMax <= 2 * kBuildWords, "16-bit counters fit the LDS block");
 static_assert(kWideR <= kBuildWords, "32-bit counters fit the LDS block");
 
@@ -611,7 +612,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
                                                              uint32_t P, const PartDesc* __restrict__ desc,
                                                              uint32_t* __restrict__ offsets, K* __restrict__ out,
                                                              uint32_t* __restrict__ long_count,
-                                                             uint32_t* __restrict__ long_list) {
+                                                             uint32_t* __restrict__ long_list,
+                                                             uint32_t* __restrict__ heavy_count,
+                                                             uint32_t* __restrict__ heavy_chunks,
+                                                             uint32_t* __restrict__ heavy_bins) {
   constexpr uint32_t kStageKeys = kBuildWords * 4 / sizeof(K);
   __shared__ uint32_t lds[kBuildWords];
   __shared__ PartDesc sd[kMaxP];
@@ -697,48 +701,18 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   }
 
   if (R <= kWideR) {
-    // More than 65535 keys (heavy keys): 32-bit LDS counters, the keys
-    // streamed from memory twice (kU loads in flight per thread), adds
-    // combined per wave for lanes in the same bucket, positions written
-    // straight to the output.
-    constexpr int kU = 16 / (sizeof(K) / 4);
-    for (uint32_t i = t; i < R; i += THREADS) lds[i] = 0;
-    __syncthreads();
-    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
-      K kv[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        kv[u] = e < m ? in[sb.kA + e] : K(0);
+    // More than 65535 keys (heavy keys): the sub-bin is shared by the
+    // workgroups of the heavy passes below.  Here its counters (its own
+    // offsets) start at zero and its chunks are queued.
+    for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = 0u;
+    if (t == 0) {
+      const uint32_t nch = (m + kHeavyChunk - 1) / kHeavyChunk;
+      const uint32_t at = atomicAdd(&heavy_count[0], nch);
+      for (uint32_t k = 0; k < nch; ++k) {
+        heavy_chunks[2 * (at + k)] = blockIdx.x;
+        heavy_chunks[2 * (at + k) + 1] = k;
       }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        lds_agg_add<false>(lds, bucket_of(kv[u], log2P, sd) - sb.gA, e < m);
-      }
-    }
-    __syncthreads();
-    lds_exclusive_scan32<THREADS>(lds, R, wsum);
-    for (uint32_t i = t; i < R; i += THREADS) {
-      const uint32_t e0 = lds[i];
-      offsets[sb.gA + i] = sb.kA + e0;
-      const uint32_t e1 = i + 1 < R ? lds[i + 1] : m;
-      if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
-    }
-    __syncthreads();
-    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
-      K kv[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        kv[u] = e < m ? in[sb.kA + e] : K(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        const uint32_t p = lds_agg_add<true>(lds, bucket_of(kv[u], log2P, sd) - sb.gA, e < m);
-        if (e < m) out[sb.kA + p] = kv[u];
-      }
+      heavy_bins[atomicAdd(&heavy_count[1], 1u)] = blockIdx.x;
     }
     return;
   }
@@ -788,6 +762,157 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     const uint32_t e0 = ld_l2(&offsets[sb.gA + i]);
     const uint32_t e1 = i + 1 < R ? ld_l2(&offsets[sb.gA + i + 1]) : sb.kB;
     if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+  }
+}
+
+// ------------------------------------------------------- heavy sub-bins
+// A sub-bin of more than 65535 keys (a few keys of very high multiplicity)
+// is built by many workgroups, one chunk of kHeavyChunk keys each, in four
+// passes over the queued chunks and sub-bins (persistent grids):
+//   count    chunk histogram in LDS, added to the sub-bin's counters;
+//   scan     counters -> bucket starts (one workgroup per sub-bin);
+//   scatter  chunk histogram again; one global add per bucket reserves the
+//            chunk's range; keys written at LDS-counted positions;
+//   fix      the counters now hold bucket ends: shift them back into
+//            starts and note the long buckets.
+// heavy_count[0] = queued chunks, [1] = heavy sub-bins.
+
+template <typename K>
+__device__ __forceinline__ void load_sub_bin_desc(PartDesc* sd, const SegPlan* plan, const PartDesc* desc,
+                                                  uint32_t seg, uint32_t P, uint32_t threads) {
+  const PartDesc* dsrc = plan->desc_by_seg ? desc + seg : desc;
+  for (uint32_t i = threadIdx.x; i < P; i += threads) sd[i] = dsrc[i];
+}
+
+template <typename K, int THREADS, int REG>
+__global__ __launch_bounds__(THREADS) void k_heavy_count(const K* __restrict__ in, const SegPlan* __restrict__ plan,
+                                                         const uint32_t* __restrict__ scan2, uint32_t log2P,
+                                                         uint32_t P, const PartDesc* __restrict__ desc,
+                                                         uint32_t* __restrict__ offsets,
+                                                         const uint32_t* __restrict__ heavy_count,
+                                                         const uint32_t* __restrict__ heavy_chunks) {
+  static_assert(THREADS * REG == kHeavyChunk, "one chunk per pass");
+  __shared__ uint32_t hist[kWideR];
+  __shared__ PartDesc sd[kMaxP];
+  const uint32_t t = threadIdx.x;
+  const uint32_t items = heavy_count[0];
+  for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const uint32_t b = heavy_chunks[2 * w], k = heavy_chunks[2 * w + 1];
+    const SubBin sb = sub_bin(plan, scan2, b);
+    const uint32_t R = sb.gB - sb.gA;
+    const uint32_t c0 = sb.kA + k * kHeavyChunk, c1 = min(sb.kB, c0 + kHeavyChunk);
+    __syncthreads();  // the previous chunk is done with hist and sd
+    load_sub_bin_desc<K>(sd, plan, desc, sb.seg, P, THREADS);
+    for (uint32_t i = t; i < R; i += THREADS) hist[i] = 0;
+    __syncthreads();
+    K v[REG];
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      v[j] = e < c1 ? in[e] : K(0);
+    }
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      lds_agg_add<false>(hist, bucket_of(v[j], log2P, sd) - sb.gA, e < c1);
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < R; i += THREADS)
+      if (hist[i] != 0) atomicAdd(&offsets[sb.gA + i], hist[i]);
+  }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_heavy_scan(const SegPlan* __restrict__ plan,
+                                                        const uint32_t* __restrict__ scan2,
+                                                        uint32_t* __restrict__ offsets,
+                                                        const uint32_t* __restrict__ heavy_count,
+                                                        const uint32_t* __restrict__ heavy_bins) {
+  __shared__ uint32_t c[kWideR];
+  __shared__ uint32_t wsum[THREADS / kWave];
+  const uint32_t t = threadIdx.x;
+  const uint32_t nb = heavy_count[1];
+  for (uint32_t j = blockIdx.x; j < nb; j += gridDim.x) {
+    const SubBin sb = sub_bin(plan, scan2, heavy_bins[j]);
+    const uint32_t R = sb.gB - sb.gA;
+    __syncthreads();
+    for (uint32_t i = t; i < R; i += THREADS) c[i] = offsets[sb.gA + i];
+    __syncthreads();
+    lds_exclusive_scan32<THREADS>(c, R, wsum);
+    for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = sb.kA + c[i];
+  }
+}
+
+template <typename K, int THREADS, int REG>
+__global__ __launch_bounds__(THREADS) void k_heavy_scatter(const K* __restrict__ in, const SegPlan* __restrict__ plan,
+                                                           const uint32_t* __restrict__ scan2, uint32_t log2P,
+                                                           uint32_t P, const PartDesc* __restrict__ desc,
+                                                           uint32_t* __restrict__ offsets, K* __restrict__ out,
+                                                           const uint32_t* __restrict__ heavy_count,
+                                                           const uint32_t* __restrict__ heavy_chunks) {
+  static_assert(THREADS * REG == kHeavyChunk, "one chunk per pass");
+  __shared__ uint32_t hist[kWideR];
+  __shared__ PartDesc sd[kMaxP];
+  const uint32_t t = threadIdx.x;
+  const uint32_t items = heavy_count[0];
+  for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const uint32_t b = heavy_chunks[2 * w], k = heavy_chunks[2 * w + 1];
+    const SubBin sb = sub_bin(plan, scan2, b);
+    const uint32_t R = sb.gB - sb.gA;
+    const uint32_t c0 = sb.kA + k * kHeavyChunk, c1 = min(sb.kB, c0 + kHeavyChunk);
+    __syncthreads();
+    load_sub_bin_desc<K>(sd, plan, desc, sb.seg, P, THREADS);
+    for (uint32_t i = t; i < R; i += THREADS) hist[i] = 0;
+    __syncthreads();
+    K v[REG];
+    uint32_t lb[REG];
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      v[j] = e < c1 ? in[e] : K(0);
+    }
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      lb[j] = bucket_of(v[j], log2P, sd) - sb.gA;
+      lds_agg_add<false>(hist, lb[j], e < c1);
+    }
+    __syncthreads();
+    // Reserve this chunk's range in every bucket it touches.
+    for (uint32_t i = t; i < R; i += THREADS)
+      if (hist[i] != 0) hist[i] = atomicAdd(&offsets[sb.gA + i], hist[i]);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
+      const uint32_t p = lds_agg_add<true>(hist, lb[j], e < c1);
+      if (e < c1) out[p] = v[j];
+    }
+  }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_heavy_fix(const SegPlan* __restrict__ plan,
+                                                       const uint32_t* __restrict__ scan2,
+                                                       uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ heavy_count,
+                                                       const uint32_t* __restrict__ heavy_bins,
+                                                       uint32_t* __restrict__ long_count,
+                                                       uint32_t* __restrict__ long_list) {
+  __shared__ uint32_t c[kWideR];
+  const uint32_t t = threadIdx.x;
+  const uint32_t nb = heavy_count[1];
+  for (uint32_t j = blockIdx.x; j < nb; j += gridDim.x) {
+    const SubBin sb = sub_bin(plan, scan2, heavy_bins[j]);
+    const uint32_t R = sb.gB - sb.gA;
+    __syncthreads();
+    for (uint32_t i = t; i < R; i += THREADS) c[i] = offsets[sb.gA + i];  // bucket ends
+    __syncthreads();
+    for (uint32_t i = t; i < R; i += THREADS) {
+      const uint32_t start = i == 0 ? sb.kA : c[i - 1];
+      offsets[sb.gA + i] = start;
+      if (c[i] - start > kLongT) note_long(long_count, long_list, sb.gA + i);
+    }
   }
 }
 
@@ -1200,11 +1325,16 @@ hipError_t msplit_level(int level, int op, int dig, const K* in, uint32_t n, uin
     const uint32_t tiles = div_up(n, kL1Tile);
     if (tiles == 0) return hipSuccess;
     if (nd > 256) return hipErrorInvalidValue;
-    return msplit_op<K, kL1Threads, 16, 256>(op, dig, dim3(tiles), in, n, nullptr, nd, log2P, P, desc, shift, counts,
+    return msplit_op<K, kL1Threads, kL1Items, 256>(op, dig, dim3(tiles), in, n, nullptr, nd, log2P, P, desc, shift, counts,
                                               out, perm, s);
   }
   if (max_tiles == 0) return hipSuccess;
-  constexpr int kItems2 = sizeof(K) == 4 ? 16 : 8;
+  // Both passes cut the same tiles (kL2Threads * kItems2 keys); counting
+  // runs them with half the threads and twice the items.
+  constexpr int kItems2 = sizeof(K) == 4 ? 8 : 4;
+  if (op == OP_COUNT)
+    return msplit_op<K, kL2Threads / 2, 2 * kItems2, kMaxD2>(op, dig, dim3(max_tiles), in, n, plan, nd, log2P, P,
+                                                              desc, shift, counts, out, perm, s);
   return msplit_op<K, kL2Threads, kItems2, kMaxD2>(op, dig, dim3(max_tiles), in, n, plan, nd, log2P, P, desc, shift,
                                                     counts, out, perm, s);
 }
@@ -1251,19 +1381,45 @@ hipError_t launch_batch_layout(const uint32_t* table_keys, uint32_t T, uint32_t 
   return hipGetLastError();
 }
 
+uint32_t heavy_chunk_keys() { return kHeavyChunk; }
+
+template <typename K>
+hipError_t lds_build_passes(const K* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
+                            uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, K* out,
+                            uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
+                            hipStream_t s) {
+  constexpr int kMinW = sizeof(K) == 4 ? 8 : 4;
+  uint32_t* heavy_chunks = heavy + 2;
+  uint32_t* heavy_bins = heavy_chunks + 2 * static_cast<size_t>(max_chunks);
+  hipError_t e = launch_fill_u32(heavy, 2, 0u, s);
+  if (e != hipSuccess) return e;
+  k_lds_build<K, kBuildThreads, 20, kMinW><<<max_subbins, kBuildThreads, 0, s>>>(
+      in, plan, scan2, log2P, P, desc, offsets, out, long_count, long_list, heavy, heavy_chunks, heavy_bins);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  constexpr uint32_t kGrid = 1024, kBinGrid = 256;
+  k_heavy_count<K, kBuildThreads, 20><<<kGrid, kBuildThreads, 0, s>>>(in, plan, scan2, log2P, P, desc, offsets,
+                                                                      heavy, heavy_chunks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_heavy_scan<kBuildThreads><<<kBinGrid, kBuildThreads, 0, s>>>(plan, scan2, offsets, heavy, heavy_bins);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_heavy_scatter<K, kBuildThreads, 20><<<kGrid, kBuildThreads, 0, s>>>(in, plan, scan2, log2P, P, desc, offsets,
+                                                                        out, heavy, heavy_chunks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_heavy_fix<kBuildThreads><<<kBinGrid, kBuildThreads, 0, s>>>(plan, scan2, offsets, heavy, heavy_bins, long_count,
+                                                                long_list);
+  return hipGetLastError();
+}
+
 hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
-                            uint32_t* long_count, uint32_t* long_list, hipStream_t s) {
+                            uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
+                            hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   if (kt == 0)
-    k_lds_build<uint32_t, kBuildThreads, 20, 8><<<max_subbins, kBuildThreads, 0, s>>>(
-        static_cast<const uint32_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint32_t*>(out),
-        long_count, long_list);
-  else
-    k_lds_build<uint64_t, kBuildThreads, 20, 4><<<max_subbins, kBuildThreads, 0, s>>>(
-        static_cast<const uint64_t*>(in), plan, scan2, log2P, P, desc, offsets, static_cast<uint64_t*>(out),
-        long_count, long_list);
-  return hipGetLastError();
+    return lds_build_passes(static_cast<const uint32_t*>(in), plan, scan2, max_subbins, log2P, P, desc, offsets,
+                            static_cast<uint32_t*>(out), long_count, long_list, heavy, max_chunks, s);
+  return lds_build_passes(static_cast<const uint64_t*>(in), plan, scan2, max_subbins, log2P, P, desc, offsets,
+                          static_cast<uint64_t*>(out), long_count, long_list, heavy, max_chunks, s);
 }
 
 uint32_t probe_chunk_keys() { return kLdsThreads * kProbeReg; }

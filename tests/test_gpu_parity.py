@@ -269,3 +269,17 @@ def test_sorted_probe_output_alignment(gpu, dtype, shift):
     assert np.array_equal(out.cpu().numpy(), oracle.count(keys, queries))
     assert np.all(buf[:shift].cpu().numpy() == 0xFFFFFFFF)
     t.free()
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("P", [1, 16])
+def test_heavy_subbins_shared_by_workgroups(gpu, dtype, P):
+    """Three keys with 300000, 150000 and 70000 copies among 400000 uniform
+    keys: their sub-bins hold more than 65535 keys, so they are built by
+    many workgroups (chunk histograms, reserved ranges), and their queries
+    are probed by many workgroups too.  Checked against the oracle."""
+    heavy = np.array([0xABCDEF01, 17, 0xFFFFFFFF], dtype=dtype)
+    keys = np.concatenate([np.repeat(heavy, [300000, 150000, 70000]), make_keys("uniform", 400000, dtype, 61)])
+    keys = keys[np.argsort(inputs.uniform_u32(keys.size, 62), kind="stable")]  # interleave
+    queries = np.concatenate([np.repeat(heavy, 50000), make_keys("uniform", 20000, dtype, 63), keys[:30000]])
+    check_table(gpu, keys, P=P, queries=queries, build="sorted")
