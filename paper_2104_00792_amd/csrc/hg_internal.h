@@ -44,8 +44,8 @@ constexpr uint32_t kProbeKeyCapBytes = 40 * 1024;  // table keys of one window i
 // long bucket is scanned).
 constexpr uint32_t kLongT = 64;
 constexpr uint32_t kMaxUnsorted = 256;
-constexpr int kLongThreads = 256;
-constexpr uint32_t kLongGrid = 2048;
+constexpr int kLongThreads = 1024;
+constexpr uint32_t kLongGrid = 512;  // resident workgroups (two per CU)
 
 // Long buckets of an atomic-path build: appended to long_list.
 hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,

@@ -999,6 +999,11 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
     if (in_lds) copy_to_lds<THREADS, 8>(skeys, tkeys + ka, nk);
     __syncthreads();
     constexpr int kU = 8;
+    // A thread remembers its last query and count: in a sub-bin that holds
+    // a heavy key, most of a thread's queries repeat it.
+    K last_q = K(0);
+    uint32_t last_c = 0;
+    bool have = false;
     for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
       K qv[kU];
 #pragma unroll
@@ -1010,11 +1015,16 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       for (int u = 0; u < kU; ++u) {
         const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
         if (e < m) {
-          const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
-          const uint32_t lo = soff[lb], hi = soff[lb + 1];
-          const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-          c2[qa + e] = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
-                                 : count_equal(tkeys, lo, hi, qv[u], srt);
+          if (!have || qv[u] != last_q) {
+            const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
+            const uint32_t lo = soff[lb], hi = soff[lb + 1];
+            const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
+            last_c = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
+                            : count_equal(tkeys, lo, hi, qv[u], srt);
+            last_q = qv[u];
+            have = true;
+          }
+          c2[qa + e] = last_c;
         }
       }
     }
