@@ -212,6 +212,15 @@ hg_status hg_table_export(const hg_table* table, uint32_t* d_part_offsets,
                           uint32_t* d_bucket_base, uint32_t* d_offsets,
                           void* d_keys, hipStream_t stream);
 
+/* hg_trim_pool -- hand cached device memory back to the system.  The
+ * library allocates tables and workspace from a stream-ordered pool of the
+ * current device that keeps freed blocks for reuse; this releases all but
+ * keep_bytes of the blocks no stream still uses (callers that share the
+ * device with other allocators, such as a serving loop, call it after
+ * freeing tables).  The library also trims the pool by itself when an
+ * allocation fails, then tries once more.  Errors: HG_ERR_HIP. */
+hg_status hg_trim_pool(uint64_t keep_bytes);
+
 /* hg_table_free -- release the table's memory in stream order on the stream
  * it was built on.  Work that uses the table on other streams must be
  * ordered before that stream's later work.  NULL is a no-op. */

@@ -18,7 +18,7 @@ import os
 
 __all__ = [
     "HGError", "Table", "hg_build", "hg_count", "hg_query", "hg_bin_partition",
-    "hg_hash_bucket", "hg_build_batched", "hg_count_batched", "hg_query_batched",
+    "hg_hash_bucket", "hg_build_batched", "hg_count_batched", "hg_query_batched", "hg_trim_pool",
     "lib", "lib_path", "profile",
 ]
 
@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.hg_table_export.restype = i32
     L.hg_table_free.argtypes = [vp]
     L.hg_table_free.restype = None
+    L.hg_trim_pool.argtypes = [u64]
+    L.hg_trim_pool.restype = i32
     L.hg_status_string.argtypes = [i32]
     L.hg_status_string.restype = ctypes.c_char_p
     L.hg_last_error.argtypes = []
@@ -296,6 +298,12 @@ def hg_query_batched(table: Table, queries, query_offsets, out=None, stream=None
     _check(lib().hg_query_batched(table.handle, _dev_ptr(queries), queries.numel(), _dev_ptr(query_offsets),
                                   _dev_ptr(out), _stream(stream)), "hg_query_batched")
     return out
+
+
+def hg_trim_pool(keep_bytes: int = 0):
+    """Hand the library's cached device memory (freed tables and workspace)
+    back to the system, keeping at most ``keep_bytes``."""
+    _check(lib().hg_trim_pool(keep_bytes), "hg_trim_pool")
 
 
 def hg_bin_partition(keys, P: int, out=None, part_offsets=None, stream=None):

@@ -113,6 +113,13 @@ class Allocs {
     e = pool_for(dev, &pool);
     if (e != hipSuccess) return e;
     e = hipMallocFromPoolAsync(p, bytes, pool, s_);
+    if (e == hipErrorOutOfMemory) {
+      // The pool keeps freed blocks; hand back what no stream still uses
+      // and try once more.
+      (void)hipGetLastError();
+      (void)hipMemPoolTrimTo(pool, 0);
+      e = hipMallocFromPoolAsync(p, bytes, pool, s_);
+    }
     if (e == hipSuccess) owned_.push_back(*p);
     return e;
   }
@@ -933,6 +940,15 @@ void hg_table_free(hg_table* table) {
   if (table->d_offsets) (void)hipFreeAsync(table->d_offsets, table->stream);
   if (table->d_meta) (void)hipFreeAsync(table->d_meta, table->stream);
   delete table;
+}
+
+hg_status hg_trim_pool(uint64_t keep_bytes) {
+  int dev = 0;
+  HG_TRY(hipGetDevice(&dev), "hipGetDevice");
+  hipMemPool_t pool;
+  HG_TRY(pool_for(dev, &pool), "memory pool");
+  HG_TRY(hipMemPoolTrimTo(pool, static_cast<size_t>(keep_bytes)), "trim memory pool");
+  return HG_OK;
 }
 
 const char* hg_status_string(hg_status s) {

@@ -268,7 +268,11 @@ class WallClock:
 
 
 class GpuExecutor:
-    def __init__(self, slots: int, device=None):
+    """Requests on `slots` torch streams.  keep_results=False drops each
+    probe's counts once it completes (a long stream would otherwise hold
+    every result in device memory)."""
+
+    def __init__(self, slots: int, device=None, keep_results: bool = True):
         import torch
 
         import paper_2104_00792_amd as hg
@@ -278,27 +282,50 @@ class GpuExecutor:
         self.dev = device or torch.device("cuda:0")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
         self.next = 0
+        self.oom_retries = 0
+        self.keep_results = keep_results
 
     def pick_stream(self):
         s = self.streams[self.next % len(self.streams)]
         self.next += 1
         return s
 
+    def _retry_on_oom(self, fn):
+        """Run fn; if the device is out of memory (both torch's cache and the
+        library's pool keep freed blocks of many sizes), wait for the device,
+        hand both caches back and run it once more."""
+        try:
+            return fn()
+        except (self.hg.HGError, self.torch.cuda.OutOfMemoryError) as e:
+            if isinstance(e, self.hg.HGError) and e.status != 2:
+                raise
+            self.torch.cuda.synchronize()
+            self.torch.cuda.empty_cache()
+            self.hg.hg_trim_pool(0)
+            self.oom_retries += 1
+            return fn()
+
     def build(self, n: int, seed: int, stream):
-        with self.torch.cuda.stream(stream):
-            keys = inputs.uniform_u32_t(n, seed, self.dev)
-            table = self.hg.hg_build(keys, stream=stream)
-            keys.record_stream(stream)
-        return table
+        def run():
+            with self.torch.cuda.stream(stream):
+                keys = inputs.uniform_u32_t(n, seed, self.dev)
+                table = self.hg.hg_build(keys, stream=stream)
+                keys.record_stream(stream)
+            return table
+
+        return self._retry_on_oom(run)
 
     def probe(self, table, table_n: int, table_seed: int, q: int, q_seed: int, stream):
-        with self.torch.cuda.stream(stream):
-            keys = inputs.uniform_u32_t(table_n, table_seed, self.dev)
-            queries = inputs.queries_hit50_t(keys, q, q_seed, self.dev)
-            counts = self.hg.hg_count(table, queries, stream=stream)
-            keys.record_stream(stream)
-            queries.record_stream(stream)
-        return counts
+        def run():
+            with self.torch.cuda.stream(stream):
+                keys = inputs.uniform_u32_t(table_n, table_seed, self.dev)
+                queries = inputs.queries_hit50_t(keys, q, q_seed, self.dev)
+                counts = self.hg.hg_count(table, queries, stream=stream)
+                keys.record_stream(stream)
+                queries.record_stream(stream)
+            return counts
+
+        return self._retry_on_oom(run)
 
     def record(self, stream):
         ev = self.torch.cuda.Event()
@@ -312,7 +339,7 @@ class GpuExecutor:
         return now
 
     def fetch(self, out):
-        return out
+        return out if self.keep_results else None
 
     def free(self, table):
         table.free()
@@ -329,18 +356,34 @@ def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10*
     for r in reqs:
         r.arrival = 0.0
     clock = WallClock()
-    srv = Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots)
+    ex = GpuExecutor(slots, keep_results=False)
+    srv = Server(ex, sizes, seeds, capacity_bytes, slots)
     srv.run(reqs, clock, progress)
     torch.cuda.synchronize()
     closed = latency_report(reqs, clock.now())
-    closed.update(evictions=srv.cache.evictions, rebuilds=srv.rebuilds, peak_reserved_bytes=srv.cache.peak)
+    closed.update(evictions=srv.cache.evictions, rebuilds=srv.rebuilds, peak_reserved_bytes=srv.cache.peak,
+                  oom_retries=ex.oom_retries)
+    _release(srv, ex)
     lam = rate if rate is not None else load * closed["requests_per_s"]
     reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=lam)
     clock = WallClock()
-    srv = Server(GpuExecutor(slots), sizes, seeds, capacity_bytes, slots)
+    ex = GpuExecutor(slots, keep_results=False)
+    srv = Server(ex, sizes, seeds, capacity_bytes, slots)
     srv.run(reqs, clock, progress)
     torch.cuda.synchronize()
     opened = latency_report(reqs, clock.now())
     opened.update(offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,
-                  peak_reserved_bytes=srv.cache.peak)
+                  peak_reserved_bytes=srv.cache.peak, oom_retries=ex.oom_retries)
+    _release(srv, ex)
     return closed, opened, reqs
+
+
+def _release(srv, ex):
+    """Free every resident table and hand the device memory back."""
+    import torch
+
+    for tid in list(srv.cache.entries):
+        ex.free(srv.cache.entries.pop(tid)[0])
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ex.hg.hg_trim_pool(0)

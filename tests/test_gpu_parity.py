@@ -283,3 +283,19 @@ def test_heavy_subbins_shared_by_workgroups(gpu, dtype, P):
     keys = keys[np.argsort(inputs.uniform_u32(keys.size, 62), kind="stable")]  # interleave
     queries = np.concatenate([np.repeat(heavy, 50000), make_keys("uniform", 20000, dtype, 63), keys[:30000]])
     check_table(gpu, keys, P=P, queries=queries, build="sorted")
+
+
+def test_trim_pool_keeps_tables_valid(gpu):
+    """Trimming the library's pool hands back only memory no table holds."""
+    import torch
+
+    keys = make_keys("uniform", 1 << 20, np.uint32, 71)
+    a = gpu.hg_build(to_dev(keys))
+    b = gpu.hg_build(to_dev(keys[: 1 << 19]))
+    b.free()
+    torch.cuda.synchronize()
+    gpu.hg_trim_pool(0)
+    q = inputs.queries_hit50(keys, 5000, 72)
+    got = gpu.hg_count(a, to_dev(q)).cpu().numpy()
+    assert np.array_equal(got, oracle.count(keys, q))
+    a.free()
