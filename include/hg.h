@@ -116,8 +116,9 @@ typedef struct hg_table_desc {
  *   opts    build options (required).
  *   out     receives the new table; set only on HG_OK.
  * Allocates the table and temporary workspace from the library's
- * stream-ordered pool; the call does not synchronize.  n = 0 builds an empty
- * table (every bucket empty, every count 0).  Errors: HG_ERR_INVALID_ARG for
+ * stream-ordered pool (or the allocator of hg_set_allocator); the call does
+ * not synchronize.  n = 0 builds an empty table (every bucket empty, every
+ * count 0).  Errors: HG_ERR_INVALID_ARG for
  * null d_keys with n > 0, null opts/out, n >= 2^32, P not a power of two,
  * a zero ratio without num_buckets, too many buckets, or unknown flags;
  * HG_ERR_UNSUPPORTED for P > 256. */
@@ -221,9 +222,63 @@ hg_status hg_table_export(const hg_table* table, uint32_t* d_part_offsets,
  * allocation fails, then tries once more.  Errors: HG_ERR_HIP. */
 hg_status hg_trim_pool(uint64_t keep_bytes);
 
+/* Device allocator hook (hg_set_allocator).
+ *   alloc(bytes, stream, ctx) returns device memory of at least `bytes`
+ *       bytes on the current device, aligned to 256 bytes and usable by work
+ *       enqueued on `stream` from the moment of the call, or NULL when it
+ *       cannot (the calling entry point then returns HG_ERR_OUT_OF_MEMORY).
+ *   free_fn(ptr, bytes, stream, ctx) takes back a block in stream order: the
+ *       stream's work enqueued before the call may still use it, so the
+ *       block may only be handed to other streams after that work. */
+typedef void* (*hg_alloc_fn)(size_t bytes, hipStream_t stream, void* ctx);
+typedef void (*hg_free_fn)(void* ptr, size_t bytes, hipStream_t stream,
+                           void* ctx);
+
+/* hg_set_allocator -- route every device allocation of the library (table
+ * memory and per-call workspace) through a caller-owned allocator, such as a
+ * framework's caching allocator or an arena sized with hg_workspace_size,
+ * instead of the library's stream-ordered pool.  Both functions null
+ * restores the pool.  The setting is process-wide and applies to calls that
+ * start after it; a table remembers the allocator it was built with and
+ * hg_table_free returns its memory there, so the allocator must outlive its
+ * tables.  Errors: HG_ERR_INVALID_ARG when exactly one function is null.  A
+ * block that is not 256-byte aligned fails the call that received it with
+ * HG_ERR_INVALID_ARG (the block is handed back first). */
+hg_status hg_set_allocator(hg_alloc_fn alloc, hg_free_fn free_fn, void* ctx);
+
+/* Operations that hg_workspace_size can size. */
+typedef enum hg_op {
+  HG_OP_BUILD = 0,          /* hg_build(n keys of kt, opts)                */
+  HG_OP_COUNT = 1,          /* hg_count_ex(table, n queries, flags = aux)  */
+  HG_OP_QUERY = 2,          /* hg_query_ex(table, n queries, flags = aux)  */
+  HG_OP_BUILD_BATCHED = 3,  /* hg_build_batched(n keys, aux tables, opts)  */
+  HG_OP_COUNT_BATCHED = 4,  /* hg_count_batched(table, n queries)          */
+  HG_OP_QUERY_BATCHED = 5   /* hg_query_batched(table, n queries)          */
+} hg_op;
+
+/* hg_workspace_size -- the device memory that one call of `op` with these
+ * arguments allocates, computed on the host without touching the device
+ * (the sizes depend only on the arguments, never on key values).
+ *   *workspace_bytes  temporary blocks, all live at once and handed back
+ *                     before the call returns (in stream order),
+ *   *table_bytes      blocks the new table keeps (builds only; else 0).
+ * Each block is counted rounded up to a multiple of 256 bytes, so an arena
+ * of workspace_bytes + table_bytes serves the call through hg_set_allocator
+ * with any bump allocator that rounds the same way.  Arguments that the call
+ * itself would reject give the same error here.  kt and opts are used by
+ * the builds, table by the probes; aux holds the probe flags for COUNT and
+ * QUERY and the number of tables for BUILD_BATCHED.  Either output may be
+ * null.  Errors: HG_ERR_INVALID_ARG for an unknown op, and those of the
+ * sized call. */
+hg_status hg_workspace_size(hg_op op, const hg_table* table, uint64_t n,
+                            hg_key_type kt, const hg_build_opts* opts,
+                            uint32_t aux, uint64_t* workspace_bytes,
+                            uint64_t* table_bytes);
+
 /* hg_table_free -- release the table's memory in stream order on the stream
- * it was built on.  Work that uses the table on other streams must be
- * ordered before that stream's later work.  NULL is a no-op. */
+ * it was built on (to the allocator it was built with).  Work that uses the
+ * table on other streams must be ordered before that stream's later work.
+ * NULL is a no-op. */
 void hg_table_free(hg_table* table);
 
 /* Human-readable name of a status code (static storage). */

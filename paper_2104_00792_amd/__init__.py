@@ -19,7 +19,7 @@ import os
 __all__ = [
     "HGError", "Table", "hg_build", "hg_count", "hg_query", "hg_bin_partition",
     "hg_hash_bucket", "hg_build_batched", "hg_count_batched", "hg_query_batched", "hg_trim_pool",
-    "lib", "lib_path", "profile",
+    "hg_set_allocator", "hg_workspace_size", "torch_allocator", "lib", "lib_path", "profile",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +36,18 @@ HG_BUILD_SORTED = 2
 # like the table, counted against LDS windows and gathered back.
 HG_PROBE_DIRECT = 1
 HG_PROBE_SORTED = 2
+# Operations sized by hg_workspace_size.
+HG_OP_BUILD = 0
+HG_OP_COUNT = 1
+HG_OP_QUERY = 2
+HG_OP_BUILD_BATCHED = 3
+HG_OP_COUNT_BATCHED = 4
+HG_OP_QUERY_BATCHED = 5
+
+# Allocator hook signatures of include/hg.h.
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = None  # the installed callbacks, kept alive while the library may call them
 
 _lib = None
 
@@ -115,6 +127,11 @@ def lib() -> ctypes.CDLL:
     L.hg_table_free.restype = None
     L.hg_trim_pool.argtypes = [u64]
     L.hg_trim_pool.restype = i32
+    L.hg_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
+    L.hg_set_allocator.restype = i32
+    L.hg_workspace_size.argtypes = [i32, vp, u64, i32, ctypes.POINTER(_BuildOpts), u32,
+                                    ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.hg_workspace_size.restype = i32
     L.hg_status_string.argtypes = [i32]
     L.hg_status_string.restype = ctypes.c_char_p
     L.hg_last_error.argtypes = []
@@ -304,6 +321,70 @@ def hg_trim_pool(keep_bytes: int = 0):
     """Hand the library's cached device memory (freed tables and workspace)
     back to the system, keeping at most ``keep_bytes``."""
     _check(lib().hg_trim_pool(keep_bytes), "hg_trim_pool")
+
+
+def hg_workspace_size(op: int, n: int = 0, key_type: int = HG_KEY_U32, P: int = 1, ratio=(1, 1),
+                      num_buckets: int = 0, flags: int = 0, table: Table | None = None, aux: int = 0):
+    """(workspace bytes, table bytes) that one call of ``op`` allocates,
+    computed on the host without touching the device.  Builds take n,
+    key_type, P, ratio, num_buckets and flags (and ``aux`` = number of tables
+    for HG_OP_BUILD_BATCHED); probes take ``table``, n = number of queries and
+    ``aux`` = probe flags."""
+    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets)
+    ws, tb = ctypes.c_uint64(), ctypes.c_uint64()
+    h = table.handle if table is not None else None
+    _check(lib().hg_workspace_size(op, h, n, key_type, ctypes.byref(opts), aux, ctypes.byref(ws), ctypes.byref(tb)),
+           "hg_workspace_size")
+    return ws.value, tb.value
+
+
+def hg_set_allocator(alloc=None, free=None):
+    """Route the library's device allocations through Python callables:
+    ``alloc(nbytes, stream_handle) -> device address (int) or 0`` and
+    ``free(address, nbytes, stream_handle)``, with the stream-ordered contract
+    of include/hg.h.  No arguments restores the library's own pool.  Tables
+    built under an allocator return their memory to it when freed, so keep the
+    callables usable until those tables are freed."""
+    global _hooks
+    if (alloc is None) != (free is None):
+        raise ValueError("hg_set_allocator takes both callables or neither")
+    if alloc is None:
+        _check(lib().hg_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "hg_set_allocator")
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        return alloc(nbytes, stream or 0) or None
+
+    def _free(ptr, nbytes, stream, ctx):
+        free(ptr, nbytes, stream or 0)
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().hg_set_allocator(hooks[0], hooks[1], None), "hg_set_allocator")
+    # Older hooks stay referenced: tables built under them still free through them.
+    _hooks = (hooks, _hooks)
+
+
+class torch_allocator:
+    """``with torch_allocator(): ...`` serves the library's device memory from
+    torch's caching allocator (the stream passed by the library is the one the
+    block is used on), then restores the library's pool."""
+
+    def __enter__(self):
+        torch = _torch()
+        dev = torch.cuda.current_device()
+
+        def alloc(nbytes, stream):
+            return torch.cuda.caching_allocator_alloc(nbytes, dev, stream)
+
+        def free(ptr, nbytes, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        hg_set_allocator(alloc, free)
+        return self
+
+    def __exit__(self, *exc):
+        hg_set_allocator()
+        return False
 
 
 def hg_bin_partition(keys, P: int, out=None, part_offsets=None, stream=None):

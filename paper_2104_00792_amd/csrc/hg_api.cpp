@@ -17,6 +17,20 @@
 
 #include "hg_internal.h"
 
+// Caller-supplied device allocator (hg_set_allocator); empty = the pool.
+struct AllocHook {
+  hg_alloc_fn alloc = nullptr;
+  hg_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+};
+
+// A device block and the allocator it goes back to.
+struct TableBlock {
+  void* p;
+  size_t bytes;
+  AllocHook hook;
+};
+
 struct hg_table {
   int device;
   hipStream_t stream;
@@ -37,6 +51,7 @@ struct hg_table {
   uint32_t nd1;             // level-1 digits
   uint32_t log2S;           // sub-bins of 2^log2S buckets
   bool batched;             // P caller-defined tables (hg_build_batched)
+  std::vector<TableBlock> blocks;  // keys, offsets and metadata, and where they go back
   std::mutex mu;
   bool have_num_buckets;
   uint64_t num_buckets;
@@ -96,22 +111,85 @@ hipError_t pool_for(int dev, hipMemPool_t* out) {
   return hipSuccess;
 }
 
+// ------------------------------------------------------- allocator hook
+std::mutex g_hook_mu;
+AllocHook g_hook;
+
+AllocHook current_hook() {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  return g_hook;
+}
+
+// Dry run of one call (hg_workspace_size): blocks are counted and handed out
+// as addresses that are never dereferenced on the host, and nothing reaches
+// the device.
+struct Measure {
+  uint64_t workspace = 0;
+  uint64_t table = 0;
+  uintptr_t next = uintptr_t(1) << 44;
+};
+thread_local Measure* t_measure = nullptr;
+
+uint64_t round256(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+
+hipError_t current_device(int* dev) {
+  if (t_measure) {
+    *dev = 0;
+    return hipSuccess;
+  }
+  return hipGetDevice(dev);
+}
+
+void free_block(const TableBlock& b, hipStream_t s) {
+  if (b.p == nullptr || t_measure) return;
+  if (b.hook.free_fn)
+    b.hook.free_fn(b.p, b.bytes, s, b.hook.ctx);
+  else
+    (void)hipFreeAsync(b.p, s);
+}
+
+// Outcome of one allocation: a HIP status, or a block from the caller's
+// allocator that breaks its alignment contract.
+struct AllocResult {
+  hipError_t e;
+  bool misaligned;
+};
+
 // Allocations of one call; frees everything still owned on destruction.
 class Allocs {
  public:
-  explicit Allocs(hipStream_t s) : s_(s) {}
+  explicit Allocs(hipStream_t s) : s_(s), hook_(current_hook()) {}
   ~Allocs() {
-    for (void* p : owned_) (void)hipFreeAsync(p, s_);
+    for (const TableBlock& b : owned_) free_block(b, s_);
   }
-  hipError_t get(void** p, size_t bytes) {
+  AllocResult get(void** p, size_t bytes) {
     *p = nullptr;
-    if (bytes == 0) return hipSuccess;
+    if (bytes == 0) return {hipSuccess, false};
+    if (t_measure) {
+      const uint64_t r = round256(bytes);
+      *p = reinterpret_cast<void*>(t_measure->next);
+      t_measure->next += r;
+      t_measure->workspace += r;
+      owned_.push_back({*p, bytes, hook_});
+      return {hipSuccess, false};
+    }
+    if (hook_.alloc) {
+      *p = hook_.alloc(bytes, s_, hook_.ctx);
+      if (*p == nullptr) return {hipErrorOutOfMemory, false};
+      if (reinterpret_cast<uintptr_t>(*p) & 255u) {
+        hook_.free_fn(*p, bytes, s_, hook_.ctx);
+        *p = nullptr;
+        return {hipSuccess, true};
+      }
+      owned_.push_back({*p, bytes, hook_});
+      return {hipSuccess, false};
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return {e, false};
     hipMemPool_t pool;
     e = pool_for(dev, &pool);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return {e, false};
     e = hipMallocFromPoolAsync(p, bytes, pool, s_);
     if (e == hipErrorOutOfMemory) {
       // The pool keeps freed blocks; hand back what no stream still uses
@@ -120,22 +198,31 @@ class Allocs {
       (void)hipMemPoolTrimTo(pool, 0);
       e = hipMallocFromPoolAsync(p, bytes, pool, s_);
     }
-    if (e == hipSuccess) owned_.push_back(*p);
-    return e;
+    if (e == hipSuccess) owned_.push_back({*p, bytes, hook_});
+    return {e, false};
   }
-  // Stop owning p (it now belongs to a table).
-  void release(void* p) {
-    for (auto& q : owned_)
-      if (q == p) q = nullptr;
-    std::vector<void*> keep;
-    for (void* q : owned_)
-      if (q) keep.push_back(q);
+  // Stop owning p: it now belongs to a table.
+  TableBlock release(void* p) {
+    TableBlock out{nullptr, 0, hook_};
+    std::vector<TableBlock> keep;
+    for (const TableBlock& b : owned_) {
+      if (b.p == p && p != nullptr)
+        out = b;
+      else
+        keep.push_back(b);
+    }
     owned_.swap(keep);
+    if (t_measure && out.p) {
+      t_measure->workspace -= round256(out.bytes);
+      t_measure->table += round256(out.bytes);
+    }
+    return out;
   }
 
  private:
   hipStream_t s_;
-  std::vector<void*> owned_;
+  AllocHook hook_;
+  std::vector<TableBlock> owned_;
 };
 
 // -------------------------------------------------------------- profiling
@@ -155,14 +242,17 @@ hipEvent_t take_event() {
     g_events.pop_back();
     return e;
   }
+  // Timing only: a device-scope release keeps the record from writing back
+  // and invalidating the caches between the bracketed kernels.
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
 class ProfScope {
  public:
   ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+    if (t_measure) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     a_ = take_event();
@@ -187,20 +277,27 @@ class ProfScope {
     hipError_t _e;                                                          \
     {                                                                       \
       ProfScope _ps(name, stream);                                          \
-      _e = (call);                                                          \
+      _e = t_measure ? hipSuccess : (call);                                 \
     }                                                                       \
     if (_e != hipSuccess) return fail_hip(_e, name);                        \
-    if (debug_sync()) {                                                     \
+    if (debug_sync() && !t_measure) {                                       \
       _e = hipStreamSynchronize(stream);                                    \
       std::fprintf(stderr, "[hg] %s -> %s\n", name, hipGetErrorString(_e)); \
       if (_e != hipSuccess) return fail_hip(_e, name);                      \
     }                                                                       \
   } while (0)
 
-#define HG_TRY(expr, what)                          \
-  do {                                              \
-    hipError_t _e = (expr);                         \
-    if (_e != hipSuccess) return fail_hip(_e, what); \
+hg_status to_status(hipError_t e, const char* what) { return e == hipSuccess ? HG_OK : fail_hip(e, what); }
+
+hg_status to_status(AllocResult r, const char* what) {
+  if (r.misaligned) return fail(HG_ERR_INVALID_ARG, "%s: the allocator returned a block not aligned to 256 bytes", what);
+  return to_status(r.e, what);
+}
+
+#define HG_TRY(expr, what)                      \
+  do {                                          \
+    hg_status _s = to_status((expr), what);     \
+    if (_s != HG_OK) return _s;                 \
   } while (0)
 
 uint32_t log2_of(uint32_t P) {
@@ -629,7 +726,7 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   const size_t ks = key_bytes(kt);
   const uint32_t num_tiles = hg::div_up(n, hg::kTileKeys);
   int device = 0;
-  HG_TRY(hipGetDevice(&device), "hipGetDevice");
+  HG_TRY(current_device(&device), "hipGetDevice");
 
   Allocs mem(stream);
   void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr;
@@ -717,9 +814,7 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   t->batched = false;
   t->have_num_buckets = false;
   t->num_buckets = 0;
-  mem.release(keys_out);
-  mem.release(offsets);
-  mem.release(meta);
+  t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
   *out = t;
   return HG_OK;
 }
@@ -765,7 +860,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   const uint32_t n32 = static_cast<uint32_t>(n);
   const size_t ks = key_bytes(kt);
   int device = 0;
-  HG_TRY(hipGetDevice(&device), "hipGetDevice");
+  HG_TRY(current_device(&device), "hipGetDevice");
   Allocs mem(stream);
   void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr, *longv = nullptr;
   const size_t meta_bytes =
@@ -833,9 +928,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   t->batched = true;
   t->have_num_buckets = false;
   t->num_buckets = 0;
-  mem.release(keys_out);
-  mem.release(offsets);
-  mem.release(meta);
+  t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
   *out = t;
   return HG_OK;
 }
@@ -936,10 +1029,48 @@ hg_status hg_table_export(const hg_table* table, uint32_t* d_part_offsets, uint3
 
 void hg_table_free(hg_table* table) {
   if (table == nullptr) return;
-  if (table->d_keys) (void)hipFreeAsync(table->d_keys, table->stream);
-  if (table->d_offsets) (void)hipFreeAsync(table->d_offsets, table->stream);
-  if (table->d_meta) (void)hipFreeAsync(table->d_meta, table->stream);
+  for (const TableBlock& b : table->blocks) free_block(b, table->stream);
   delete table;
+}
+
+hg_status hg_set_allocator(hg_alloc_fn alloc, hg_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(HG_ERR_INVALID_ARG, "hg_set_allocator takes both functions or neither");
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  g_hook.alloc = alloc;
+  g_hook.free_fn = free_fn;
+  g_hook.ctx = alloc ? ctx : nullptr;
+  return HG_OK;
+}
+
+hg_status hg_workspace_size(hg_op op, const hg_table* table, uint64_t n, hg_key_type kt, const hg_build_opts* opts,
+                            uint32_t aux, uint64_t* workspace_bytes, uint64_t* table_bytes) {
+  // Run the call itself in dry-run mode: same argument checks, same sizes,
+  // nothing enqueued.  The placeholder pointers only pass the null checks.
+  Measure m;
+  struct Scope {
+    explicit Scope(Measure* mm) : prev(t_measure) { t_measure = mm; }
+    ~Scope() { t_measure = prev; }
+    Measure* prev;
+  } scope(&m);
+  void* ph = reinterpret_cast<void*>(uintptr_t(1) << 43);
+  uint32_t* ph32 = static_cast<uint32_t*>(ph);
+  hg_table* t = nullptr;
+  hg_status st;
+  switch (op) {
+    case HG_OP_BUILD: st = hg_build(ph, n, kt, opts, nullptr, &t); break;
+    case HG_OP_COUNT: st = hg_count_ex(table, ph, n, ph32, aux, nullptr); break;
+    case HG_OP_QUERY: st = hg_query_ex(table, ph, n, static_cast<uint8_t*>(ph), aux, nullptr); break;
+    case HG_OP_BUILD_BATCHED: st = hg_build_batched(ph, n, kt, aux, ph32, opts, nullptr, &t); break;
+    case HG_OP_COUNT_BATCHED: st = hg_count_batched(table, ph, n, ph32, ph32, nullptr); break;
+    case HG_OP_QUERY_BATCHED: st = hg_query_batched(table, ph, n, ph32, static_cast<uint8_t*>(ph), nullptr); break;
+    default: return fail(HG_ERR_INVALID_ARG, "unknown op %d", static_cast<int>(op));
+  }
+  delete t;  // its blocks are placeholders: nothing to free
+  if (st != HG_OK) return st;
+  if (workspace_bytes) *workspace_bytes = m.workspace;
+  if (table_bytes) *table_bytes = m.table;
+  return HG_OK;
 }
 
 hg_status hg_trim_pool(uint64_t keep_bytes) {

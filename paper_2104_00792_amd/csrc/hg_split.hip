@@ -637,20 +637,21 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     // Two 16-bit values per word: first each key's bucket in the sub-bin
     // (R <= kSMax), then its position (m <= 65535).
     uint32_t pos[(REG + 1) / 2];
-    if (regs) {
+    if (regs && m > 0) {
+      // Every load first, all in flight at once: a lane past the sub-bin's
+      // end re-reads its last key (its counter add is skipped), so nothing
+      // between the loads depends on a branch.
+      const uint32_t last = m - 1;
+#pragma unroll
+      for (int j = 0; j < REG; ++j) v[j] = in[sb.kA + min(static_cast<uint32_t>(j) * THREADS + t, last)];
 #pragma unroll
       for (int j = 0; j < REG; ++j) {
         const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
-        v[j] = K(0);
-        uint32_t lb = 0;
-        if (e < m) {
-          v[j] = in[sb.kA + e];
-          lb = bucket_of(v[j], log2P, sd) - sb.gA;
-          atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
-        }
+        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
+        if (e < m) atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
         if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
       }
-    } else {
+    } else if (!regs) {
       for (uint32_t e = t; e < m; e += THREADS) {
         const uint32_t lb = bucket_of(in[sb.kA + e], log2P, sd) - sb.gA;
         atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));

@@ -53,7 +53,7 @@ def test_header_declares_the_core_calls():
     fns = declared_functions()
     for name in ["hg_build", "hg_count", "hg_query", "hg_bin_partition", "hg_hash_bucket", "hg_table_info",
                  "hg_table_export", "hg_table_free", "hg_status_string", "hg_last_error", "hg_build_batched",
-                 "hg_count_batched", "hg_query_batched"]:
+                 "hg_count_batched", "hg_query_batched", "hg_set_allocator", "hg_workspace_size"]:
         assert name in fns
 
 
@@ -165,3 +165,65 @@ def test_build_batched_rejects(lib, case, expected):
 def test_batched_probe_rejects(lib):
     assert lib.hg_count_batched(None, FAKE, 10, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
     assert lib.hg_query_batched(None, FAKE, 10, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+HG_OP_BUILD, HG_OP_COUNT, HG_OP_QUERY, HG_OP_BUILD_BATCHED, HG_OP_COUNT_BATCHED, HG_OP_QUERY_BATCHED = range(6)
+
+
+def workspace(lib, op, n=0, kt=0, P=1, num=1, den=1, flags=0, V=0, aux=0, table=None):
+    lib.hg_workspace_size.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.POINTER(Opts), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    o = Opts(P, num, den, flags, V)
+    ws, tb = ctypes.c_uint64(7), ctypes.c_uint64(7)
+    st = lib.hg_workspace_size(op, table, n, kt, ctypes.byref(o), aux, ctypes.byref(ws), ctypes.byref(tb))
+    return st, ws.value, tb.value
+
+
+def test_set_allocator_takes_both_functions_or_neither(lib):
+    lib.hg_set_allocator.argtypes = [ALLOC_FN, FREE_FN, ctypes.c_void_p]
+    assert lib.hg_set_allocator(ALLOC_FN(lambda n, s, c: None), FREE_FN(), None) == HG_ERR_INVALID_ARG
+    assert lib.hg_set_allocator(ALLOC_FN(), FREE_FN(lambda p, n, s, c: None), None) == HG_ERR_INVALID_ARG
+    assert lib.hg_set_allocator(ALLOC_FN(), FREE_FN(), None) == HG_OK  # the library's pool
+
+
+@pytest.mark.parametrize("n, kt, P, num, den, V", [
+    (0, 0, 1, 1, 1, 0), (1, 0, 16, 1, 1, 0), (5000, 1, 1, 1, 2, 0), (1 << 20, 0, 1, 0, 0, 1 << 20),
+    (1 << 22, 0, 16, 1, 1, 0), (1 << 28, 0, 16, 1, 1, 0), (1 << 27, 1, 1, 1, 2, 0)])
+def test_workspace_size_of_a_build_needs_no_device(lib, n, kt, P, num, den, V):
+    """The dry run makes no HIP call.  The table keeps its keys, its offsets
+    over floor(n * num / den) + P buckets (or V + 1) and a small metadata
+    block, each rounded up to 256 bytes."""
+    st, ws, tb = workspace(lib, HG_OP_BUILD, n=n, kt=kt, P=P, num=num, den=den, V=V)
+    assert st == HG_OK, lib.hg_last_error()
+    ks = 4 if kt == 0 else 8
+    bound = V if V else n * num // den + P
+    floor = n * ks + (bound + 1) * 4
+    assert floor <= tb <= floor + 3 * 256 + (1 << 16)
+    assert tb % 256 == 0 and ws % 256 == 0
+    if n >= (1 << 22):  # sorted build: two split buffers of n keys at least
+        assert ws >= 2 * n * ks
+
+
+def test_workspace_size_grows_with_n(lib):
+    prev = (0, 0)
+    for n in [0, 1, 100, 4096, 1 << 16, 1 << 20, 1 << 24]:
+        st, ws, tb = workspace(lib, HG_OP_BUILD, n=n, P=16)
+        assert st == HG_OK
+        assert tb >= prev[1]
+        prev = (ws, tb)
+
+
+def test_workspace_size_mirrors_the_calls_errors(lib):
+    assert workspace(lib, HG_OP_BUILD, n=10, P=3)[0] == HG_ERR_INVALID_ARG
+    assert workspace(lib, HG_OP_BUILD, n=10, P=512)[0] == HG_ERR_UNSUPPORTED
+    assert workspace(lib, HG_OP_BUILD, n=1 << 32)[0] == HG_ERR_INVALID_ARG
+    assert workspace(lib, HG_OP_BUILD, n=10, num=0)[0] == HG_ERR_INVALID_ARG
+    assert workspace(lib, HG_OP_COUNT, n=10)[0] == HG_ERR_INVALID_ARG          # no table
+    assert workspace(lib, HG_OP_QUERY_BATCHED, n=10)[0] == HG_ERR_INVALID_ARG  # no table
+    assert workspace(lib, HG_OP_BUILD_BATCHED, n=10, aux=0)[0] == HG_ERR_INVALID_ARG  # no tables
+    assert workspace(lib, 17)[0] == HG_ERR_INVALID_ARG
+    st, ws, tb = workspace(lib, HG_OP_BUILD_BATCHED, n=1 << 20, aux=4096)
+    assert st == HG_OK and tb >= (1 << 20) * 4 + ((1 << 20) + 4096 + 1) * 4
