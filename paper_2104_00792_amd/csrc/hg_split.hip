@@ -990,30 +990,51 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   __syncthreads();
 
   if (R <= Wb) {
-    // The whole sub-bin is one window: load it, then stream the queries
-    // through it (kU loads in flight per thread), each counted and written
-    // once.
-    copy_to_lds<THREADS, 8>(soff, offsets + sb.gA, R + 1);
-    __syncthreads();
-    const uint32_t ka = soff[0], nk = soff[R] - ka;
+    // The whole sub-bin is one window.  Its offsets, its keys and the first
+    // queries are all requested before any of them is waited on (one memory
+    // round trip per workgroup instead of one per array); the key range comes
+    // from two uniform loads.  Lanes past an array's end re-read its last
+    // element and store nothing.
+    if (m == 0) return;  // whole workgroup
+    constexpr int kUO = ((1u << kMaxLog2W) + THREADS) / THREADS;  // R + 1 <= 2^kMaxLog2W + 1 offsets
+    constexpr int kUK = (KCAP + THREADS - 1) / THREADS;
+    constexpr int kUQ = 10;
+    uint32_t xo[kUO];
+    K xk[kUK], qv[kUQ];
+#pragma unroll
+    for (int u = 0; u < kUO; ++u) xo[u] = offsets[sb.gA + min(static_cast<uint32_t>(u) * THREADS + t, R)];
+#pragma unroll
+    for (int u = 0; u < kUQ; ++u) qv[u] = q2[qa + min(static_cast<uint32_t>(u) * THREADS + t, m - 1)];
+    // The key loads wait for the key range; the loads above are in flight
+    // meanwhile.
+    const uint32_t ka = offsets[sb.gA], nk = offsets[sb.gB] - ka;
     const bool in_lds = nk <= KCAP;
-    if (in_lds) copy_to_lds<THREADS, 8>(skeys, tkeys + ka, nk);
+    const bool load_keys = in_lds && nk > 0;
+    if (load_keys) {
+#pragma unroll
+      for (int u = 0; u < kUK; ++u) xk[u] = tkeys[ka + min(static_cast<uint32_t>(u) * THREADS + t, nk - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kUO; ++u) {
+      const uint32_t i = static_cast<uint32_t>(u) * THREADS + t;
+      if (i <= R) soff[i] = xo[u];
+    }
+    if (load_keys) {
+#pragma unroll
+      for (int u = 0; u < kUK; ++u) {
+        const uint32_t i = static_cast<uint32_t>(u) * THREADS + t;
+        if (i < nk) skeys[i] = xk[u];
+      }
+    }
     __syncthreads();
-    constexpr int kU = 8;
     // A thread remembers its last query and count: in a sub-bin that holds
     // a heavy key, most of a thread's queries repeat it.
     K last_q = K(0);
     uint32_t last_c = 0;
     bool have = false;
-    for (uint32_t c0 = 0; c0 < m; c0 += THREADS * kU) {
-      K qv[kU];
+    for (uint32_t c0 = 0;;) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        qv[u] = e < m ? q2[qa + e] : K(0);
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < kUQ; ++u) {
         const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
         if (e < m) {
           if (!have || qv[u] != last_q) {
@@ -1028,6 +1049,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
           c2[qa + e] = last_c;
         }
       }
+      c0 += THREADS * kUQ;
+      if (c0 >= m) break;
+#pragma unroll
+      for (int u = 0; u < kUQ; ++u) qv[u] = q2[qa + min(c0 + static_cast<uint32_t>(u) * THREADS + t, m - 1)];
     }
     return;
   }
