@@ -74,20 +74,20 @@ def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> f
         "lds_build": 2 * ks * n + 4 * B,            # keys in, keys out, offsets out
         # probe, sorted path
         "qsplit1_count": ks * q,                    # read queries
-        "qsplit1_scatter": (2 * ks + 4) * q,        # queries in and out, permutation out
+        "qsplit1_scatter": (2 * ks + 2) * q,        # queries in and out, 16-bit tile slots out
         "qsplit2_count": ks * q,
-        "qsplit2_scatter": (2 * ks + 4) * q,
+        "qsplit2_scatter": (2 * ks + 2) * q,
         "lds_probe": ks * q + 4 * B + ks * n + 4 * q,  # queries, offsets, table keys, counts out
-        "qgather2": 12 * q,                         # permutation, counts in, counts out
-        "qgather1": 12 * q,
+        "qgather2": 10 * q,                         # tile slots, counts in, counts out
+        "qgather1": 10 * q,
         # batched tables
         "bsplit_count": ks * n,
         "bsplit_scatter": 2 * ks * n,
         "blds_build": 2 * ks * n + 4 * B,
         "bqsplit_count": ks * q,
-        "bqsplit_scatter": (2 * ks + 4) * q,
+        "bqsplit_scatter": (2 * ks + 2) * q,
         "blds_probe": ks * q + 4 * B + ks * n + 4 * q,
-        "bqgather": 12 * q,
+        "bqgather": 10 * q,
         # atomic path and direct probe
         "zero_counts": 4 * (B + 1),                 # counters written
         "bucket_hist": ks * n + 4 * B,              # keys in, counters out once

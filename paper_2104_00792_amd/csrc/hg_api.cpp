@@ -424,7 +424,8 @@ uint32_t probe_log2W(hg_key_type kt, uint64_t n, uint64_t buckets) {
 // The two splits of n keys (or queries) against layout (log2P, desc): the
 // level-1 scatter into buf1 (level-1 counts already scanned and the plan
 // written), then level-2 counts, scan and scatter into buf2.  perm1 / perm2
-// (probes) receive each key's output position in the level it moves in.
+// (probes) receive each key's slot in its split tile at that level, which
+// the tile gathers invert.
 struct SplitBufs {
   uint32_t* counts1;
   uint32_t* bsums;
@@ -439,8 +440,8 @@ struct SplitBufs {
 };
 
 hg_status split_two_levels(const void* src, uint32_t n, hg_key_type kt, const SplitParams& sp, uint32_t log2P,
-                           uint32_t P, const hg::PartDesc* desc, const SplitBufs& w, uint32_t* perm1,
-                           uint32_t* perm2, const char* const names[4], hipStream_t s) {
+                           uint32_t P, const hg::PartDesc* desc, const SplitBufs& w, uint16_t* perm1,
+                           uint16_t* perm2, const char* const names[4], hipStream_t s) {
   const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
   HG_LAUNCH(names[0], s,
             hg::launch_msplit(kt, 1, hg::OP_SCATTER, dig1, src, n, 0, nullptr, sp.nd1, log2P, P, desc, sp.sh1,
@@ -556,8 +557,8 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   if (st != HG_OK) return st;
   void *c2v = nullptr, *p1v = nullptr, *p2v = nullptr;
   HG_TRY(mem.get(&c2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate split-order counts");
-  HG_TRY(mem.get(&p1v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-1 permutation");
-  HG_TRY(mem.get(&p2v, std::max<uint64_t>(q, 1) * sizeof(uint32_t)), "allocate level-2 permutation");
+  HG_TRY(mem.get(&p1v, std::max<uint64_t>(q, 1) * sizeof(uint16_t)), "allocate level-1 permutation");
+  HG_TRY(mem.get(&p2v, std::max<uint64_t>(q, 1) * sizeof(uint16_t)), "allocate level-2 permutation");
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   const int dig1 = sp.mode == 0 ? hg::DIG_PART : hg::DIG_COARSE;
   const uint32_t max_subbins = w.max_subbins;
@@ -570,8 +571,8 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
             hg::launch_plan(w.counts1, w.tiles1, sp.nd1, q, sp.mode, t->d_bucket_base, t->d_bucket_base + t->P, nullptr,
                             sp.sh1, sp.log2S, tile2, w.max_tiles2, w.max_subbins, nullptr, w.plan, s));
   uint32_t* c2 = static_cast<uint32_t*>(c2v);
-  uint32_t* perm1 = static_cast<uint32_t*>(p1v);
-  uint32_t* perm2 = static_cast<uint32_t*>(p2v);
+  uint16_t* perm1 = static_cast<uint16_t*>(p1v);
+  uint16_t* perm2 = static_cast<uint16_t*>(p2v);
   static const char* const kNames[4] = {"qsplit1_scatter", "qsplit2_count", "qsplit2_scan", "qsplit2_scatter"};
   st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, w, perm1, perm2, kNames, s);
   if (st != HG_OK) return st;
@@ -583,8 +584,10 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   // The level-1 buffer is dead once the level-2 split has read it: it takes
   // the counts in level-1 order (q words fit in q keys).
   uint32_t* c1 = static_cast<uint32_t*>(w.buf1);
-  HG_LAUNCH("qgather2", s, hg::launch_perm_gather(perm2, c2, q, c1, false, s));
-  HG_LAUNCH("qgather1", s, hg::launch_perm_gather(perm1, c1, q, out, !count, s));
+  HG_LAUNCH("qgather2", s,
+            hg::launch_tile_gather(kt, 2, perm2, c2, q, w.max_tiles2, w.plan, 0, w.counts2, c1, false, s));
+  HG_LAUNCH("qgather1", s,
+            hg::launch_tile_gather(kt, 1, perm1, c1, q, 0, nullptr, sp.nd1, w.counts1, out, !count, s));
   return HG_OK;
 }
 
@@ -642,9 +645,10 @@ hg_status alloc_l2(Allocs& mem, uint64_t n, hg_key_type kt, uint32_t nseg, uint6
 }
 
 // Count, scan and scatter of the segments of w.plan (one descriptor per
-// segment) from src into w.buf2; perm (probes) receives output positions.
+// segment) from src into w.buf2; perm (probes) receives each key's slot in
+// its split tile.
 hg_status split_segments(const void* src, uint32_t n, hg_key_type kt, uint32_t log2S, const hg::PartDesc* desc,
-                         const L2Bufs& w, uint32_t* perm, const char* const names[3], hipStream_t s) {
+                         const L2Bufs& w, uint16_t* perm, const char* const names[3], hipStream_t s) {
   HG_LAUNCH(names[0], s,
             hg::launch_msplit(kt, 2, hg::OP_COUNT, hg::DIG_SUB, src, n, w.max_tiles2, w.plan, 0, 0, 1, desc, log2S,
                               w.counts2, nullptr, nullptr, s));
@@ -671,10 +675,10 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   if (st != HG_OK) return st;
   void *qov = nullptr, *pv = nullptr, *c2v = nullptr;
   HG_TRY(mem.get(&qov, (static_cast<uint64_t>(T) + 1) * sizeof(uint32_t)), "allocate query offsets");
-  HG_TRY(mem.get(&pv, q * sizeof(uint32_t)), "allocate permutation");
+  HG_TRY(mem.get(&pv, q * sizeof(uint16_t)), "allocate permutation");
   HG_TRY(mem.get(&c2v, q * sizeof(uint32_t)), "allocate split-order counts");
   uint32_t* qo = static_cast<uint32_t*>(qov);
-  uint32_t* perm = static_cast<uint32_t*>(pv);
+  uint16_t* perm = static_cast<uint16_t*>(pv);
   uint32_t* c2 = static_cast<uint32_t*>(c2v);
   const uint32_t tile2 = static_cast<uint32_t>(hg::l2_tile_keys(kt));
   HG_LAUNCH("bq_offsets", s, hg::launch_batch_layout(d_qo, T, q32, 1, 1, qo, nullptr, nullptr, s));
@@ -691,7 +695,8 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q32, 0, 1, t->d_desc, t->d_offsets,
                                  t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound),
                                  static_cast<uint32_t*>(qv), c2, s));
-  HG_LAUNCH("bqgather", s, hg::launch_perm_gather(perm, c2, q32, d_out, !count, s));
+  HG_LAUNCH("bqgather", s,
+            hg::launch_tile_gather(kt, 2, perm, c2, q32, w.max_tiles2, w.plan, 0, w.counts2, d_out, !count, s));
   return HG_OK;
 }
 

@@ -103,14 +103,17 @@ enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1 };
 // bucket >> shift, capped at nd - 1), DIG_SUB (bucket offset in the segment
 // >> shift, capped).  COUNT writes per-tile digit counts; SCATTER moves `in`
 // to `out` using the scanned counts and, when perm is not null, writes
-// perm[i] = output position of in[i].
+// perm[i] = slot of in[i] among its tile's keys in digit order.
 hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
                          const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
-                         uint32_t shift, uint32_t* counts, void* out, uint32_t* perm, hipStream_t s);
+                         uint32_t shift, uint32_t* counts, void* out, uint16_t* perm, hipStream_t s);
 
-// out[i] = src[perm[i]] for i < n (u32), or src[perm[i]] != 0 as bytes.
-hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
-                              hipStream_t s);
+// Inverse of a split (same level, tiles, plan and scanned counts) applied to
+// u32 values: out[i] = src[position of key i after the split], or that value
+// != 0 as bytes.  perm as written by the split's SCATTER.
+hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const uint32_t* src, uint32_t n,
+                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan, void* out,
+                              bool found, hipStream_t s);
 
 // Plan of the level-2 split, written into `plan` (plan_bytes(nseg,
 // max_tiles, max_subbins) bytes; the level-2 grid is max_tiles, the sub-bin

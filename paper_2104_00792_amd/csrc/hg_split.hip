@@ -97,11 +97,52 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
   return x * q + min(x, r) + b / kXcd;
 }
 
+// Where split tile blockIdx.x lies: its segment (plan) or the single segment
+// [0, n) with nd digits and gridDim.x tiles, the digit count D, the tiles T
+// and count base cb of the segment, and the tile's keys [base + head, base +
+// tail).  The tiles of a segment start at its first key rounded down to
+// kTileAlign keys, so that every interior tile takes 16-byte loads; the first
+// and last tiles mask what lies outside the segment.  False: no tile (the
+// workgroup exits).
+struct TileLoc {
+  uint32_t D, T, k0, k1, cb, gs, tl, seg, base, head, tail;
+};
+
+__device__ __forceinline__ bool tile_loc(const SegPlan* plan, uint32_t nd, uint32_t n, uint32_t tile, TileLoc& L) {
+  L.D = nd;
+  L.T = gridDim.x;
+  L.k0 = 0;
+  L.k1 = n;
+  L.cb = 0;
+  L.gs = 0;
+  L.seg = 0;
+  if (plan != nullptr) {
+    const uint32_t G = plan->total_tiles;
+    if (blockIdx.x >= G) return false;
+    const uint32_t b = xcd_tile(blockIdx.x, G);
+    L.seg = plan->tile_seg[b];
+    L.tl = b - plan->tile_first[L.seg];
+    L.D = plan->D[L.seg];
+    L.T = plan->T[L.seg];
+    L.k0 = plan->key0[L.seg];
+    L.k1 = plan->key0[L.seg + 1];
+    L.cb = plan->cbase[L.seg];
+    L.gs = plan->g0[L.seg];
+  } else {
+    L.tl = xcd_tile(blockIdx.x, gridDim.x);
+  }
+  L.base = (L.k0 & ~(kTileAlign - 1)) + L.tl * tile;
+  L.head = L.base < L.k0 ? L.k0 - L.base : 0u;
+  L.tail = min(tile, L.k1 - L.base);
+  return true;
+}
+
 // One split pass over a tile: per-tile digit counts (COUNT), or the move of
 // the tile's keys to their digit runs (SCATTER).  SCATTER ranks each key by
 // one LDS atomic on the tile histogram, stages the tile in LDS in digit
 // order and writes every run with consecutive lanes; when `perm` is given it
-// also records, in input order, the output position of every key.
+// also records, in input order, every key's slot in that staging order (its
+// index among the tile's keys sorted by digit, below 2^16).
 // 1024-thread workgroups are sized for two per CU (eight waves per SIMD, so
 // at most 64 VGPRs), smaller ones for at least four waves per SIMD.
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP, int DIG>
@@ -109,7 +150,7 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
                                                     const SegPlan* __restrict__ plan, uint32_t nd, uint32_t log2P,
                                                     uint32_t P, const PartDesc* __restrict__ desc, uint32_t shift,
                                                     uint32_t* __restrict__ counts, K* __restrict__ out,
-                                                    uint32_t* __restrict__ perm) {
+                                                    uint16_t* __restrict__ perm) {
   constexpr int TILE = THREADS * ITEMS;
   constexpr bool kCount = OP == OP_COUNT;
   constexpr int kDPT = (MAXD + THREADS - 1) / THREADS;  // digits per thread in the scan
@@ -123,28 +164,10 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   __shared__ uint16_t sdig[kCount ? 1 : TILE];
 
   const uint32_t t = threadIdx.x;
-  uint32_t D = nd, T = gridDim.x, k0 = 0, k1 = n, cb = 0, gs = 0, tl, seg = 0;
-  if (plan != nullptr) {
-    const uint32_t G = plan->total_tiles;
-    if (blockIdx.x >= G) return;  // whole workgroup
-    const uint32_t b = xcd_tile(blockIdx.x, G);
-    seg = plan->tile_seg[b];
-    tl = b - plan->tile_first[seg];
-    D = plan->D[seg];
-    T = plan->T[seg];
-    k0 = plan->key0[seg];
-    k1 = plan->key0[seg + 1];
-    cb = plan->cbase[seg];
-    gs = plan->g0[seg];
-  } else {
-    tl = xcd_tile(blockIdx.x, gridDim.x);
-  }
-  // The tiles of a segment start at its first key rounded down to
-  // kTileAlign keys, so that every interior tile takes 16-byte loads; the
-  // first and last tiles mask what lies outside the segment.
-  const uint32_t base = (k0 & ~(kTileAlign - 1)) + tl * TILE;
-  const uint32_t head = base < k0 ? k0 - base : 0u;
-  const uint32_t tail = min(static_cast<uint32_t>(TILE), k1 - base);
+  TileLoc L;
+  if (!tile_loc(plan, nd, n, TILE, L)) return;  // whole workgroup
+  const uint32_t D = L.D, T = L.T, cb = L.cb, gs = L.gs, tl = L.tl, seg = L.seg;
+  const uint32_t base = L.base, head = L.head, tail = L.tail;
   const uint32_t cnt = tail - head;  // keys of this tile
   const bool vec = head == 0 && tail == static_cast<uint32_t>(TILE) &&
                    (reinterpret_cast<uintptr_t>(in + base) & 15) == 0;
@@ -210,7 +233,7 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   }
   __syncthreads();
 
-  // Stage the tile in digit order; d[i] becomes the key's output position.
+  // Stage the tile in digit order; d[i] becomes the key's staging slot.
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t dig = d[i] & 0xFFFFu;
@@ -219,24 +242,24 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
       stage_k[pos] = v[i];
       sdig[pos] = static_cast<uint16_t>(dig);
     }
-    d[i] = delta[dig] + pos;
+    d[i] = pos;
   }
   if (perm != nullptr) {
     constexpr int kVec = 16 / sizeof(K);
     if (vec) {
-      // kVec consecutive keys per thread and load: one 16- or 8-byte store.
+      // kVec consecutive keys per thread and load: one 8- or 4-byte store.
 #pragma unroll
       for (int i = 0; i < ITEMS; i += kVec) {
-        uint32_t* dst = perm + base + elem_of<K, THREADS>(true, i, t);
+        uint16_t* dst = perm + base + elem_of<K, THREADS>(true, i, t);
         if (kVec == 4)
-          *reinterpret_cast<uint4*>(dst) = make_uint4(d[i], d[i + 1], d[i + 2], d[i + 3]);
+          *reinterpret_cast<uint2*>(dst) = make_uint2(d[i] | (d[i + 1] << 16), d[i + 2] | (d[i + 3] << 16));
         else
-          *reinterpret_cast<uint2*>(dst) = make_uint2(d[i], d[i + 1]);
+          *reinterpret_cast<uint32_t*>(dst) = d[i] | (d[i + 1] << 16);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i)
-        if ((mask >> i) & 1u) perm[base + elem_of<K, THREADS>(false, i, t)] = d[i];
+        if ((mask >> i) & 1u) perm[base + elem_of<K, THREADS>(false, i, t)] = static_cast<uint16_t>(d[i]);
     }
   }
   __syncthreads();
@@ -247,57 +270,124 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   }
 }
 
-// out[i] = src[perm[i]] (u32 values), or (src[perm[i]] != 0) as bytes: the
-// inverse of a split applied to per-key values.  A workgroup takes 8192
-// consecutive elements, in XCD order like the split tiles: the values of
-// neighbouring split tiles sit side by side in every digit run, so the
-// workgroups reading them share each line in one L2.
-constexpr uint32_t kGatherThreads = 256, kGatherPer = 32, kGatherElems = kGatherThreads * kGatherPer;
-
-template <bool FOUND>
-__global__ __launch_bounds__(kGatherThreads) void k_perm_gather(const uint32_t* __restrict__ perm,
-                                                                const uint32_t* __restrict__ src, uint32_t n,
-                                                                void* __restrict__ out) {
+// The inverse of a split applied to per-key values (u32), one split tile per
+// workgroup, on the tiles of the split itself: the tile's digit runs of
+// `src` (split order; run of digit d at the scanned count of (d, tile), its
+// length up to the next entry) are copied into LDS in the tile's digit order,
+// then out[i] = stage[perm[i]] for the tile's keys in input order, or
+// (stage[perm[i]] != 0) as bytes.  Every global access reads or writes
+// consecutive elements: a run, the slots, the output.
+template <int THREADS, int ITEMS, int MAXD, bool FOUND>
+__global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gather(
+    const uint16_t* __restrict__ perm, const uint32_t* __restrict__ src, uint32_t n,
+    const SegPlan* __restrict__ plan, uint32_t nd, const uint32_t* __restrict__ scan, void* __restrict__ out) {
+  constexpr int TILE = THREADS * ITEMS;
+  constexpr int kDPT = (MAXD + THREADS - 1) / THREADS;
+  constexpr int kW = THREADS / kWave;
+  static_assert(ITEMS % 4 == 0, "four slots per 8-byte load");
+  __shared__ uint32_t dstart[MAXD + 1];
+  __shared__ uint32_t delta[MAXD];  // src index of a slot minus the slot
+  __shared__ uint32_t wtot[kW];
+  __shared__ uint32_t stage[TILE];
+  __shared__ uint16_t sdg[TILE];    // digit of each slot
   const uint32_t t = threadIdx.x;
-  const uint32_t base = xcd_tile(blockIdx.x, gridDim.x) * kGatherElems;
-  const uint32_t end = min(n, base + kGatherElems);
-  const bool aligned = FOUND ? (reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + base) & 3) == 0
-                             : (reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + base) & 15) == 0;
-  if (end - base == kGatherElems && aligned) {
-    // Round r covers elements base + r * 1024 + 4t .. + 3.
-    constexpr int R = kGatherPer / 4;
-    uint4 p[R];
+  TileLoc L;
+  if (!tile_loc(plan, nd, n, TILE, L)) return;  // whole workgroup
+  const uint32_t cnt = L.tail - L.head;         // at least 1: a tile holds keys
+  const uint32_t first = L.base + L.head;       // input order: elements first + e, e < cnt
+  const uintptr_t oa = FOUND ? reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + first)
+                             : reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + first);
+  const bool vec = cnt == static_cast<uint32_t>(TILE) && (first & 3u) == 0 &&
+                   (reinterpret_cast<uintptr_t>(perm + first) & 7u) == 0 && (oa & (FOUND ? 3u : 15u)) == 0;
+
+  // The slots of the tile's keys (input order) are needed last but depend on
+  // nothing: they are requested first, four per thread and load.
+  uint2 pv[ITEMS / 4];
+  if (vec) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      p[r] = *reinterpret_cast<const uint4*>(perm + base + r * (kGatherThreads * 4) + 4 * t);
-    uint32_t v[kGatherPer];
+    for (int r = 0; r < ITEMS / 4; ++r)
+      pv[r] = *reinterpret_cast<const uint2*>(perm + first + static_cast<uint32_t>(r) * (THREADS * 4) + 4 * t);
+  }
+
+  // Runs of the tile's digits: start in src and length (the entry after
+  // (d, tile) is (d, tile + 1), or (d + 1, 0); after the segment's last entry
+  // comes the segment's end).
+  uint32_t c[kDPT], s0[kDPT], sum = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v[4 * r] = src[p[r].x];
-      v[4 * r + 1] = src[p[r].y];
-      v[4 * r + 2] = src[p[r].z];
-      v[4 * r + 3] = src[p[r].w];
+  for (int x = 0; x < kDPT; ++x) {
+    const uint32_t dd = kDPT * t + x;
+    c[x] = 0;
+    s0[x] = 0;
+    if (dd < L.D) {
+      const uint32_t at = L.cb + dd * L.T + L.tl;
+      s0[x] = scan[at];
+      c[x] = (dd + 1 == L.D && L.tl + 1 == L.T ? L.k1 : scan[at + 1]) - s0[x];
     }
+    sum += c[x];
+  }
+  uint32_t total;
+  uint32_t ex = block_exclusive_sum<THREADS>(sum, wtot, total);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t i = base + r * (kGatherThreads * 4) + 4 * t;
-      if (FOUND) {
-        const uint32_t packed = (v[4 * r] != 0 ? 1u : 0u) | (v[4 * r + 1] != 0 ? 0x100u : 0u) |
-                                (v[4 * r + 2] != 0 ? 0x10000u : 0u) | (v[4 * r + 3] != 0 ? 0x1000000u : 0u);
-        *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + i) = packed;
-      } else {
-        *reinterpret_cast<uint4*>(static_cast<uint32_t*>(out) + i) =
-            make_uint4(v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]);
-      }
+  for (int x = 0; x < kDPT; ++x) {
+    const uint32_t dd = kDPT * t + x;
+    if (dd < L.D) {
+      dstart[dd] = ex;
+      delta[dd] = s0[x] - ex;
+    }
+    ex += c[x];
+  }
+  if (t == 0) dstart[L.D] = total;
+  __syncthreads();
+
+  // Digit of every slot: wave w marks the runs of digits w, w + kW, ...
+  {
+    const uint32_t w = t / kWave, l = lane_id();
+    for (uint32_t dd = w; dd < L.D; dd += kW) {
+      const uint32_t a = dstart[dd], b = dstart[dd + 1];
+      for (uint32_t j = a + l; j < b; j += kWave) sdg[j] = static_cast<uint16_t>(dd);
+    }
+  }
+  __syncthreads();
+
+  // Slot j takes src[delta[digit] + j]: consecutive slots of a run read
+  // consecutive elements.  Lanes past the tile's end redo its last slot and
+  // store nothing.
+  uint32_t v[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t j = min(static_cast<uint32_t>(i) * THREADS + t, cnt - 1);
+    v[i] = delta[sdg[j]] + j;
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) v[i] = src[v[i]];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t j = static_cast<uint32_t>(i) * THREADS + t;
+    if (j < cnt) stage[j] = v[i];
+  }
+  __syncthreads();
+
+  if (vec) {
+    // Four consecutive elements per thread and round.
+#pragma unroll
+    for (int r = 0; r < ITEMS / 4; ++r) {
+      const uint32_t e = first + static_cast<uint32_t>(r) * (THREADS * 4) + 4 * t;
+      const uint32_t a = stage[pv[r].x & 0xFFFFu], b = stage[pv[r].x >> 16], cc = stage[pv[r].y & 0xFFFFu],
+                     dd = stage[pv[r].y >> 16];
+      if (FOUND)
+        *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + e) =
+            (a != 0 ? 1u : 0u) | (b != 0 ? 0x100u : 0u) | (cc != 0 ? 0x10000u : 0u) | (dd != 0 ? 0x1000000u : 0u);
+      else
+        *reinterpret_cast<uint4*>(static_cast<uint32_t*>(out) + e) = make_uint4(a, b, cc, dd);
     }
     return;
   }
-  for (uint32_t i = base + t; i < end; i += kGatherThreads) {
-    const uint32_t x = src[perm[i]];
+  for (uint32_t e = t; e < cnt; e += THREADS) {
+    const uint32_t x = stage[perm[first + e]];
     if (FOUND)
-      static_cast<uint8_t*>(out)[i] = x != 0 ? 1 : 0;
+      static_cast<uint8_t*>(out)[first + e] = x != 0 ? 1 : 0;
     else
-      static_cast<uint32_t*>(out)[i] = x;
+      static_cast<uint32_t*>(out)[first + e] = x;
   }
 }
 
@@ -1328,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_find_long(const uint32_t* __restrict__ 
 
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP>
 hipError_t msplit_dig(int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd, uint32_t log2P,
-                      uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out, uint32_t* perm,
+                      uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out, uint16_t* perm,
                       hipStream_t s) {
   if (dig == DIG_PART)
     k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_PART><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
@@ -1345,7 +1435,7 @@ hipError_t msplit_dig(int dig, dim3 grid, const K* in, uint32_t n, const SegPlan
 template <typename K, int THREADS, int ITEMS, int MAXD>
 hipError_t msplit_op(int op, int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd,
                      uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out,
-                     uint32_t* perm, hipStream_t s) {
+                     uint16_t* perm, hipStream_t s) {
   if (op == OP_COUNT)
     return msplit_dig<K, THREADS, ITEMS, MAXD, OP_COUNT>(dig, grid, in, n, plan, nd, log2P, P, desc, shift, counts,
                                                         out, perm, s);
@@ -1356,7 +1446,7 @@ hipError_t msplit_op(int op, int dig, dim3 grid, const K* in, uint32_t n, const 
 template <typename K>
 hipError_t msplit_level(int level, int op, int dig, const K* in, uint32_t n, uint32_t max_tiles, const SegPlan* plan,
                         uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t shift,
-                        uint32_t* counts, K* out, uint32_t* perm, hipStream_t s) {
+                        uint32_t* counts, K* out, uint16_t* perm, hipStream_t s) {
   if (level == 1) {
     const uint32_t tiles = div_up(n, kL1Tile);
     if (tiles == 0) return hipSuccess;
@@ -1379,7 +1469,7 @@ hipError_t msplit_level(int level, int op, int dig, const K* in, uint32_t n, uin
 
 hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uint32_t n, uint32_t max_tiles,
                          const SegPlan* plan, uint32_t nd, uint32_t log2P, uint32_t P, const PartDesc* desc,
-                         uint32_t shift, uint32_t* counts, void* out, uint32_t* perm, hipStream_t s) {
+                         uint32_t shift, uint32_t* counts, void* out, uint16_t* perm, hipStream_t s) {
   if (kt == 0)
     return msplit_level<uint32_t>(level, op, dig, static_cast<const uint32_t*>(in), n, max_tiles, plan, nd, log2P, P,
                                   desc, shift, counts, static_cast<uint32_t*>(out), perm, s);
@@ -1387,15 +1477,29 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
                                 desc, shift, counts, static_cast<uint64_t*>(out), perm, s);
 }
 
-hipError_t launch_perm_gather(const uint32_t* perm, const uint32_t* src, uint32_t n, void* out, bool found,
-                              hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const uint32_t blocks = div_up(n, kGatherElems);
+template <int THREADS, int ITEMS, int MAXD>
+hipError_t tile_gather(dim3 grid, const uint16_t* perm, const uint32_t* src, uint32_t n, const SegPlan* plan,
+                       uint32_t nd, const uint32_t* scan, void* out, bool found, hipStream_t s) {
   if (found)
-    k_perm_gather<true><<<blocks, kGatherThreads, 0, s>>>(perm, src, n, out);
+    k_tile_gather<THREADS, ITEMS, MAXD, true><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan, out);
   else
-    k_perm_gather<false><<<blocks, kGatherThreads, 0, s>>>(perm, src, n, out);
+    k_tile_gather<THREADS, ITEMS, MAXD, false><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan, out);
   return hipGetLastError();
+}
+
+hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const uint32_t* src, uint32_t n,
+                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan, void* out,
+                              bool found, hipStream_t s) {
+  if (level == 1) {
+    const uint32_t tiles = div_up(n, kL1Tile);
+    if (tiles == 0) return hipSuccess;
+    if (nd > 256) return hipErrorInvalidValue;
+    return tile_gather<kL1Tile / 8, 8, 256>(dim3(tiles), perm, src, n, nullptr, nd, scan, out, found, s);
+  }
+  if (max_tiles == 0) return hipSuccess;
+  if (kt == 0)
+    return tile_gather<kL2Threads, 8, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, out, found, s);
+  return tile_gather<kL2Threads, 4, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, out, found, s);
 }
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
