@@ -143,7 +143,7 @@ def main():
     ap.add_argument("--workload", default="p16_u32_2^28", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--n", type=int, default=None, help="override the key count (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--requests", type=int, default=100000, help="serving: requests in the stream")
     ap.add_argument("--tables", type=int, default=4096, help="batched: number of tables")
     ap.add_argument("--calibrate-copy", action="store_true",
