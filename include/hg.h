@@ -64,14 +64,22 @@ typedef enum hg_key_type { HG_KEY_U32 = 0, HG_KEY_U64 = 1 } hg_key_type;
  *                Both nonzero unless num_buckets is used.
  *   num_buckets  if nonzero and P == 1: the bucket count V itself
  *                (1 <= V <= 2^32 - 2); otherwise ignored.
- * The total bucket count sum(V_p) must stay below 2^32 - 1 (32-bit offsets,
- * Sec. 4.3 keeps the table size 32-bit). */
+ *   log2_subbin  sorted build: sub-bins of 2^log2_subbin buckets (10..13),
+ *                which sets the keys each workgroup of the LDS build takes;
+ *                0 lets the library choose.
+ *   split_bits   sorted build: at most 2^split_bits level-2 digits per
+ *                level-1 segment (7..10); 0 lets the library choose.
+ * The last two change speed only, never the table; a table keeps them for
+ * its probes.  The total bucket count sum(V_p) must stay below 2^32 - 1
+ * (32-bit offsets, Sec. 4.3 keeps the table size 32-bit). */
 typedef struct hg_build_opts {
   uint32_t P;
   uint32_t ratio_num;
   uint32_t ratio_den;
   uint32_t flags;     /* HG_BUILD_* below; 0 lets the library choose */
   uint64_t num_buckets;
+  uint32_t log2_subbin;
+  uint32_t split_bits;
 } hg_build_opts;
 
 /* Build strategies (same table, different kernels).  ATOMIC: histogram and
@@ -120,8 +128,9 @@ typedef struct hg_table_desc {
  * not synchronize.  n = 0 builds an empty table (every bucket empty, every
  * count 0).  Errors: HG_ERR_INVALID_ARG for
  * null d_keys with n > 0, null opts/out, n >= 2^32, P not a power of two,
- * a zero ratio without num_buckets, too many buckets, or unknown flags;
- * HG_ERR_UNSUPPORTED for P > 256. */
+ * a zero ratio without num_buckets, too many buckets, unknown flags, or
+ * log2_subbin / split_bits outside their ranges; HG_ERR_UNSUPPORTED for
+ * P > 256. */
 hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt,
                    const hg_build_opts* opts, hipStream_t stream,
                    hg_table** out);

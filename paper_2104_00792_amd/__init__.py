@@ -65,6 +65,8 @@ class _BuildOpts(ctypes.Structure):
         ("ratio_den", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
         ("num_buckets", ctypes.c_uint64),
+        ("log2_subbin", ctypes.c_uint32),
+        ("split_bits", ctypes.c_uint32),
     ]
 
 
@@ -238,14 +240,17 @@ class Table:
             pass
 
 
-def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None, flags: int = 0) -> Table:
+def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None, flags: int = 0,
+             log2_subbin: int = 0, split_bits: int = 0) -> Table:
     """Build a table from a device tensor of 32- or 64-bit keys.
 
     V_p = max(1, n_p * ratio[0] // ratio[1]); with P == 1 a nonzero
     ``num_buckets`` fixes V instead.  ``flags``: HG_BUILD_ATOMIC or
-    HG_BUILD_SORTED to pin the strategy (the table is the same)."""
+    HG_BUILD_SORTED to pin the strategy (the table is the same).
+    ``log2_subbin`` (10..13) and ``split_bits`` (7..10) tune the sorted build
+    (0: the library's choice); they never change the table."""
     kt = _key_type(keys)
-    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets)
+    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets, log2_subbin, split_bits)
     h = ctypes.c_void_p()
     _check(lib().hg_build(_dev_ptr(keys), keys.numel(), kt, ctypes.byref(opts), _stream(stream),
                           ctypes.byref(h)), "hg_build")
@@ -277,15 +282,16 @@ def hg_query(table: Table, queries, out=None, stream=None, flags: int = 0):
     return out
 
 
-def hg_build_batched(keys, table_offsets, ratio=(1, 1), stream=None) -> Table:
+def hg_build_batched(keys, table_offsets, ratio=(1, 1), stream=None, log2_subbin: int = 0) -> Table:
     """Build T tables at once: table t holds keys[table_offsets[t] ..
     table_offsets[t+1]) (``table_offsets``: uint32 device tensor of T + 1
-    entries from 0 to n) with V_t = max(1, n_t * ratio[0] // ratio[1])."""
+    entries from 0 to n) with V_t = max(1, n_t * ratio[0] // ratio[1]).
+    ``log2_subbin`` (10..13, 0: the library's choice) tunes the build."""
     kt = _key_type(keys)
     T = table_offsets.numel() - 1
     if table_offsets.dtype not in (_torch().uint32, _torch().int32):
         raise TypeError("table_offsets must be 32-bit")
-    opts = _BuildOpts(1, ratio[0], ratio[1], 0, 0)
+    opts = _BuildOpts(1, ratio[0], ratio[1], 0, 0, log2_subbin, 0)
     h = ctypes.c_void_p()
     _check(lib().hg_build_batched(_dev_ptr(keys), keys.numel(), kt, max(T, 0), _dev_ptr(table_offsets),
                                   ctypes.byref(opts), _stream(stream), ctypes.byref(h)), "hg_build_batched")
@@ -324,13 +330,14 @@ def hg_trim_pool(keep_bytes: int = 0):
 
 
 def hg_workspace_size(op: int, n: int = 0, key_type: int = HG_KEY_U32, P: int = 1, ratio=(1, 1),
-                      num_buckets: int = 0, flags: int = 0, table: Table | None = None, aux: int = 0):
+                      num_buckets: int = 0, flags: int = 0, table: Table | None = None, aux: int = 0,
+                      log2_subbin: int = 0, split_bits: int = 0):
     """(workspace bytes, table bytes) that one call of ``op`` allocates,
     computed on the host without touching the device.  Builds take n,
     key_type, P, ratio, num_buckets and flags (and ``aux`` = number of tables
     for HG_OP_BUILD_BATCHED); probes take ``table``, n = number of queries and
     ``aux`` = probe flags."""
-    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets)
+    opts = _BuildOpts(P, ratio[0], ratio[1], flags, num_buckets, log2_subbin, split_bits)
     ws, tb = ctypes.c_uint64(), ctypes.c_uint64()
     h = table.handle if table is not None else None
     _check(lib().hg_workspace_size(op, h, n, key_type, ctypes.byref(opts), aux, ctypes.byref(ws), ctypes.byref(tb)),

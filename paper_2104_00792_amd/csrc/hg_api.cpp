@@ -385,16 +385,19 @@ uint32_t split_l2_bits() {
 // sub-bins (the last of which may grow to 2^kLog2SLds buckets in LDS);
 // otherwise by coarse bucket ranges of 2^L2 sub-bins each (at most 256
 // ranges; ranges grow when the table needs more).
-SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound) {
+// opts->log2_subbin and opts->split_bits, when nonzero, replace the two
+// choices (already range-checked).
+SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound, const hg_build_opts* opts) {
   SplitParams sp;
   const uint64_t buckets = bound > P ? bound - P : 1;
   uint32_t rho_log = 0;  // ceil(log2(keys per bucket)), at least 0
   while ((buckets << rho_log) < n) ++rho_log;
   uint32_t l = hg::kLog2SMax > rho_log ? hg::kLog2SMax - rho_log : 0;
   if (l < hg::kLog2SMin) l = hg::kLog2SMin;
+  if (opts->log2_subbin != 0) l = opts->log2_subbin;
   sp.log2S = l;
   const uint64_t S = 1ull << l;
-  const uint32_t l2 = split_l2_bits();
+  const uint32_t l2 = opts->split_bits != 0 ? opts->split_bits : split_l2_bits();
   const uint64_t fits = ((1ull << l2) - 1) * S + (1ull << hg::kLog2SLds) / 2;
   if (P > 1 && (buckets + P - 1) / P <= fits) {
     sp.mode = 0;
@@ -700,6 +703,15 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   return HG_OK;
 }
 
+hg_status check_tuning(const hg_build_opts* opts) {
+  if (opts->log2_subbin != 0 && (opts->log2_subbin < hg::kLog2SMin || opts->log2_subbin > hg::kLog2SMax))
+    return fail(HG_ERR_INVALID_ARG, "log2_subbin = %u outside [%u, %u]", opts->log2_subbin, hg::kLog2SMin,
+                hg::kLog2SMax);
+  if (opts->split_bits != 0 && (opts->split_bits < 7 || opts->split_bits > 10))
+    return fail(HG_ERR_INVALID_ARG, "split_bits = %u outside [7, 10]", opts->split_bits);
+  return HG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -707,6 +719,7 @@ extern "C" {
 hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_build_opts* opts, hipStream_t stream,
                    hg_table** out) {
   if (out == nullptr || opts == nullptr) return fail(HG_ERR_INVALID_ARG, "null opts or out");
+  if (check_tuning(opts) != HG_OK) return HG_ERR_INVALID_ARG;
   hg_status st = check_n_P(n, kt, opts->P);
   if (st != HG_OK) return st;
   if (n > 0 && d_keys == nullptr) return fail(HG_ERR_INVALID_ARG, "null keys");
@@ -756,7 +769,7 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, 2, 0u, stream));
   HG_LAUNCH("zero_unsorted", stream, hg::launch_fill_u32(unsorted, 1, 0u, stream));
 
-  const SplitParams sp = split_params(P, n, bound);
+  const SplitParams sp = split_params(P, n, bound, opts);
   uint32_t* offs = static_cast<uint32_t*>(offsets);
   const bool sorted = (opts->flags & HG_BUILD_SORTED) != 0 ||
                       ((opts->flags & HG_BUILD_ATOMIC) == 0 && bound >= (1ull << 22) && n >= (1ull << 20));
@@ -846,6 +859,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
                            const uint32_t* d_table_offsets, const hg_build_opts* opts, hipStream_t stream,
                            hg_table** out) {
   if (out == nullptr || opts == nullptr) return fail(HG_ERR_INVALID_ARG, "null opts or out");
+  if (check_tuning(opts) != HG_OK) return HG_ERR_INVALID_ARG;
   hg_status st = check_n_P(n, kt, 1);
   if (st != HG_OK) return st;
   const uint32_t T = num_tables;
@@ -890,7 +904,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   HG_LAUNCH("batch_layout", stream,
             hg::launch_batch_layout(d_table_offsets, T, n32, opts->ratio_num, opts->ratio_den, po, bb, desc, stream));
 
-  const SplitParams sp = split_params(1, n, bound);  // sub-bin size from the batch's keys per bucket
+  const SplitParams sp = split_params(1, n, bound, opts);  // sub-bin size from the batch's keys per bucket
   L2Bufs w;
   st = alloc_l2(mem, n, kt, T, bound, sp.log2S, w);
   if (st != HG_OK) return st;

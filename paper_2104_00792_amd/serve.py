@@ -346,10 +346,11 @@ class GpuExecutor:
 
 
 def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10**9, rate: float | None = None,
-                build_log2=(10, 24), probe_log2=(8, 22), load: float = 0.8, progress=None):
+                build_log2=(10, 24), probe_log2=(8, 22), loads=(0.8,), progress=None):
     """Closed-loop capacity first (every request present at t = 0), then an
-    open-loop Poisson stream at `load` times that capacity.  Returns both
-    reports and the open-loop requests."""
+    open-loop Poisson stream at each of `loads` times that capacity (or at
+    `rate` requests/s).  Returns the closed-loop report, the open-loop
+    reports by load, and the last open-loop requests."""
     import torch
 
     reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=1.0)
@@ -364,17 +365,22 @@ def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10*
     closed.update(evictions=srv.cache.evictions, rebuilds=srv.rebuilds, peak_reserved_bytes=srv.cache.peak,
                   oom_retries=ex.oom_retries)
     _release(srv, ex)
-    lam = rate if rate is not None else load * closed["requests_per_s"]
-    reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=lam)
-    clock = WallClock()
-    ex = GpuExecutor(slots, keep_results=False)
-    srv = Server(ex, sizes, seeds, capacity_bytes, slots)
-    srv.run(reqs, clock, progress)
-    torch.cuda.synchronize()
-    opened = latency_report(reqs, clock.now())
-    opened.update(offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,
-                  peak_reserved_bytes=srv.cache.peak, oom_retries=ex.oom_retries)
-    _release(srv, ex)
+    opened = {}
+    for load in loads:
+        lam = rate if rate is not None else load * closed["requests_per_s"]
+        if progress is not None:
+            progress(f"open loop at {load} of capacity ({lam:.0f} requests/s offered)")
+        reqs, sizes, seeds = make_trace(num, build_log2=build_log2, probe_log2=probe_log2, rate=lam)
+        clock = WallClock()
+        ex = GpuExecutor(slots, keep_results=False)
+        srv = Server(ex, sizes, seeds, capacity_bytes, slots)
+        srv.run(reqs, clock, progress)
+        torch.cuda.synchronize()
+        rep = latency_report(reqs, clock.now())
+        rep.update(load=load, offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,
+                   peak_reserved_bytes=srv.cache.peak, oom_retries=ex.oom_retries)
+        opened[load] = rep
+        _release(srv, ex)
     return closed, opened, reqs
 
 

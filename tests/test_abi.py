@@ -16,7 +16,8 @@ HG_OK, HG_ERR_INVALID_ARG, HG_ERR_OUT_OF_MEMORY, HG_ERR_HIP, HG_ERR_UNSUPPORTED 
 
 class Opts(ctypes.Structure):
     _fields_ = [("P", ctypes.c_uint32), ("ratio_num", ctypes.c_uint32), ("ratio_den", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("num_buckets", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("num_buckets", ctypes.c_uint64), ("log2_subbin", ctypes.c_uint32),
+                ("split_bits", ctypes.c_uint32)]
 
 
 def declared_functions():
@@ -71,8 +72,8 @@ def test_status_strings(lib):
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 
 
-def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, flags=0, out=True):
-    opts = Opts(P, num, den, flags, V)
+def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, flags=0, out=True, sub=0, bits=0):
+    opts = Opts(P, num, den, flags, V, sub, bits)
     h = ctypes.c_void_p()
     return lib.hg_build(keys, n, kt, ctypes.byref(opts), None, ctypes.byref(h) if out else None)
 
@@ -91,6 +92,10 @@ def build(lib, keys, n, kt=0, P=1, num=1, den=1, V=0, flags=0, out=True):
     (dict(keys=FAKE, n=10, flags=4), HG_ERR_INVALID_ARG),    # unknown build flag
     (dict(keys=FAKE, n=10, flags=3), HG_ERR_INVALID_ARG),    # both strategies
     (dict(keys=FAKE, n=10, out=False), HG_ERR_INVALID_ARG),  # null out
+    (dict(keys=FAKE, n=10, sub=9), HG_ERR_INVALID_ARG),      # sub-bins below 2^10 buckets
+    (dict(keys=FAKE, n=10, sub=14), HG_ERR_INVALID_ARG),     # sub-bins above LDS size
+    (dict(keys=FAKE, n=10, bits=6), HG_ERR_INVALID_ARG),     # level-2 digits
+    (dict(keys=FAKE, n=10, bits=11), HG_ERR_INVALID_ARG),
 ])
 def test_build_rejects(lib, case, expected):
     assert build(lib, **case) == expected
@@ -134,8 +139,8 @@ def test_table_calls_reject_null(lib):
 
 
 def build_batched(lib, keys=FAKE, n=10, kt=0, T=3, offs=FAKE, P=1, num=1, den=1, V=0, flags=0, out=True,
-                  opts=True):
-    o = Opts(P, num, den, flags, V)
+                  opts=True, sub=0):
+    o = Opts(P, num, den, flags, V, sub, 0)
     h = ctypes.c_void_p()
     return lib.hg_build_batched(keys, n, kt, T, offs, ctypes.byref(o) if opts else None, None,
                                 ctypes.byref(h) if out else None)
@@ -156,6 +161,7 @@ def build_batched(lib, keys=FAKE, n=10, kt=0, T=3, offs=FAKE, P=1, num=1, den=1,
     (dict(n=(1 << 32) - 1, num=2), HG_ERR_INVALID_ARG),     # too many buckets
     (dict(out=False), HG_ERR_INVALID_ARG),
     (dict(opts=False), HG_ERR_INVALID_ARG),
+    (dict(sub=15), HG_ERR_INVALID_ARG),
 ])
 def test_build_batched_rejects(lib, case, expected):
     assert build_batched(lib, **case) == expected
