@@ -135,6 +135,25 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt,
                    const hg_build_opts* opts, hipStream_t stream,
                    hg_table** out);
 
+/* hg_build_like -- a HashGraph of n keys (the query set) with the layout of
+ * `table`: the same partitions, table sizes V_p and bucket bases, so that
+ * bucket g of both tables holds exactly the keys that hash to g (Sec. 3.3,
+ * "Querying": the query set gets its own HashGraph over the same hash
+ * values).  The keys have the table's key type.  Errors: as hg_build, plus
+ * HG_ERR_INVALID_ARG for a null or batched table. */
+hg_status hg_build_like(const hg_table* table, const void* d_keys, uint64_t n,
+                        hipStream_t stream, hg_table** out);
+
+/* hg_intersect -- the per-bucket list intersections of Sec. 3.3: for every
+ * position j of the query table's key array (bucket order, see
+ * hg_table_info), d_counts[j] = number of keys of `table` equal to that
+ * query key; both lists are the same bucket's.  `queries` must come from
+ * hg_build_like(table, ...).  d_counts: queries' n uint32.  Errors:
+ * HG_ERR_INVALID_ARG for null tables, a query table not built like `table`,
+ * or null d_counts with n > 0. */
+hg_status hg_intersect(const hg_table* table, const hg_table* queries,
+                       uint32_t* d_counts, hipStream_t stream);
+
 /* hg_count -- exact multiplicity of each query among the table's keys: the
  * query hashes to its bucket and every key of the bucket is compared
  * (Sec. 3.3 "Querying"; Sec. 5.4: the count of each key's appearances).
@@ -200,6 +219,31 @@ hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt,
                            uint32_t P, void* d_out_keys,
                            uint32_t* d_part_offsets, hipStream_t stream);
 
+/* hg_bin_partition_balanced -- the hash-range split with count-balanced
+ * ranges (Algorithm 2, Phases 1 and 2; Sec. 4.1 "Phase 1: Multi-GPU Data
+ * Partitioning"), P ranges for P devices.
+ *   H(k) = hash(k) mod hash_range, 1 <= hash_range < 2^32 (the hash range
+ *   HR of Sec. 4.1, e.g. the global table size).  The range is cut into
+ *   bins of BinSize = ceil(HR / num_bins) consecutive values, bin =
+ *   floor(H / BinSize), ceil(HR / BinSize) bins; num_bins 0 takes
+ *   ceil(sqrt(HR)) (the paper's O(sqrt(HR))), num_bins <= 2^14.
+ *   Boundary d (0 < d < P) is the first bin whose exclusive prefix count
+ *   reaches floor(n * d / P) keys: d_bin_splits[0..P] (device, P+1 uint32;
+ *   [0] = 0, [P] = number of bins, non-decreasing).  Partition d holds the
+ *   keys with d_bin_splits[d] <= bin < d_bin_splits[d+1]; so the first d
+ *   partitions hold between floor(n d / P) keys and that plus one bin's keys.
+ *   d_out_keys[n]: the keys grouped by partition (order inside a partition
+ *   unspecified); d_part_offsets[P+1] (device, part_offsets[P] = n).
+ *   1 <= P <= 256 (any P, not only powers of two).  d_out_keys must not
+ *   overlap d_keys.  Errors: HG_ERR_INVALID_ARG for P, hash_range or
+ *   num_bins out of range, n >= 2^32, null outputs, or null keys with
+ *   n > 0. */
+hg_status hg_bin_partition_balanced(const void* d_keys, uint64_t n,
+                                    hg_key_type kt, uint32_t P,
+                                    uint64_t hash_range, uint32_t num_bins,
+                                    void* d_out_keys, uint32_t* d_part_offsets,
+                                    uint32_t* d_bin_splits, hipStream_t stream);
+
 /* hg_hash_bucket -- the first loop of Algorithm 1 on its own: for each key,
  * d_hash[i] = hash(k) (uint64; for 32-bit keys the upper half is 0) and
  * d_bucket[i] = hash(k) mod V.  Either output may be null.  1 <= V < 2^32.
@@ -262,7 +306,8 @@ typedef enum hg_op {
   HG_OP_QUERY = 2,          /* hg_query_ex(table, n queries, flags = aux)  */
   HG_OP_BUILD_BATCHED = 3,  /* hg_build_batched(n keys, aux tables, opts)  */
   HG_OP_COUNT_BATCHED = 4,  /* hg_count_batched(table, n queries)          */
-  HG_OP_QUERY_BATCHED = 5   /* hg_query_batched(table, n queries)          */
+  HG_OP_QUERY_BATCHED = 5,  /* hg_query_batched(table, n queries)          */
+  HG_OP_BIN_PARTITION = 6   /* hg_bin_partition(n keys of kt, P = aux)     */
 } hg_op;
 
 /* hg_workspace_size -- the device memory that one call of `op` with these
@@ -276,7 +321,7 @@ typedef enum hg_op {
  * with any bump allocator that rounds the same way.  Arguments that the call
  * itself would reject give the same error here.  kt and opts are used by
  * the builds, table by the probes; aux holds the probe flags for COUNT and
- * QUERY and the number of tables for BUILD_BATCHED.  Either output may be
+ * QUERY, the number of tables for BUILD_BATCHED and P for BIN_PARTITION.  Either output may be
  * null.  Errors: HG_ERR_INVALID_ARG for an unknown op, and those of the
  * sized call. */
 hg_status hg_workspace_size(hg_op op, const hg_table* table, uint64_t n,

@@ -63,6 +63,8 @@ def load_library(path: str):
     lib.orc_count.restype = i32
     lib.orc_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp]
     lib.orc_bin_partition.restype = i32
+    lib.orc_bin_partition_balanced.argtypes = [vp, u64, i32, u32, u64, u32, vp, vp, vp]
+    lib.orc_bin_partition_balanced.restype = i32
     return lib
 
 
@@ -165,6 +167,42 @@ def bin_partition(keys: np.ndarray, P: int):
     out = np.empty_like(keys)
     _check(_load().orc_bin_partition(_ptr(keys), keys.size, _kt(keys), P, _ptr(po), _ptr(out)), "bin_partition")
     return po, out
+
+
+def bin_partition_balanced(keys: np.ndarray, P: int, HR: int, num_bins: int = 0):
+    """Count-balanced split (step O6, Algorithm 2 Phases 1 and 2):
+    (part_offsets[P+1], bin_splits[P+1], keys grouped by partition, each
+    group ascending)."""
+    keys = np.ascontiguousarray(keys)
+    po = np.empty(P + 1, np.uint32)
+    splits = np.empty(P + 1, np.uint32)
+    out = np.empty_like(keys)
+    _check(_load().orc_bin_partition_balanced(_ptr(keys), keys.size, _kt(keys), P, HR, num_bins, _ptr(po),
+                                              _ptr(splits), _ptr(out)), "bin_partition_balanced")
+    return po, splits, out
+
+
+def build_like(table_keys: np.ndarray, queries: np.ndarray, P: int = 1, num: int = 1, den: int = 1, V: int = 0):
+    """The query set's HashGraph over the buckets of the table built from
+    table_keys (Sec. 3.3, "Querying"): the table's V_p and bucket bases, the
+    queries' own partition offsets; each query in bucket bucket_base[p] +
+    hash mod V_p, where p is the partition of its hash.  Returns
+    dict(part_offsets, bucket_base, offsets, keys), keys canonical (each
+    bucket ascending)."""
+    queries = np.ascontiguousarray(queries)
+    _, bb = layout(table_keys, P, num, den, V)
+    B = int(bb[P])
+    w = 32 if queries.dtype == np.uint32 else 64
+    h, _ = hash_bucket(queries, 1)
+    h = h.astype(np.uint64)
+    log2P = P.bit_length() - 1
+    p = (h >> np.uint64(w - log2P)).astype(np.int64) if log2P else np.zeros(queries.size, np.int64)
+    Vp = np.diff(bb.astype(np.int64)).astype(np.uint64)
+    g = bb[p].astype(np.int64) + (h % Vp[p]).astype(np.int64) if queries.size else np.zeros(0, np.int64)
+    order = np.lexsort((queries, g))
+    offsets = np.concatenate([[0], np.cumsum(np.bincount(g, minlength=B))]).astype(np.uint32)
+    po = np.concatenate([[0], np.cumsum(np.bincount(p, minlength=P))]).astype(np.uint32)
+    return {"part_offsets": po, "bucket_base": bb, "offsets": offsets, "keys": queries[order]}
 
 
 def canonicalize(offsets: np.ndarray, keys: np.ndarray) -> np.ndarray:

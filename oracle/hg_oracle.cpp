@@ -8,7 +8,8 @@
 // std::sort of tuples plus run-length counting.
 //
 // What is computed (Sec. 3.1 "Single-GPU HashGraph", Algorithm 1; Sec. 3.3
-// Phase 2, Algorithm 2; the CSR paragraph of Sec. 3.1):
+// Phase 2, Algorithm 2; the CSR paragraph of Sec. 3.1; the count-balanced
+// ranges of Algorithm 2, Phase 1, in step O6 below):
 //   * hash(e): the MurmurHash3 64/32-bit finalizers applied to the key value
 //     (Sec. 4.2 names Murmur; the variant is our reading, see below).
 //   * partition of a key: the top log2(P) bits of its hash (fixed equal hash
@@ -282,6 +283,66 @@ int orc_bin_partition(const void* keys, uint64_t n, int kt, uint32_t P,
     po += n_p[p];
   }
   part_offsets[P] = static_cast<uint32_t>(po);
+  for (uint64_t i = 0; i < n; ++i) key_put(keys_out, kt, i, t[i].second);
+  return ORC_OK;
+}
+
+// Step O6: the count-balanced split of Algorithm 2, Phases 1 and 2 (Sec. 4.1,
+// "Phase 1: Multi-GPU Data Partitioning" and "Phase 2"), one partition per
+// device.  The reduced hash H = hash mod HR covers the hash range HR; the
+// range is cut into bins of BinSize = ceil(HR / num_bins) consecutive values
+// (bin = floor(H / BinSize), ceil(HR / BinSize) bins; num_bins = 0 takes
+// ceil(sqrt(HR)), at most 2^14).  BinOffset is the exclusive prefix sum of the
+// keys per bin.  Boundary d (0 < d < P) is the first bin whose BinOffset
+// reaches floor(n * d / P), the key count the first d partitions should hold;
+// split[0] = 0 and split[P] = the number of bins.  A key belongs to the last
+// partition d with split[d] <= bin.  Outputs: part_offsets[P+1], bin_splits
+// [P+1], and the keys grouped by partition, each group ascending.
+int orc_bin_partition_balanced(const void* keys, uint64_t n, int kt, uint32_t P, uint64_t HR, uint32_t num_bins,
+                               uint32_t* part_offsets, uint32_t* bin_splits, void* keys_out) {
+  if (kt != KT_U32 && kt != KT_U64) return ORC_BAD_ARG;
+  if (n >= (1ull << 32) || P == 0 || P > 256 || HR == 0 || HR >= (1ull << 32) || num_bins > (1u << 14))
+    return ORC_BAD_ARG;
+  uint64_t bins_asked = num_bins;
+  if (bins_asked == 0) {
+    bins_asked = 1;
+    while (bins_asked * bins_asked < HR) ++bins_asked;  // ceil(sqrt(HR))
+    if (bins_asked > (1u << 14)) bins_asked = 1u << 14;
+  }
+  const uint64_t bin_size = (HR + bins_asked - 1) / bins_asked;
+  const uint64_t nbins = (HR + bin_size - 1) / bin_size;
+  std::vector<uint64_t> bin_of(n);
+  std::vector<uint64_t> count(nbins, 0);
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t H = hash_of(key_at(keys, kt, i), kt) % HR;
+    bin_of[i] = H / bin_size;
+    ++count[bin_of[i]];
+  }
+  std::vector<uint64_t> bin_offset(nbins + 1, 0);
+  for (uint64_t b = 0; b < nbins; ++b) bin_offset[b + 1] = bin_offset[b] + count[b];
+  std::vector<uint64_t> split(P + 1, 0);
+  split[P] = nbins;
+  for (uint32_t d = 1; d < P; ++d) {
+    const uint64_t target = n * d / P;
+    split[d] = static_cast<uint64_t>(std::lower_bound(bin_offset.begin(), bin_offset.end(), target) -
+                                     bin_offset.begin());
+  }
+  std::vector<std::pair<uint32_t, uint64_t>> t(n);
+  std::vector<uint64_t> n_d(P, 0);
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint32_t d =
+        static_cast<uint32_t>(std::upper_bound(split.begin(), split.end(), bin_of[i]) - split.begin()) - 1;
+    t[i] = std::make_pair(d, key_at(keys, kt, i));
+    ++n_d[d];
+  }
+  std::sort(t.begin(), t.end());
+  uint64_t po = 0;
+  for (uint32_t d = 0; d < P; ++d) {
+    part_offsets[d] = static_cast<uint32_t>(po);
+    po += n_d[d];
+  }
+  part_offsets[P] = static_cast<uint32_t>(po);
+  for (uint32_t d = 0; d <= P; ++d) bin_splits[d] = static_cast<uint32_t>(split[d]);
   for (uint64_t i = 0; i < n; ++i) key_put(keys_out, kt, i, t[i].second);
   return ORC_OK;
 }

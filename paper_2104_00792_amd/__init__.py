@@ -17,8 +17,8 @@ import ctypes
 import os
 
 __all__ = [
-    "HGError", "Table", "hg_build", "hg_count", "hg_query", "hg_bin_partition",
-    "hg_hash_bucket", "hg_build_batched", "hg_count_batched", "hg_query_batched", "hg_trim_pool",
+    "HGError", "Table", "hg_build", "hg_build_like", "hg_intersect", "hg_count", "hg_query", "hg_bin_partition",
+    "hg_hash_bucket", "hg_bin_partition_balanced", "hg_build_batched", "hg_count_batched", "hg_query_batched", "hg_trim_pool",
     "hg_set_allocator", "hg_workspace_size", "torch_allocator", "lib", "lib_path", "profile",
 ]
 
@@ -43,6 +43,7 @@ HG_OP_QUERY = 2
 HG_OP_BUILD_BATCHED = 3
 HG_OP_COUNT_BATCHED = 4
 HG_OP_QUERY_BATCHED = 5
+HG_OP_BIN_PARTITION = 6
 
 # Allocator hook signatures of include/hg.h.
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -103,6 +104,10 @@ def lib() -> ctypes.CDLL:
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     L.hg_build.argtypes = [vp, u64, i32, ctypes.POINTER(_BuildOpts), vp, ctypes.POINTER(vp)]
     L.hg_build.restype = i32
+    L.hg_build_like.argtypes = [vp, vp, u64, vp, ctypes.POINTER(vp)]
+    L.hg_build_like.restype = i32
+    L.hg_intersect.argtypes = [vp, vp, vp, vp]
+    L.hg_intersect.restype = i32
     L.hg_count.argtypes = [vp, vp, u64, vp, vp]
     L.hg_count.restype = i32
     L.hg_query.argtypes = [vp, vp, u64, vp, vp]
@@ -119,6 +124,8 @@ def lib() -> ctypes.CDLL:
     L.hg_query_batched.restype = i32
     L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
     L.hg_bin_partition.restype = i32
+    L.hg_bin_partition_balanced.argtypes = [vp, u64, i32, u32, u64, u32, vp, vp, vp, vp]
+    L.hg_bin_partition_balanced.restype = i32
     L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
     L.hg_hash_bucket.restype = i32
     L.hg_table_info.argtypes = [vp, ctypes.POINTER(_TableDesc)]
@@ -255,6 +262,27 @@ def hg_build(keys, P: int = 1, ratio=(1, 1), num_buckets: int = 0, stream=None, 
     _check(lib().hg_build(_dev_ptr(keys), keys.numel(), kt, ctypes.byref(opts), _stream(stream),
                           ctypes.byref(h)), "hg_build")
     return Table(h.value, kt, keys.numel(), P)
+
+
+def hg_build_like(table: Table, keys, stream=None) -> Table:
+    """A HashGraph of `keys` (the query set) over the same buckets as
+    `table` (Sec. 3.3): bucket g of both holds the keys hashing to g."""
+    if _key_type(keys) != table.key_type:
+        raise TypeError("keys and table keys differ in width")
+    h = ctypes.c_void_p()
+    _check(lib().hg_build_like(table.handle, _dev_ptr(keys), keys.numel(), _stream(stream), ctypes.byref(h)),
+           "hg_build_like")
+    return Table(h.value, table.key_type, keys.numel(), table.P)
+
+
+def hg_intersect(table: Table, queries: Table, out=None, stream=None):
+    """Per-bucket intersections (Sec. 3.3): for each key of the query table
+    in its bucket order, the number of equal keys in `table` (uint32)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(queries.n, dtype=torch.uint32, device="cuda")
+    _check(lib().hg_intersect(table.handle, queries.handle, _dev_ptr(out), _stream(stream)), "hg_intersect")
+    return out
 
 
 def hg_count(table: Table, queries, out=None, stream=None, flags: int = 0):
@@ -406,6 +434,25 @@ def hg_bin_partition(keys, P: int, out=None, part_offsets=None, stream=None):
     _check(lib().hg_bin_partition(_dev_ptr(keys), keys.numel(), kt, P, _dev_ptr(out), _dev_ptr(part_offsets),
                                   _stream(stream)), "hg_bin_partition")
     return out, part_offsets
+
+
+def hg_bin_partition_balanced(keys, P: int, hash_range: int, num_bins: int = 0, out=None, part_offsets=None,
+                              bin_splits=None, stream=None):
+    """Count-balanced hash-range split into P partitions (Algorithm 2,
+    Phases 1 and 2): (keys grouped by partition, part_offsets[P+1],
+    bin_splits[P+1]).  num_bins 0 takes ceil(sqrt(hash_range))."""
+    torch = _torch()
+    kt = _key_type(keys)
+    if out is None:
+        out = torch.empty_like(keys)
+    if part_offsets is None:
+        part_offsets = torch.empty(P + 1, dtype=torch.uint32, device=keys.device)
+    if bin_splits is None:
+        bin_splits = torch.empty(P + 1, dtype=torch.uint32, device=keys.device)
+    _check(lib().hg_bin_partition_balanced(_dev_ptr(keys), keys.numel(), kt, P, hash_range, num_bins, _dev_ptr(out),
+                                           _dev_ptr(part_offsets), _dev_ptr(bin_splits), _stream(stream)),
+           "hg_bin_partition_balanced")
+    return out, part_offsets, bin_splits
 
 
 def hg_hash_bucket(keys, V: int, want_hash: bool = True, stream=None):

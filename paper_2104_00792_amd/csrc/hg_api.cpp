@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -51,6 +52,8 @@ struct hg_table {
   uint32_t nd1;             // level-1 digits
   uint32_t log2S;           // sub-bins of 2^log2S buckets
   bool batched;             // P caller-defined tables (hg_build_batched)
+  uint64_t id;              // nonzero, unique in the process
+  uint64_t like_id;         // id of the table whose layout this one copies (hg_build_like), else 0
   std::vector<TableBlock> blocks;  // keys, offsets and metadata, and where they go back
   std::mutex mu;
   bool have_num_buckets;
@@ -110,6 +113,8 @@ hipError_t pool_for(int dev, hipMemPool_t* out) {
   *out = pool;
   return hipSuccess;
 }
+
+std::atomic<uint64_t> g_next_table_id{1};
 
 // ------------------------------------------------------- allocator hook
 std::mutex g_hook_mu;
@@ -486,11 +491,21 @@ hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams
   return HG_OK;
 }
 
+// Table layout from the scanned tile counts: the sizes from the ratio (or
+// the plain V), or copied from another table's descriptors (`like`: the
+// query table of hg_build_like).
+hipError_t layout_of(const hg::PartDesc* like, const uint32_t* tile_base, uint32_t num_tiles, uint32_t P, uint32_t n,
+                     const hg_build_opts* opts, uint64_t V_plain, uint32_t* po, uint32_t* bb, hg::PartDesc* desc,
+                     hipStream_t s) {
+  if (like != nullptr) return hg::launch_layout_like(tile_base, num_tiles, P, n, like, po, bb, desc, s);
+  return hg::launch_layout(tile_base, num_tiles, P, n, opts->ratio_num, opts->ratio_den, V_plain, po, bb, desc, s);
+}
+
 // The LDS-sorted build (splits + one LDS counting sort per sub-bin).
 hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P, uint32_t log2P,
                        const hg_build_opts* opts, bool plain_V, uint64_t bound, const SplitParams& sp,
-                       uint32_t* po, uint32_t* bb, hg::PartDesc* desc, uint32_t* offs, void* keys_out,
-                       uint32_t* long_count, uint32_t* long_list, Allocs& mem, hipStream_t s) {
+                       const hg::PartDesc* like, uint32_t* po, uint32_t* bb, hg::PartDesc* desc, uint32_t* offs,
+                       void* keys_out, uint32_t* long_count, uint32_t* long_list, Allocs& mem, hipStream_t s) {
   SplitBufs w;
   hg_status st = alloc_split(mem, n, kt, sp, P, bound, w, 0);
   if (st != HG_OK) return st;
@@ -502,21 +517,17 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
                                 w.counts1, nullptr, nullptr, s));
     HG_LAUNCH("split1_scan", s,
               hg::launch_scan_exclusive(w.counts1, nullptr, static_cast<uint64_t>(P) * w.tiles1, w.bsums, s));
-    HG_LAUNCH("layout", s,
-              hg::launch_layout(w.counts1, w.tiles1, P, n, opts->ratio_num, opts->ratio_den, 0, po, bb, desc, s));
+    HG_LAUNCH("layout", s, layout_of(like, w.counts1, w.tiles1, P, n, opts, 0, po, bb, desc, s));
   } else {
     if (P > 1) {
       HG_LAUNCH("part_count", s, hg::launch_part_count(kt, keys, n, log2P, hg::div_up(n, hg::kTileKeys), w.counts1, s));
       HG_LAUNCH("part_scan", s,
                 hg::launch_scan_exclusive(w.counts1, nullptr,
                                           static_cast<uint64_t>(P) * hg::div_up(n, hg::kTileKeys), w.bsums, s));
-      HG_LAUNCH("layout", s,
-                hg::launch_layout(w.counts1, hg::div_up(n, hg::kTileKeys), P, n, opts->ratio_num, opts->ratio_den, 0,
-                                  po, bb, desc, s));
+      HG_LAUNCH("layout", s, layout_of(like, w.counts1, hg::div_up(n, hg::kTileKeys), P, n, opts, 0, po, bb, desc, s));
     } else {
       HG_LAUNCH("layout", s,
-                hg::launch_layout(nullptr, 0, 1, n, opts->ratio_num, opts->ratio_den,
-                                  plain_V ? opts->num_buckets : 0, po, bb, desc, s));
+                layout_of(like, nullptr, 0, 1, n, opts, plain_V ? opts->num_buckets : 0, po, bb, desc, s));
     }
     HG_LAUNCH("split1_count", s,
               hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_COARSE, keys, n, 0, nullptr, sp.nd1, log2P, P, desc,
@@ -716,8 +727,10 @@ hg_status check_tuning(const hg_build_opts* opts) {
 
 extern "C" {
 
-hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_build_opts* opts, hipStream_t stream,
-                   hg_table** out) {
+// The build of hg_build, or of hg_build_like when `like` is given (then the
+// layout, hence every key's bucket, is the one of `like`).
+static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, const hg_build_opts* opts,
+                            const hg_table* like, hipStream_t stream, hg_table** out) {
   if (out == nullptr || opts == nullptr) return fail(HG_ERR_INVALID_ARG, "null opts or out");
   if (check_tuning(opts) != HG_OK) return HG_ERR_INVALID_ARG;
   hg_status st = check_n_P(n, kt, opts->P);
@@ -738,6 +751,8 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
     bound = n * static_cast<uint64_t>(opts->ratio_num) / opts->ratio_den + P;
     if (bound > 0xFFFFFFFEull) return fail(HG_ERR_INVALID_ARG, "table ratio gives more than 2^32 - 2 buckets");
   }
+  if (like != nullptr) bound = like->buckets_bound;  // the same buckets
+  const hg::PartDesc* like_desc = like != nullptr ? like->d_desc : nullptr;
 
   const uint32_t n32 = static_cast<uint32_t>(n);
   const uint32_t log2P = log2_of(P);
@@ -774,8 +789,8 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   const bool sorted = (opts->flags & HG_BUILD_SORTED) != 0 ||
                       ((opts->flags & HG_BUILD_ATOMIC) == 0 && bound >= (1ull << 22) && n >= (1ull << 20));
   if (sorted) {
-    st = build_sorted(d_keys, n32, kt, P, log2P, opts, plain_V, bound, sp, po, bb, desc, offs, keys_out, long_ctr,
-                      long_list, mem, stream);
+    st = build_sorted(d_keys, n32, kt, P, log2P, opts, plain_V, bound, sp, like_desc, po, bb, desc, offs, keys_out,
+                      long_ctr, long_list, mem, stream);
     if (st != HG_OK) return st;
   } else {
   const uint64_t part_elems = P > 1 ? static_cast<uint64_t>(P) * num_tiles : 0;
@@ -791,13 +806,12 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
                        static_cast<uint32_t*>(bsums), buffer, stream);
     if (st != HG_OK) return st;
     HG_LAUNCH("layout", stream,
-              hg::launch_layout(static_cast<uint32_t*>(tile_counts), num_tiles, P, n32, opts->ratio_num,
-                                opts->ratio_den, 0, po, bb, desc, stream));
+              layout_of(like_desc, static_cast<uint32_t*>(tile_counts), num_tiles, P, n32, opts, 0, po, bb, desc,
+                        stream));
     src = buffer;
   } else {
     HG_LAUNCH("layout", stream,
-              hg::launch_layout(nullptr, 0, 1, n32, opts->ratio_num, opts->ratio_den,
-                                plain_V ? opts->num_buckets : 0, po, bb, desc, stream));
+              layout_of(like_desc, nullptr, 0, 1, n32, opts, plain_V ? opts->num_buckets : 0, po, bb, desc, stream));
   }
 
   HG_LAUNCH("zero_counts", stream, hg::launch_fill_u32(offs, bound + 1, 0u, stream));
@@ -830,10 +844,44 @@ hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_buil
   t->nd1 = sp.nd1;
   t->log2S = sp.log2S;
   t->batched = false;
+  t->id = g_next_table_id.fetch_add(1);
+  t->like_id = like != nullptr ? like->id : 0;
   t->have_num_buckets = false;
   t->num_buckets = 0;
   t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
   *out = t;
+  return HG_OK;
+}
+
+hg_status hg_build(const void* d_keys, uint64_t n, hg_key_type kt, const hg_build_opts* opts, hipStream_t stream,
+                   hg_table** out) {
+  return build_impl(d_keys, n, kt, opts, nullptr, stream, out);
+}
+
+hg_status hg_build_like(const hg_table* table, const void* d_keys, uint64_t n, hipStream_t stream, hg_table** out) {
+  if (table == nullptr) return fail(HG_ERR_INVALID_ARG, "null table");
+  if (table->batched) return fail(HG_ERR_INVALID_ARG, "a batched table has no single layout to copy");
+  hg_build_opts o = {};
+  o.P = table->P;
+  o.ratio_num = 1;
+  o.ratio_den = 1;
+  return build_impl(d_keys, n, table->kt, &o, table, stream, out);
+}
+
+hg_status hg_intersect(const hg_table* table, const hg_table* queries, uint32_t* d_counts, hipStream_t stream) {
+  if (table == nullptr || queries == nullptr) return fail(HG_ERR_INVALID_ARG, "null table");
+  if (queries->like_id != table->id)
+    return fail(HG_ERR_INVALID_ARG, "the query table was not built like this table (hg_build_like)");
+  if (queries->n == 0) return HG_OK;
+  if (d_counts == nullptr) return fail(HG_ERR_INVALID_ARG, "null counts");
+  // Bucket g of both tables holds the keys that hash to g, and the query
+  // table lists its keys bucket by bucket: each query key is counted in the
+  // table's list of the same bucket, the lists of consecutive buckets in
+  // turn.
+  HG_LAUNCH("intersect", stream,
+            hg::launch_probe(table->kt, true, table->d_keys, table->d_offsets, table->d_desc, table->log2P, table->P,
+                             table->d_unsorted, queries->d_keys, static_cast<uint32_t>(queries->n), d_counts,
+                             stream));
   return HG_OK;
 }
 
@@ -945,6 +993,8 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   t->nd1 = T;
   t->log2S = sp.log2S;
   t->batched = true;
+  t->id = g_next_table_id.fetch_add(1);
+  t->like_id = 0;
   t->have_num_buckets = false;
   t->num_buckets = 0;
   t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
@@ -982,6 +1032,56 @@ hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   HG_LAUNCH("part_offsets", stream,
             hg::launch_layout(static_cast<uint32_t*>(tile_counts), num_tiles, P, n32, 1, 1, 0, d_part_offsets,
                               nullptr, nullptr, stream));
+  return HG_OK;
+}
+
+hg_status hg_bin_partition_balanced(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t P, uint64_t hash_range,
+                                    uint32_t num_bins, void* d_out_keys, uint32_t* d_part_offsets,
+                                    uint32_t* d_bin_splits, hipStream_t stream) {
+  if (kt != HG_KEY_U32 && kt != HG_KEY_U64) return fail(HG_ERR_INVALID_ARG, "unknown key type %d", (int)kt);
+  if (n >= (1ull << 32)) return fail(HG_ERR_INVALID_ARG, "n = %llu is not below 2^32", (unsigned long long)n);
+  if (P == 0 || P > hg::kMaxP) return fail(HG_ERR_INVALID_ARG, "P = %u outside [1, %u]", P, hg::kMaxP);
+  if (hash_range == 0 || hash_range >= (1ull << 32))
+    return fail(HG_ERR_INVALID_ARG, "hash range %llu outside [1, 2^32)", (unsigned long long)hash_range);
+  if (num_bins > hg::kMaxBins) return fail(HG_ERR_INVALID_ARG, "num_bins = %u exceeds %u", num_bins, hg::kMaxBins);
+  if (d_part_offsets == nullptr || d_bin_splits == nullptr) return fail(HG_ERR_INVALID_ARG, "null outputs");
+  if (n > 0 && (d_keys == nullptr || d_out_keys == nullptr)) return fail(HG_ERR_INVALID_ARG, "null keys");
+  uint64_t bins = num_bins;
+  if (bins == 0) {  // ceil(sqrt(HR)), at most kMaxBins
+    bins = 1;
+    while (bins * bins < hash_range && bins < hg::kMaxBins) ++bins;
+  }
+  const uint32_t HR = static_cast<uint32_t>(hash_range);
+  const uint32_t bin_size = static_cast<uint32_t>((hash_range + bins - 1) / bins);
+  const uint32_t nbins = static_cast<uint32_t>((hash_range + bin_size - 1) / bin_size);
+  const uint32_t n32 = static_cast<uint32_t>(n);
+  const uint32_t tiles = hg::div_up(n, hg::kL1Tile);
+  const uint64_t tile_elems = static_cast<uint64_t>(P) * tiles;
+  Allocs mem(stream);
+  void *bc = nullptr, *bs = nullptr, *tc = nullptr, *rd = nullptr;
+  HG_TRY(mem.get(&bc, (static_cast<uint64_t>(nbins) + 1) * sizeof(uint32_t)), "allocate bin counts");
+  HG_TRY(mem.get(&bs, (hg::div_up(std::max<uint64_t>(nbins, tile_elems), hg::kScanChunk) + 1) * sizeof(uint32_t)),
+         "allocate scan workspace");
+  HG_TRY(mem.get(&tc, std::max<uint64_t>(tile_elems, 1) * sizeof(uint32_t)), "allocate tile counts");
+  HG_TRY(mem.get(&rd, sizeof(hg::PartDesc) + (hg::kMaxP + 1) * sizeof(uint32_t)), "allocate range descriptor");
+  uint32_t* bin_counts = static_cast<uint32_t*>(bc);
+  uint32_t* bsums = static_cast<uint32_t*>(bs);
+  uint32_t* tile_counts = static_cast<uint32_t*>(tc);
+  hg::PartDesc* rdesc = static_cast<hg::PartDesc*>(rd);
+  HG_LAUNCH("bin_zero", stream, hg::launch_fill_u32(bin_counts, nbins, 0u, stream));
+  HG_LAUNCH("bin_hist", stream, hg::launch_bin_hist(kt, d_keys, n32, HR, bin_size, nbins, bin_counts, stream));
+  HG_LAUNCH("bin_scan", stream, hg::launch_scan_exclusive(bin_counts, nullptr, nbins, bsums, stream));
+  HG_LAUNCH("bin_splits", stream,
+            hg::launch_range_splits(bin_counts, nbins, n32, P, HR, bin_size, d_bin_splits, rdesc, stream));
+  HG_LAUNCH("range_count", stream,
+            hg::launch_msplit(kt, 1, hg::OP_COUNT, hg::DIG_RANGE, d_keys, n32, 0, nullptr, P, 0, 1, rdesc, 0,
+                              tile_counts, nullptr, nullptr, stream));
+  HG_LAUNCH("range_scan", stream, hg::launch_scan_exclusive(tile_counts, nullptr, tile_elems, bsums, stream));
+  HG_LAUNCH("range_offsets", stream,
+            hg::launch_layout(tile_counts, tiles, P, n32, 1, 1, 0, d_part_offsets, nullptr, nullptr, stream));
+  HG_LAUNCH("range_scatter", stream,
+            hg::launch_msplit(kt, 1, hg::OP_SCATTER, hg::DIG_RANGE, d_keys, n32, 0, nullptr, P, 0, 1, rdesc, 0,
+                              tile_counts, d_out_keys, nullptr, stream));
   return HG_OK;
 }
 
@@ -1083,6 +1183,7 @@ hg_status hg_workspace_size(hg_op op, const hg_table* table, uint64_t n, hg_key_
     case HG_OP_BUILD_BATCHED: st = hg_build_batched(ph, n, kt, aux, ph32, opts, nullptr, &t); break;
     case HG_OP_COUNT_BATCHED: st = hg_count_batched(table, ph, n, ph32, ph32, nullptr); break;
     case HG_OP_QUERY_BATCHED: st = hg_query_batched(table, ph, n, ph32, static_cast<uint8_t*>(ph), nullptr); break;
+    case HG_OP_BIN_PARTITION: st = hg_bin_partition(ph, n, kt, aux, ph, ph32, nullptr); break;
     default: return fail(HG_ERR_INVALID_ARG, "unknown op %d", static_cast<int>(op));
   }
   delete t;  // its blocks are placeholders: nothing to free

@@ -71,6 +71,12 @@ __host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 __host__ __device__ __forceinline__ uint32_t recip32(uint32_t V) { return 0xFFFFFFFFu / V; }
 __host__ __device__ __forceinline__ uint64_t recip64(uint32_t V) { return ~0ull / V; }
 
+// floor(h / V) by the same truncated reciprocal (one correction step).
+__host__ __device__ __forceinline__ uint32_t quot_by_recip(uint32_t h, uint32_t V, uint32_t m32) {
+  const uint32_t q = mulhi32(h, m32);
+  return h - q * V >= V ? q + 1 : q;
+}
+
 __host__ __device__ __forceinline__ uint32_t mod_by_recip(uint32_t h, uint32_t V, uint32_t m32, uint64_t) {
   const uint32_t q = mulhi32(h, m32);
   uint32_t r = h - q * V;

@@ -94,7 +94,10 @@ inline size_t plan_bytes(uint32_t max_seg, uint32_t max_tiles, uint32_t max_subb
          sizeof(uint32_t) * (kPlanArrays * (static_cast<size_t>(max_seg) + 1) + max_tiles + max_subbins);
 }
 
-enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2 };
+// DIG_RANGE (level 1 only): desc[0] maps a key to H = hash mod HR, and the
+// P + 1 u32 right after desc[0] are range starts (bounds[0] = 0,
+// non-decreasing); the digit is the last d < nd with bounds[d] <= H.
+enum DigitKind { DIG_PART = 0, DIG_COARSE = 1, DIG_SUB = 2, DIG_RANGE = 3 };
 enum SplitOp { OP_COUNT = 0, OP_SCATTER = 1 };
 
 // One split pass.  level 1: a single segment [0, n) with nd <= 256 digits and
@@ -114,6 +117,18 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const uint32_t* src, uint32_t n,
                               uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan, void* out,
                               bool found, hipStream_t s);
+
+// Count-balanced ranges (Algorithm 2, Phase 1): kMaxBins bins at most.
+constexpr uint32_t kMaxBins = 1u << 14;
+// counts[b] += keys with floor((hash mod HR) / bin_size) == b, b < nbins
+// (counts zeroed by the caller).
+hipError_t launch_bin_hist(int kt, const void* keys, uint32_t n, uint32_t HR, uint32_t bin_size, uint32_t nbins,
+                           uint32_t* counts, hipStream_t s);
+// From the scanned bin counts: splits[0..P] (first bin whose prefix reaches
+// floor(n d / P); splits[0] = 0, splits[P] = nbins) and the DIG_RANGE
+// descriptor at rdesc (mod HR, then bounds[d] = min(splits[d] * bin_size, HR)).
+hipError_t launch_range_splits(const uint32_t* bin_offset, uint32_t nbins, uint32_t n, uint32_t P, uint32_t HR,
+                               uint32_t bin_size, uint32_t* splits, PartDesc* rdesc, hipStream_t s);
 
 // Plan of the level-2 split, written into `plan` (plan_bytes(nseg,
 // max_tiles, max_subbins) bytes; the level-2 grid is max_tiles, the sub-bin
@@ -180,6 +195,12 @@ hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t 
 hipError_t launch_layout(const uint32_t* tile_base, uint32_t num_tiles, uint32_t P, uint32_t n,
                          uint32_t num, uint32_t den, uint64_t V_plain, uint32_t* part_offsets,
                          uint32_t* bucket_base, PartDesc* desc, hipStream_t s);
+
+// As launch_layout, with the table sizes and bucket bases copied from the
+// descriptors `src` of another table (P of them).
+hipError_t launch_layout_like(const uint32_t* tile_base, uint32_t num_tiles, uint32_t P, uint32_t n,
+                              const PartDesc* src, uint32_t* part_offsets, uint32_t* bucket_base, PartDesc* desc,
+                              hipStream_t s);
 
 hipError_t launch_hist(int kt, const void* keys, uint32_t n, uint32_t log2P, uint32_t P,
                        const PartDesc* desc, uint32_t* cnt, hipStream_t s);

@@ -194,6 +194,103 @@ __global__ __launch_bounds__(kBlock) void k_layout(const uint32_t* __restrict__ 
   if (t == 0) bb[P] = total;
 }
 
+// Layout of a table built like another (the query table of Sec. 3.3): the
+// partition offsets from the scanned tile counts, every table size and
+// bucket base copied from the source table, so that bucket g of both tables
+// holds the keys that hash to g.  One workgroup; P <= 256.
+__global__ __launch_bounds__(kBlock) void k_layout_like(const uint32_t* __restrict__ tile_base, uint32_t num_tiles,
+                                                        uint32_t P, uint32_t n, const PartDesc* __restrict__ src,
+                                                        uint32_t* __restrict__ po, uint32_t* __restrict__ bb,
+                                                        PartDesc* __restrict__ desc) {
+  const uint32_t t = threadIdx.x;
+  if (t < P) {
+    po[t] = (tile_base != nullptr && num_tiles != 0) ? tile_base[static_cast<uint64_t>(t) * num_tiles] : 0u;
+    const PartDesc d = src[t];
+    desc[t] = d;
+    bb[t] = d.base;
+  }
+  if (t == 0) {
+    po[P] = n;
+    bb[P] = src[P - 1].base + src[P - 1].V;
+  }
+}
+
+// ------------------------------------- count-balanced ranges (Alg. 2, Phase 1)
+// Keys per bin of the reduced hash range: H = hash(k) mod HR, bin =
+// floor(H / bin_size).  A persistent grid; a workgroup counts its share in
+// LDS (eight keys per thread in flight), then adds its nonzero counters to
+// the global ones.
+constexpr int kBinThreads = 1024;
+constexpr int kBinItems = 8;
+
+template <typename K>
+__global__ __launch_bounds__(kBinThreads) void k_bin_hist(const K* __restrict__ keys, uint32_t n, uint32_t HR,
+                                                          uint32_t bin_size, uint32_t nbins,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t hist[kMaxBins];
+  const uint32_t t = threadIdx.x;
+  for (uint32_t i = t; i < nbins; i += kBinThreads) hist[i] = 0;
+  const uint32_t m_hr = recip32(HR), m_bs = recip32(bin_size);
+  const uint64_t m_hr64 = recip64(HR);
+  __syncthreads();
+  constexpr uint64_t kStep = kBinThreads * kBinItems;
+  // 64-bit positions: n may come within one step of 2^32.
+  for (uint64_t base = blockIdx.x * kStep; base < n; base += gridDim.x * kStep) {
+    K v[kBinItems];
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+      const uint64_t i = base + static_cast<uint64_t>(u) * kBinThreads + t;
+      v[u] = keys[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kBinItems; ++u) {
+      const uint32_t H = mod_by_recip(KeyTraits<K>::hash(v[u]), HR, m_hr, m_hr64);
+      const uint32_t b = quot_by_recip(H, bin_size, m_bs);
+      if (base + static_cast<uint64_t>(u) * kBinThreads + t < n) atomicAdd(&hist[b], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < nbins; i += kBinThreads)
+    if (hist[i] != 0) atomicAdd(&counts[i], hist[i]);
+}
+
+// One workgroup: the range boundaries from the scanned bin counts (entry
+// nbins of the prefix sums is n), and the DIG_RANGE descriptor.
+__global__ __launch_bounds__(kBlock) void k_range_splits(const uint32_t* __restrict__ bin_offset, uint32_t nbins,
+                                                         uint32_t n, uint32_t P, uint32_t HR, uint32_t bin_size,
+                                                         uint32_t* __restrict__ splits,
+                                                         PartDesc* __restrict__ rdesc) {
+  uint32_t* bounds = reinterpret_cast<uint32_t*>(rdesc + 1);
+  for (uint32_t d = threadIdx.x; d <= P; d += kBlock) {
+    uint32_t sp = d == 0 ? 0u : nbins;
+    if (d > 0 && d < P) {
+      const uint64_t target = static_cast<uint64_t>(n) * d / P;
+      uint32_t lo = 0, hi = nbins + 1;  // first x in [0, nbins] with prefix(x) >= target
+      while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const uint32_t v = mid == nbins ? n : bin_offset[mid];
+        if (v < target)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      sp = lo;
+    }
+    splits[d] = sp;
+    const uint64_t hb = static_cast<uint64_t>(sp) * bin_size;
+    bounds[d] = static_cast<uint32_t>(hb < HR ? hb : HR);
+  }
+  if (threadIdx.x == 0) {
+    PartDesc pd;
+    pd.V = HR;
+    pd.base = 0;
+    pd.m32 = recip32(HR);
+    pd.pad = 0;
+    pd.m64 = recip64(HR);
+    rdesc[0] = pd;
+  }
+}
+
 // ------------------------------------------------ histogram and scatter (a5, a7)
 // One atomic per lane, except that the lanes sharing the first active lane's
 // bucket are combined into a single atomic (duplicate-heavy inputs).
@@ -361,6 +458,35 @@ hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_scan_down<<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout_like(const uint32_t* tile_base, uint32_t num_tiles, uint32_t P, uint32_t n,
+                              const PartDesc* src, uint32_t* part_offsets, uint32_t* bucket_base, PartDesc* desc,
+                              hipStream_t s) {
+  k_layout_like<<<1, kBlock, 0, s>>>(tile_base, num_tiles, P, n, src, part_offsets, bucket_base, desc);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_hist(int kt, const void* keys, uint32_t n, uint32_t HR, uint32_t bin_size, uint32_t nbins,
+                           uint32_t* counts, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nbins == 0 || nbins > kMaxBins || HR == 0 || bin_size == 0) return hipErrorInvalidValue;
+  constexpr uint32_t kStep = kBinThreads * kBinItems;
+  const uint32_t chunks = div_up(n, kStep);
+  const uint32_t grid = chunks < 512u ? chunks : 512u;
+  if (kt == 0)
+    k_bin_hist<uint32_t><<<grid, kBinThreads, 0, s>>>(static_cast<const uint32_t*>(keys), n, HR, bin_size, nbins,
+                                                      counts);
+  else
+    k_bin_hist<uint64_t><<<grid, kBinThreads, 0, s>>>(static_cast<const uint64_t*>(keys), n, HR, bin_size, nbins,
+                                                      counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_range_splits(const uint32_t* bin_offset, uint32_t nbins, uint32_t n, uint32_t P, uint32_t HR,
+                               uint32_t bin_size, uint32_t* splits, PartDesc* rdesc, hipStream_t s) {
+  k_range_splits<<<1, kBlock, 0, s>>>(bin_offset, nbins, n, P, HR, bin_size, splits, rdesc);
   return hipGetLastError();
 }
 

@@ -160,6 +160,7 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   __shared__ uint32_t delta[kCount ? 1 : MAXD];  // output position of the digit's run minus dstart
   __shared__ uint32_t wtot[THREADS / kWave];
   __shared__ PartDesc sd[DIG == DIG_PART ? 1 : kMaxP];
+  __shared__ uint32_t srange[DIG == DIG_RANGE ? kMaxP + 1 : 1];
   __shared__ K stage_k[kCount ? 1 : TILE];
   __shared__ uint16_t sdig[kCount ? 1 : TILE];
 
@@ -177,6 +178,10 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
     const PartDesc* dsrc = (plan != nullptr && plan->desc_by_seg) ? desc + seg : desc;
     for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
   }
+  if (DIG == DIG_RANGE) {
+    const uint32_t* bounds = reinterpret_cast<const uint32_t*>(desc + 1);
+    for (uint32_t i = t; i <= D; i += THREADS) srange[i] = bounds[i];
+  }
   for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
   __syncthreads();
 
@@ -191,6 +196,14 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   for (int i = 0; i < ITEMS; ++i) {
     if (DIG == DIG_PART) {
       d[i] = part_of(KeyTraits<K>::hash(v[i]), log2P);
+    } else if (DIG == DIG_RANGE) {
+      // The last range starting at or below H (bounds[0] = 0, D <= 256).
+      const uint32_t H = bucket_of(v[i], 0, sd);
+      uint32_t lo = 0;
+#pragma unroll
+      for (uint32_t st = 128; st > 0; st >>= 1)
+        if (lo + st < D && srange[lo + st] <= H) lo += st;
+      d[i] = lo;
     } else {
       const uint32_t g = bucket_of(v[i], log2P, sd);
       d[i] = min((g - gs) >> shift, D - 1);
@@ -1346,7 +1359,9 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
     }
     __syncthreads();
 
-    if (!soverflow) {
+    if (!soverflow && ssize[0] <= 1) {
+      // one distinct key: the bucket is already one run
+    } else if (!soverflow) {
       // 2. rank the distinct keys, then rewrite the bucket as ascending runs
       const uint32_t nd = ssize[0];
       K myv = 0;
@@ -1420,6 +1435,15 @@ template <typename K, int THREADS, int ITEMS, int MAXD, int OP>
 hipError_t msplit_dig(int dig, dim3 grid, const K* in, uint32_t n, const SegPlan* plan, uint32_t nd, uint32_t log2P,
                       uint32_t P, const PartDesc* desc, uint32_t shift, uint32_t* counts, K* out, uint16_t* perm,
                       hipStream_t s) {
+  if (dig == DIG_RANGE) {
+    if constexpr (MAXD <= 256) {  // level 1 only
+      k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_RANGE><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc,
+                                                                               shift, counts, out, perm);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (dig == DIG_PART)
     k_msplit<K, THREADS, ITEMS, MAXD, OP, DIG_PART><<<grid, THREADS, 0, s>>>(in, n, plan, nd, log2P, P, desc, shift,
                                                                             counts, out, perm);

@@ -54,7 +54,8 @@ def test_header_declares_the_core_calls():
     fns = declared_functions()
     for name in ["hg_build", "hg_count", "hg_query", "hg_bin_partition", "hg_hash_bucket", "hg_table_info",
                  "hg_table_export", "hg_table_free", "hg_status_string", "hg_last_error", "hg_build_batched",
-                 "hg_count_batched", "hg_query_batched", "hg_set_allocator", "hg_workspace_size"]:
+                 "hg_count_batched", "hg_query_batched", "hg_set_allocator", "hg_workspace_size",
+                 "hg_bin_partition_balanced", "hg_build_like", "hg_intersect"]:
         assert name in fns
 
 
@@ -233,3 +234,35 @@ def test_workspace_size_mirrors_the_calls_errors(lib):
     assert workspace(lib, 17)[0] == HG_ERR_INVALID_ARG
     st, ws, tb = workspace(lib, HG_OP_BUILD_BATCHED, n=1 << 20, aux=4096)
     assert st == HG_OK and tb >= (1 << 20) * 4 + ((1 << 20) + 4096 + 1) * 4
+
+
+def test_bin_partition_balanced_rejects(lib):
+    f = lib.hg_bin_partition_balanced
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    ok = dict(keys=FAKE, n=10, kt=0, P=3, HR=1000, bins=0, out=FAKE, po=FAKE, sp=FAKE)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["keys"], a["n"], a["kt"], a["P"], a["HR"], a["bins"], a["out"], a["po"], a["sp"], None)
+
+    assert call(P=0) == HG_ERR_INVALID_ARG
+    assert call(P=257) == HG_ERR_INVALID_ARG
+    assert call(HR=0) == HG_ERR_INVALID_ARG
+    assert call(HR=1 << 32) == HG_ERR_INVALID_ARG
+    assert call(bins=(1 << 14) + 1) == HG_ERR_INVALID_ARG
+    assert call(n=1 << 32) == HG_ERR_INVALID_ARG
+    assert call(kt=4) == HG_ERR_INVALID_ARG
+    assert call(po=None) == HG_ERR_INVALID_ARG
+    assert call(sp=None) == HG_ERR_INVALID_ARG
+    assert call(keys=None) == HG_ERR_INVALID_ARG
+    assert call(out=None) == HG_ERR_INVALID_ARG
+
+
+def test_build_like_and_intersect_reject_null(lib):
+    lib.hg_build_like.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+    lib.hg_intersect.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    h = ctypes.c_void_p()
+    assert lib.hg_build_like(None, FAKE, 10, None, ctypes.byref(h)) == HG_ERR_INVALID_ARG
+    assert lib.hg_intersect(None, None, FAKE, None) == HG_ERR_INVALID_ARG

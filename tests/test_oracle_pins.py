@@ -263,8 +263,91 @@ def pin_partition():
                 assert np.array_equal(out, np.sort(keys))
 
 
+def pin_balanced_worked_example():
+    """The hand-worked example of tests/golden/balanced_split_example.txt."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "balanced_split_example.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    HR = int(rows[0][1])
+    bins = int(rows[1][1])
+    H = np.array([int(x) for x in rows[2][1:]], dtype=np.uint32)
+    keys = fmix32_inverse(H)  # hash(key) = H < HR, so hash mod HR = H
+    for r in rows[3:]:
+        P = int(r[1])
+        i = r.index("part_offsets")
+        want_splits = [int(x) for x in r[3:i]]
+        want_po = [int(x) for x in r[i + 1:]]
+        po, splits, out = oracle.bin_partition_balanced(keys, P, HR, bins)
+        assert splits.tolist() == want_splits, (P, splits)
+        assert po.tolist() == want_po, (P, po)
+        hout = oracle_hash(out)
+        for d in range(P):
+            assert sorted(hout[po[d]:po[d + 1]].tolist()) == sorted(
+                int(h) for h in H if want_splits[d] <= int(h) // 10 < want_splits[d + 1])
+
+
+def pin_balanced_split_definition():
+    """Splits, grouping and balance checked against the definition by brute
+    force: every boundary by a linear scan of the prefix sums, every key's
+    partition from its own bin."""
+    rng_keys = [inputs.uniform_u32(30000, 41), inputs.sample_with_replacement(30000, 42),
+                inputs.zipf_u64(30000, 1 << 10, 43)]
+    for keys in rng_keys:
+        for P, HR, nb in [(1, 1 << 16, 0), (2, 1000, 0), (7, 1 << 20, 0), (16, 12345, 100), (256, 1 << 31, 0),
+                          (5, 1, 0), (3, 50000, 1)]:
+            po, splits, out = oracle.bin_partition_balanced(keys, P, HR, nb)
+            want_bins = nb or min(1 << 14, int(np.ceil(np.sqrt(HR))))
+            while want_bins * want_bins < HR and not nb and want_bins < (1 << 14):
+                want_bins += 1
+            bs = -(-HR // want_bins)
+            nbins = -(-HR // bs)
+            b = (oracle_hash(keys) % np.uint64(HR)).astype(np.int64) // bs
+            cnt = np.bincount(b, minlength=nbins)
+            off = np.concatenate([[0], np.cumsum(cnt)])
+            n = keys.size
+            assert splits[0] == 0 and splits[P] == nbins
+            for d in range(1, P):
+                target = n * d // P
+                first = next(x for x in range(nbins + 1) if off[x] >= target)
+                assert splits[d] == first, (P, HR, d)
+            bo = (oracle_hash(out) % np.uint64(HR)).astype(np.int64) // bs
+            for d in range(P):
+                seg = bo[po[d]:po[d + 1]]
+                assert np.all((seg >= splits[d]) & (seg < max(splits[d + 1], splits[d]))) or seg.size == 0
+                assert po[d + 1] - po[d] == cnt[splits[d]:splits[d + 1]].sum()
+            assert po[P] == n
+            assert np.array_equal(np.sort(out), np.sort(keys))
+            # Balance: the first d partitions hold at least their share and
+            # at most one bin more.
+            for d in range(1, P):
+                assert n * d // P <= po[d] <= n * d // P + cnt.max()
+
+
+def pin_build_like():
+    """The query set's HashGraph (Sec. 3.3) against the table build: built
+    from the table's own keys it is that table; for other queries, every
+    query that is a table key sits in the bucket where the table holds it."""
+    for dt in (np.uint32, np.uint64):
+        keys = inputs.uniform_u64(6000, 71).astype(dt)
+        for P, num, den, V in [(1, 1, 1, 0), (4, 1, 1, 0), (16, 1, 2, 0), (1, 1, 1, 777)]:
+            t = oracle.build_table(keys, P, num, den, V)
+            same = oracle.build_like(keys, keys, P, num, den, V)
+            for f in ("part_offsets", "bucket_base", "offsets", "keys"):
+                assert np.array_equal(same[f], t[f]), (P, f)
+            queries = inputs.queries_hit50(keys, 4000, 72)
+            q = oracle.build_like(keys, queries, P, num, den, V)
+            assert np.array_equal(q["bucket_base"], t["bucket_base"]) and q["offsets"].size == t["offsets"].size
+            assert np.array_equal(np.sort(q["keys"]), np.sort(queries))
+            qb = np.repeat(np.arange(q["offsets"].size - 1), np.diff(q["offsets"].astype(np.int64)))
+            tb = np.repeat(np.arange(t["offsets"].size - 1), np.diff(t["offsets"].astype(np.int64)))
+            where = dict(zip(t["keys"].tolist(), tb.tolist()))
+            for key, b in zip(q["keys"].tolist(), qb.tolist()):
+                if key in where:
+                    assert where[key] == b
+
+
 PINS = [pin_murmur3_published_vectors, pin_murmur3_against_library, pin_fmix32_inverse_round_trip,
-        pin_fmix64_inverse_round_trip, pin_csr_brute_force, pin_csr_invariants, pin_counts, pin_partition]
+        pin_fmix64_inverse_round_trip, pin_csr_brute_force, pin_csr_invariants, pin_counts, pin_partition,
+        pin_balanced_worked_example, pin_balanced_split_definition, pin_build_like]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -289,6 +372,11 @@ MUTANTS = {
                           "    run += bucket_count[g];\n    offsets[g] = static_cast<uint32_t>(run);"),
     "count_existence_only": ("counts[j] = static_cast<uint32_t>(r.second - r.first);",
                              "counts[j] = r.second != r.first ? 1u : 0u;"),
+    "balanced_search_upper": ("split[d] = static_cast<uint64_t>(std::lower_bound(bin_offset.begin(), ",
+                              "split[d] = static_cast<uint64_t>(std::upper_bound(bin_offset.begin(), "),
+    "balanced_target_shifted": ("const uint64_t target = n * d / P;", "const uint64_t target = n * (d + 1) / P;"),
+    "balanced_bin_size_floor": ("const uint64_t bin_size = (HR + bins_asked - 1) / bins_asked;",
+                                "const uint64_t bin_size = HR / bins_asked > 0 ? HR / bins_asked : 1;"),
 }
 
 
