@@ -821,8 +821,12 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
   HG_LAUNCH("bucket_scatter", stream, hg::launch_scatter(kt, src, n32, log2P, P, desc, offs + 1, keys_out, stream));
   HG_LAUNCH("find_long", stream, hg::launch_find_long(offs, bb + P, bound, long_ctr, long_list, stream));
   }
+  void* bigv = nullptr;
+  HG_TRY(mem.get(&bigv, hg::big_words(n, static_cast<uint32_t>(ks)) * sizeof(uint32_t)),
+         "allocate long-bucket chunk lists");
   HG_LAUNCH("long_sort", stream,
-            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted, stream));
+            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted,
+                                 static_cast<uint32_t*>(bigv), n, stream));
 
   hg_table* t = new hg_table();
   t->device = device;
@@ -970,8 +974,12 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   HG_LAUNCH("blds_build", stream,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, desc, offs, keys_out, long_ctr,
                                  long_list, hw.words, hw.max_chunks, stream));
+  void* bigv = nullptr;
+  HG_TRY(mem.get(&bigv, hg::big_words(n, static_cast<uint32_t>(ks)) * sizeof(uint32_t)),
+         "allocate long-bucket chunk lists");
   HG_LAUNCH("long_sort", stream,
-            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted, stream));
+            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted,
+                                 static_cast<uint32_t*>(bigv), n, stream));
 
   hg_table* t = new hg_table();
   t->device = device;

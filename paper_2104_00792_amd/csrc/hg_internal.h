@@ -50,10 +50,23 @@ constexpr uint32_t kLongGrid = 512;  // resident workgroups (two per CU)
 // Long buckets of an atomic-path build: appended to long_list.
 hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,
                             uint32_t* long_count, uint32_t* long_list, hipStream_t s);
+// Long buckets of more than kBigChunk keys are shared by many workgroups,
+// one chunk of kBigChunk keys each: chunk sets of distinct keys, one merge
+// per bucket, then the rewrite chunk by chunk.  Their bookkeeping lives in a
+// workspace of big_words(n, key bytes) u32 words.
+constexpr uint32_t kBigChunk = 1u << 16;
+constexpr uint32_t kSetMax = 64;  // distinct keys a long bucket may have to be rewritten as runs
+inline uint64_t big_buckets_max(uint64_t n) { return n / kBigChunk + 1; }
+inline uint64_t big_words(uint64_t n, uint32_t ks) {
+  const uint64_t nb = big_buckets_max(n), nc = 2 * nb;
+  return 4 + 2 * nb + 3 * nc + nc * kSetMax * (1 + ks / 4) + nb * (1 + (kSetMax + 1) + kSetMax * ks / 4) + 4;
+}
+
 // Sort every listed long bucket in place (persistent workgroups; `work` is a
-// zeroed counter).
+// zeroed counter; `big` a workspace of big_words(n, ks) words for n keys).
 hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
-                            uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s);
+                            uint32_t* work, void* keys, uint32_t* unsorted, uint32_t* big, uint64_t n,
+                            hipStream_t s);
 
 inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 8 : 4); }
 // Level-2 tiles of a segment start at its first key rounded down to this

@@ -1231,11 +1231,16 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 //   1. the distinct keys of the bucket and their multiplicities, found by
 //      leader election in each wave (one round per distinct key in the
 //      wave's 64 keys) and merged into a set of at most kSetMax;
-//   2. the bucket rewritten as runs of those keys in ascending order;
+//   2. the bucket rewritten as runs of those keys in ascending order (not
+//      needed for a single distinct key);
 //   3. a bucket with more distinct keys is bitonic-sorted in LDS when it has
 //      at most kSortCap keys, and otherwise listed as unsorted.
-constexpr uint32_t kSetMax = 64;
+// A bucket of more than kBigChunk keys is queued instead, in chunks: every
+// chunk finds its own distinct keys (k_big_scan), one workgroup per bucket
+// merges them and lays out the runs (k_big_fix), and every chunk rewrites
+// its range (k_big_write).
 constexpr uint32_t kSortCap = 4096;
+constexpr uint32_t kOver = 0xFFFFFFFFu;  // more than kSetMax distinct keys
 
 template <typename K>
 __device__ __forceinline__ K readlane_key(K v, uint32_t lane);
@@ -1271,12 +1276,161 @@ __device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, 
   return true;
 }
 
+// The distinct keys of src[a .. b) and their multiplicities, by the whole
+// workgroup: each wave builds a set, wave 0 merges them into sval[0] /
+// scnt[0] / ssize[0]; *soverflow is set when there are more than kSetMax.
+// Every thread calls it; it starts and ends with a barrier.
+template <typename K, int THREADS>
+__device__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K (*sval)[kSetMax],
+                            uint32_t (*scnt)[kSetMax], uint32_t* ssize, uint32_t* soverflow) {
+  constexpr int W = THREADS / kWave;
+  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
+  if (l == 0) ssize[w] = 0;
+  if (t == 0) *soverflow = 0;
+  __syncthreads();
+  // The wave keeps the last key it met and that key's pending count in
+  // registers, and touches the set only when the key changes (a run of one
+  // heavy key costs a ballot per 64 keys).  Each wave reads kGroups groups
+  // of 64 keys per round, all loads in flight before the first is used.
+  constexpr int kGroups = 8;
+  K last = K(0);
+  uint32_t pend = 0;
+  bool ok = true;
+  for (uint32_t c0 = a + w * kWave * kGroups; c0 < b && ok; c0 += THREADS * kGroups) {
+    if (*soverflow) break;
+    K kv[kGroups];
+#pragma unroll
+    for (int gi = 0; gi < kGroups; ++gi) {
+      const uint32_t i = c0 + gi * kWave + l;
+      kv[gi] = i < b ? src[i] : K(0);
+    }
+#pragma unroll
+    for (int gi = 0; gi < kGroups; ++gi) {
+      const uint32_t i = c0 + gi * kWave + l;
+      const bool valid = i < b;
+      const K key = kv[gi];
+      uint64_t active = ballot(valid);
+      if (pend != 0) {
+        const uint64_t same = ballot(valid && key == last);
+        pend += popc64(same);
+        active &= ~same;
+      }
+      while (active != 0 && ok) {
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(active)) - 1);
+        const K v = readlane_key(key, leader);
+        const uint64_t match = ballot(valid && key == v) & active;
+        active &= ~match;
+        if (pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) {
+          ok = false;
+          break;
+        }
+        last = v;
+        pend = popc64(match);
+      }
+    }
+  }
+  if (ok && pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) ok = false;
+  if (!ok && l == 0) *soverflow = 1;
+  __syncthreads();
+  if (w == 0 && !*soverflow) {
+    for (int x = 1; x < W; ++x) {
+      const uint32_t nx = ssize[x];
+      for (uint32_t e = 0; e < nx; ++e) {
+        if (!set_add(sval[0], scnt[0], &ssize[0], sval[x][e], scnt[x][e])) {
+          if (l == 0) *soverflow = 1;
+          break;
+        }
+      }
+      if (*soverflow) break;
+    }
+  }
+  __syncthreads();
+}
+
+// Ranks the nd distinct keys of sval[0] / scnt[0] into ascending order in
+// sval[1] / scnt[1] and their run starts into run0[0 .. nd].  Every thread
+// calls it (nd <= kSetMax <= THREADS).
+template <typename K>
+__device__ void rank_runs(uint32_t nd, K (*sval)[kSetMax], uint32_t (*scnt)[kSetMax], uint32_t* run0) {
+  const uint32_t t = threadIdx.x;
+  K myv = 0;
+  uint32_t myc = 0, rank = 0;
+  if (t < nd) {
+    myv = sval[0][t];
+    myc = scnt[0][t];
+    for (uint32_t j = 0; j < nd; ++j) rank += sval[0][j] < myv ? 1u : 0u;
+  }
+  __syncthreads();
+  if (t < nd) {
+    sval[1][rank] = myv;
+    scnt[1][rank] = myc;
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (uint32_t r = 0; r < nd; ++r) {
+      run0[r] = run;
+      run += scnt[1][r];
+    }
+    run0[nd] = run;
+  }
+  __syncthreads();
+}
+
+// Workspace of the chunked long buckets (big_words words).
+template <typename K>
+struct BigWork {
+  uint32_t* ctr;        // [0] big buckets, [1] chunks
+  uint32_t* big_g;      // bucket id of big bucket b
+  uint32_t* big_first;  // its first chunk
+  uint32_t* chunk_b;    // big bucket of chunk c
+  uint32_t* chunk_k;    // chunk number inside its bucket
+  uint32_t* chunk_n;    // distinct keys of chunk c, or kOver
+  uint32_t* chunk_cnt;  // [c][kSetMax]
+  K* chunk_key;         // [c][kSetMax]
+  uint32_t* run_n;      // distinct keys of big bucket b, or kOver
+  uint32_t* run0;       // [b][kSetMax + 1] run starts
+  K* run_key;           // [b][kSetMax]
+};
+
+template <typename K>
+BigWork<K> big_work(uint32_t* base, uint64_t n) {
+  const uint64_t nb = big_buckets_max(n), nc = 2 * nb;
+  auto align8 = [base](uint32_t* p) { return base + (((p - base) + 1) & ~static_cast<ptrdiff_t>(1)); };
+  BigWork<K> w;
+  uint32_t* p = base;
+  w.ctr = p;
+  p += 4;
+  w.big_g = p;
+  p += nb;
+  w.big_first = p;
+  p += nb;
+  w.chunk_b = p;
+  p += nc;
+  w.chunk_k = p;
+  p += nc;
+  w.chunk_n = p;
+  p += nc;
+  w.chunk_cnt = p;
+  p += nc * kSetMax;
+  p = align8(p);
+  w.chunk_key = reinterpret_cast<K*>(p);
+  p += nc * kSetMax * (sizeof(K) / 4);
+  w.run_n = p;
+  p += nb;
+  w.run0 = p;
+  p += nb * (kSetMax + 1);
+  p = align8(p);
+  w.run_key = reinterpret_cast<K*>(p);
+  return w;
+}
+
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __restrict__ offsets,
                                                             const uint32_t* __restrict__ long_list,
                                                             const uint32_t* __restrict__ long_count,
                                                             uint32_t* __restrict__ work, K* __restrict__ keys,
-                                                            uint32_t* __restrict__ unsorted) {
+                                                            uint32_t* __restrict__ unsorted, BigWork<K> bw) {
   constexpr int W = kLongThreads / kWave;
   __shared__ K sval[W][kSetMax];
   __shared__ uint32_t scnt[W][kSetMax];
@@ -1285,107 +1439,39 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   __shared__ uint32_t soverflow;
   __shared__ uint32_t sidx;
   __shared__ K sbuf[kSortCap];
-  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
+  const uint32_t t = threadIdx.x;
   const uint32_t total = *long_count;
   for (;;) {
     if (t == 0) sidx = atomicAdd(work, 1u);
-    if (l == 0) ssize[w] = 0;
-    if (t == 0) soverflow = 0;
     __syncthreads();
     const uint32_t idx = sidx;
     if (idx >= total) break;  // uniform: every thread read the same sidx
     const uint32_t g = long_list[idx];
     const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
-
-    // 1. distinct keys with multiplicities.  The wave keeps the last key it
-    // met and that key's pending count in registers, and touches the set
-    // only when the key changes (a bucket of one heavy key costs a ballot
-    // per 64 keys).
-    {
-      // Each wave reads kGroups groups of 64 keys per round (all loads in
-      // flight before the first is used).
-      constexpr int kGroups = 8;
-      K last = K(0);
-      uint32_t pend = 0;
-      bool ok = true;
-      for (uint32_t c0 = w * kWave * kGroups; c0 < L && ok; c0 += kLongThreads * kGroups) {
-        if (soverflow) break;
-        K kv[kGroups];
-#pragma unroll
-        for (int gi = 0; gi < kGroups; ++gi) {
-          const uint32_t i = c0 + gi * kWave + l;
-          kv[gi] = i < L ? keys[lo + i] : K(0);
-        }
-#pragma unroll
-        for (int gi = 0; gi < kGroups; ++gi) {
-          const uint32_t i = c0 + gi * kWave + l;
-          const bool valid = i < L;
-          const K key = kv[gi];
-          uint64_t active = ballot(valid);
-          if (pend != 0) {
-            const uint64_t same = ballot(valid && key == last);
-            pend += popc64(same);
-            active &= ~same;
-          }
-          while (active != 0 && ok) {
-            const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(active)) - 1);
-            const K v = readlane_key(key, leader);
-            const uint64_t match = ballot(valid && key == v) & active;
-            active &= ~match;
-            if (pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) {
-              ok = false;
-              break;
-            }
-            last = v;
-            pend = popc64(match);
-          }
+    if (L > kBigChunk) {
+      // Queued in chunks for the workgroups of k_big_scan.
+      if (t == 0) {
+        const uint32_t b = atomicAdd(&bw.ctr[0], 1u);
+        const uint32_t nch = (L + kBigChunk - 1) / kBigChunk;
+        const uint32_t at = atomicAdd(&bw.ctr[1], nch);
+        bw.big_g[b] = g;
+        bw.big_first[b] = at;
+        for (uint32_t k = 0; k < nch; ++k) {
+          bw.chunk_b[at + k] = b;
+          bw.chunk_k[at + k] = k;
         }
       }
-      if (ok && pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) ok = false;
-      if (!ok && l == 0) soverflow = 1;
+      __syncthreads();
+      continue;
     }
-    __syncthreads();
-    if (w == 0 && !soverflow) {
-      for (int x = 1; x < W; ++x) {
-        const uint32_t nx = ssize[x];
-        for (uint32_t e = 0; e < nx; ++e) {
-          if (!set_add(sval[0], scnt[0], &ssize[0], sval[x][e], scnt[x][e])) {
-            if (l == 0) soverflow = 1;
-            break;
-          }
-        }
-        if (soverflow) break;
-      }
-    }
-    __syncthreads();
 
+    wg_distinct<K, kLongThreads>(keys + lo, 0, L, sval, scnt, ssize, &soverflow);
     if (!soverflow && ssize[0] <= 1) {
       // one distinct key: the bucket is already one run
     } else if (!soverflow) {
-      // 2. rank the distinct keys, then rewrite the bucket as ascending runs
+      // rank the distinct keys, then rewrite the bucket as ascending runs
       const uint32_t nd = ssize[0];
-      K myv = 0;
-      uint32_t myc = 0, rank = 0;
-      if (t < nd) {
-        myv = sval[0][t];
-        myc = scnt[0][t];
-        for (uint32_t j = 0; j < nd; ++j) rank += sval[0][j] < myv ? 1u : 0u;
-      }
-      __syncthreads();
-      if (t < nd) {
-        sval[1][rank] = myv;
-        scnt[1][rank] = myc;
-      }
-      __syncthreads();
-      if (t == 0) {
-        uint32_t run = 0;
-        for (uint32_t r = 0; r < nd; ++r) {
-          run0[r] = run;
-          run += scnt[1][r];
-        }
-        run0[nd] = run;
-      }
-      __syncthreads();
+      rank_runs<K>(nd, sval, scnt, run0);
       // Positions only grow along a thread's loop: walk the run index.
       uint32_t a = 0;
       for (uint32_t i = t; i < L; i += kLongThreads) {
@@ -1393,7 +1479,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
         keys[lo + i] = sval[1][a];
       }
     } else if (L <= kSortCap) {
-      // 3. many distinct keys, few enough to sort in LDS
+      // many distinct keys, few enough to sort in LDS
       uint32_t p2 = 1;
       while (p2 < L) p2 <<= 1;
       for (uint32_t i = t; i < p2; i += kLongThreads) sbuf[i] = i < L ? keys[lo + i] : ~K(0);
@@ -1420,6 +1506,117 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
       if (u < kMaxUnsorted) unsorted[1 + u] = g;
     }
     __syncthreads();
+  }
+}
+
+// Every queued chunk of a big bucket: its distinct keys (or kOver).
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_big_scan(const uint32_t* __restrict__ offsets,
+                                                           const K* __restrict__ keys, BigWork<K> bw) {
+  constexpr int W = kLongThreads / kWave;
+  __shared__ K sval[W][kSetMax];
+  __shared__ uint32_t scnt[W][kSetMax];
+  __shared__ uint32_t ssize[W];
+  __shared__ uint32_t soverflow;
+  const uint32_t t = threadIdx.x;
+  const uint32_t nch = bw.ctr[1];
+  for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const uint32_t g = bw.big_g[bw.chunk_b[c]];
+    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+    const uint32_t a = bw.chunk_k[c] * kBigChunk, b = min(L, a + kBigChunk);
+    wg_distinct<K, kLongThreads>(keys + lo, a, b, sval, scnt, ssize, &soverflow);
+    const uint32_t nd = soverflow ? kOver : ssize[0];
+    if (t == 0) bw.chunk_n[c] = nd;
+    if (nd != kOver && t < nd) {
+      bw.chunk_key[static_cast<size_t>(c) * kSetMax + t] = sval[0][t];
+      bw.chunk_cnt[static_cast<size_t>(c) * kSetMax + t] = scnt[0][t];
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per big bucket: the chunk sets merged, ranked into runs;
+// too many distinct keys list the bucket as unsorted.
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __restrict__ offsets, BigWork<K> bw,
+                                                          uint32_t* __restrict__ unsorted) {
+  constexpr int W = kLongThreads / kWave;
+  __shared__ K sval[W][kSetMax];
+  __shared__ uint32_t scnt[W][kSetMax];
+  __shared__ uint32_t ssize[1];
+  __shared__ uint32_t run0[kSetMax + 1];
+  __shared__ uint32_t soverflow;
+  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
+  const uint32_t nbig = bw.ctr[0];
+  for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    const uint32_t g = bw.big_g[bi];
+    const uint32_t L = offsets[g + 1] - offsets[g];
+    const uint32_t first = bw.big_first[bi], nch = (L + kBigChunk - 1) / kBigChunk;
+    if (t == 0) {
+      ssize[0] = 0;
+      soverflow = 0;
+    }
+    __syncthreads();
+    if (w == 0) {
+      for (uint32_t c = first; c < first + nch && !soverflow; ++c) {
+        const uint32_t nd = bw.chunk_n[c];
+        if (nd == kOver) {
+          if (l == 0) soverflow = 1;
+          break;
+        }
+        for (uint32_t e = 0; e < nd; ++e) {
+          if (!set_add(sval[0], scnt[0], &ssize[0], bw.chunk_key[static_cast<size_t>(c) * kSetMax + e],
+                       bw.chunk_cnt[static_cast<size_t>(c) * kSetMax + e])) {
+            if (l == 0) soverflow = 1;
+            break;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    if (soverflow) {
+      if (t == 0) {
+        bw.run_n[bi] = kOver;
+        const uint32_t u = atomicAdd(&unsorted[0], 1u);
+        if (u < kMaxUnsorted) unsorted[1 + u] = g;
+      }
+    } else {
+      const uint32_t nd = ssize[0];
+      rank_runs<K>(nd, sval, scnt, run0);
+      if (t < nd) bw.run_key[static_cast<size_t>(bi) * kSetMax + t] = sval[1][t];
+      if (t <= nd) bw.run0[static_cast<size_t>(bi) * (kSetMax + 1) + t] = run0[t];
+      if (t == 0) bw.run_n[bi] = nd;
+    }
+    __syncthreads();
+  }
+}
+
+// Every chunk of a big bucket with 2 .. kSetMax distinct keys: its range
+// rewritten from the bucket's runs.
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_big_write(const uint32_t* __restrict__ offsets,
+                                                            K* __restrict__ keys, BigWork<K> bw) {
+  __shared__ uint32_t run0[kSetMax + 1];
+  __shared__ K rkey[kSetMax];
+  const uint32_t t = threadIdx.x;
+  const uint32_t nch = bw.ctr[1];
+  for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const uint32_t bi = bw.chunk_b[c];
+    const uint32_t nd = bw.run_n[bi];
+    if (nd == kOver || nd <= 1) continue;  // uniform over the workgroup
+    const uint32_t g = bw.big_g[bi];
+    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+    const uint32_t a = bw.chunk_k[c] * kBigChunk, b = min(L, a + kBigChunk);
+    __syncthreads();  // the previous chunk is done with run0 / rkey
+    if (t <= nd) run0[t] = bw.run0[static_cast<size_t>(bi) * (kSetMax + 1) + t];
+    if (t < nd) rkey[t] = bw.run_key[static_cast<size_t>(bi) * kSetMax + t];
+    __syncthreads();
+    uint32_t r = 0;
+    for (uint32_t i = a + t; i < b; i += kLongThreads) {
+      while (r + 1 < nd && run0[r + 1] <= i) ++r;
+      keys[lo + i] = rkey[r];
+    }
   }
 }
 
@@ -1621,15 +1818,30 @@ hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets
   return hipGetLastError();
 }
 
-hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
-                            uint32_t* work, void* keys, uint32_t* unsorted, hipStream_t s) {
-  if (kt == 0)
-    k_long_sort<uint32_t><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work,
-                                                             static_cast<uint32_t*>(keys), unsorted);
-  else
-    k_long_sort<uint64_t><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work,
-                                                             static_cast<uint64_t*>(keys), unsorted);
+template <typename K>
+hipError_t long_sort_typed(const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
+                           uint32_t* work, K* keys, uint32_t* unsorted, uint32_t* big, uint64_t n, hipStream_t s) {
+  const BigWork<K> bw = big_work<K>(big, n);
+  hipError_t e = launch_fill_u32(bw.ctr, 2, 0u, s);
+  if (e != hipSuccess) return e;
+  k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work, keys, unsorted, bw);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_big_scan<K><<<2 * kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_big_fix<K><<<kLongGrid / 2, kLongThreads, 0, s>>>(offsets, bw, unsorted);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_big_write<K><<<2 * kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
   return hipGetLastError();
+}
+
+hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
+                            uint32_t* work, void* keys, uint32_t* unsorted, uint32_t* big, uint64_t n,
+                            hipStream_t s) {
+  if (kt == 0)
+    return long_sort_typed<uint32_t>(offsets, long_list, long_count, work, static_cast<uint32_t*>(keys), unsorted,
+                                     big, n, s);
+  return long_sort_typed<uint64_t>(offsets, long_list, long_count, work, static_cast<uint64_t*>(keys), unsorted, big,
+                                   n, s);
 }
 
 }  // namespace hg

@@ -223,6 +223,14 @@ LONG_CASES = {
     # many distinct keys in buckets longer than 4096: left unsorted, scanned
     "unsorted_V3": lambda: (make_keys("uniform", 20000, np.uint64, 9), 3),
     "mixed_70x100_V2": lambda: (np.repeat(np.arange(70, dtype=np.uint64) * 977, 100), 2),
+    # buckets longer than 2^16 keys, shared by many workgroups in chunks:
+    # 12 values in shuffled order over 4 buckets (a few runs per bucket), one
+    # value 200000 times, 300 values over 2 buckets (too many to rewrite), and
+    # a bucket of exactly 2^16 + 1 keys with two values
+    "big_runs_V4": lambda: ((np.arange(12, dtype=np.uint64) * 7919)[inputs.uniform_u32(300000, 44) % 12], 4),
+    "big_one_key": lambda: (np.full(200000, 99, np.uint64), 0),
+    "big_unsorted_V2": lambda: ((np.arange(300, dtype=np.uint64) * 31)[inputs.uniform_u32(150000, 45) % 300], 2),
+    "big_two_chunks_V1": lambda: (np.array([5, 3], np.uint64)[inputs.uniform_u32((1 << 16) + 1, 46) % 2], 1),
 }
 
 
