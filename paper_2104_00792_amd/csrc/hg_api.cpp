@@ -777,11 +777,12 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
 
   // Long-bucket bookkeeping: at most n / (kLongT + 1) buckets exceed kLongT.
   void* longv = nullptr;
-  const uint64_t long_cap = n / (hg::kLongT + 1) + 1;
-  HG_TRY(mem.get(&longv, (2 + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
-  uint32_t* long_ctr = static_cast<uint32_t*>(longv);  // [0] count, [1] work counter
-  uint32_t* long_list = long_ctr + 2;
-  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, 2, 0u, stream));
+  const uint64_t long_cap = hg::long_list_cap(n);
+  HG_TRY(mem.get(&longv, (hg::kLongCtr + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
+  uint32_t* long_ctr = static_cast<uint32_t*>(longv);
+  uint32_t* long_list = long_ctr + hg::kLongCtr;
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, hg::kLongCtr, 0u, stream));
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr + 4, 1, static_cast<uint32_t>(long_cap), stream));
   HG_LAUNCH("zero_unsorted", stream, hg::launch_fill_u32(unsorted, 1, 0u, stream));
 
   const SplitParams sp = split_params(P, n, bound, opts);
@@ -825,8 +826,8 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
   HG_TRY(mem.get(&bigv, hg::big_words(n, static_cast<uint32_t>(ks)) * sizeof(uint32_t)),
          "allocate long-bucket chunk lists");
   HG_LAUNCH("long_sort", stream,
-            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted,
-                                 static_cast<uint32_t*>(bigv), n, stream));
+            hg::launch_long_sort(kt, offs, long_ctr, long_list, keys_out, unsorted, static_cast<uint32_t*>(bigv), n,
+                                 stream));
 
   hg_table* t = new hg_table();
   t->device = device;
@@ -946,12 +947,13 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   dp = (dp + 7) & ~static_cast<uintptr_t>(7);
   hg::PartDesc* desc = reinterpret_cast<hg::PartDesc*>(dp);
   uint32_t* unsorted = reinterpret_cast<uint32_t*>(desc + T);
-  const uint64_t long_cap = n / (hg::kLongT + 1) + 1;
-  HG_TRY(mem.get(&longv, (2 + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
+  const uint64_t long_cap = hg::long_list_cap(n);
+  HG_TRY(mem.get(&longv, (hg::kLongCtr + long_cap) * sizeof(uint32_t)), "allocate long-bucket list");
   uint32_t* long_ctr = static_cast<uint32_t*>(longv);
-  uint32_t* long_list = long_ctr + 2;
+  uint32_t* long_list = long_ctr + hg::kLongCtr;
   uint32_t* offs = static_cast<uint32_t*>(offsets);
-  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, 2, 0u, stream));
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr, hg::kLongCtr, 0u, stream));
+  HG_LAUNCH("zero_long", stream, hg::launch_fill_u32(long_ctr + 4, 1, static_cast<uint32_t>(long_cap), stream));
   HG_LAUNCH("zero_unsorted", stream, hg::launch_fill_u32(unsorted, 1, 0u, stream));
   HG_LAUNCH("batch_layout", stream,
             hg::launch_batch_layout(d_table_offsets, T, n32, opts->ratio_num, opts->ratio_den, po, bb, desc, stream));
@@ -978,8 +980,8 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   HG_TRY(mem.get(&bigv, hg::big_words(n, static_cast<uint32_t>(ks)) * sizeof(uint32_t)),
          "allocate long-bucket chunk lists");
   HG_LAUNCH("long_sort", stream,
-            hg::launch_long_sort(kt, offs, long_list, long_ctr, long_ctr + 1, keys_out, unsorted,
-                                 static_cast<uint32_t*>(bigv), n, stream));
+            hg::launch_long_sort(kt, offs, long_ctr, long_list, keys_out, unsorted, static_cast<uint32_t*>(bigv), n,
+                                 stream));
 
   hg_table* t = new hg_table();
   t->device = device;

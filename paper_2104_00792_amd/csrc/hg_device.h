@@ -123,6 +123,15 @@ __device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t lane) {
   return __builtin_amdgcn_readlane(v, lane);
 }
 
+// A value that every lane of the wave holds alike (say one LDS word that all
+// lanes read), taken from the first active lane.  The compiler then knows it
+// is wave-uniform: branches and loop exits that depend on it stay scalar, so
+// the wave is never split between the paths of a loop.  Without it, a loop
+// whose exit depends on an LDS load is compiled with per-lane exit masks, and
+// lanes may re-enter the loop while others wait at its exit; a value one lane
+// computes and readlane broadcasts is then read while that lane is away.
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Inclusive sum over the 64 lanes of a wave with DPP lane moves (no LDS
 // round trip): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
 // last lane of a row is broadcast into the next row (row_bcast:15 into rows 1

@@ -44,6 +44,14 @@ constexpr uint32_t kProbeKeyCapBytes = 40 * 1024;  // table keys of one window i
 // long bucket is scanned).
 constexpr uint32_t kLongT = 64;
 constexpr uint32_t kMaxUnsorted = 256;
+// Long buckets of at most kWaveLong keys are sorted by one wave each, longer
+// ones by a workgroup.  Their ids share one list (the short ones from the
+// front, the others from the back) of long_list_cap(n) entries, after
+// kLongCtr counter words: [0] short ones, [1] their work counter, [2] long
+// ones, [3] their work counter, [4] the list's length.
+constexpr uint32_t kWaveLong = 4096;
+constexpr uint32_t kLongCtr = 8;
+inline uint64_t long_list_cap(uint64_t n) { return 2 * (n / (kLongT + 1) + 1); }
 constexpr int kLongThreads = 1024;
 constexpr uint32_t kLongGrid = 512;  // resident workgroups (two per CU)
 
@@ -56,17 +64,18 @@ hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets
 // workspace of big_words(n, key bytes) u32 words.
 constexpr uint32_t kBigChunk = 1u << 16;
 constexpr uint32_t kSetMax = 64;  // distinct keys a long bucket may have to be rewritten as runs
+constexpr uint32_t kOver = 0xFFFFFFFFu;  // marks more than kSetMax distinct keys
 inline uint64_t big_buckets_max(uint64_t n) { return n / kBigChunk + 1; }
 inline uint64_t big_words(uint64_t n, uint32_t ks) {
   const uint64_t nb = big_buckets_max(n), nc = 2 * nb;
   return 4 + 2 * nb + 3 * nc + nc * kSetMax * (1 + ks / 4) + nb * (1 + (kSetMax + 1) + kSetMax * ks / 4) + 4;
 }
 
-// Sort every listed long bucket in place (persistent workgroups; `work` is a
-// zeroed counter; `big` a workspace of big_words(n, ks) words for n keys).
-hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
-                            uint32_t* work, void* keys, uint32_t* unsorted, uint32_t* big, uint64_t n,
-                            hipStream_t s);
+// Sort every listed long bucket in place (persistent workgroups; long_ctr
+// and long_list as above; `big` a workspace of big_words(n, ks) words for n
+// keys).
+hipError_t launch_long_sort(int kt, const uint32_t* offsets, uint32_t* long_ctr, uint32_t* long_list, void* keys,
+                            uint32_t* unsorted, uint32_t* big, uint64_t n, hipStream_t s);
 
 inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 8 : 4); }
 // Level-2 tiles of a segment start at its first key rounded down to this

@@ -702,9 +702,14 @@ __device__ __forceinline__ void st_l2(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Appends bucket g to the long-bucket list.
-__device__ __forceinline__ void note_long(uint32_t* long_count, uint32_t* long_list, uint32_t g) {
-  long_list[atomicAdd(long_count, 1u)] = g;
+// Appends long bucket g (len keys) to its list.  Both lists share one
+// array of ctr[4] entries: buckets of at most kWaveLong keys from the front
+// (ctr[0] of them), longer ones from the back (ctr[2]).
+__device__ __forceinline__ void note_long(uint32_t* ctr, uint32_t* list, uint32_t g, uint32_t len) {
+  if (len <= kWaveLong)
+    list[atomicAdd(&ctr[0], 1u)] = g;
+  else
+    list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
 }
 
 // MINW: waves per SIMD to fit (8: two workgroups of 1024 threads per CU).
@@ -766,7 +771,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       const uint32_t e0 = get_half(lds, i);
       offsets[sb.gA + i] = sb.kA + e0;
       const uint32_t e1 = i + 1 < R ? get_half(lds, i + 1) : m;
-      if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+      if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i, e1 - e0);
     }
     __syncthreads();
     if (!regs) {
@@ -865,7 +870,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   for (uint32_t i = t; i < R; i += THREADS) {
     const uint32_t e0 = ld_l2(&offsets[sb.gA + i]);
     const uint32_t e1 = i + 1 < R ? ld_l2(&offsets[sb.gA + i + 1]) : sb.kB;
-    if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i);
+    if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i, e1 - e0);
   }
 }
 
@@ -1015,7 +1020,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_fix(const SegPlan* __restrict
     for (uint32_t i = t; i < R; i += THREADS) {
       const uint32_t start = i == 0 ? sb.kA : c[i - 1];
       offsets[sb.gA + i] = start;
-      if (c[i] - start > kLongT) note_long(long_count, long_list, sb.gA + i);
+      if (c[i] - start > kLongT) note_long(long_count, long_list, sb.gA + i, c[i] - start);
     }
   }
 }
@@ -1240,7 +1245,6 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 // merges them and lays out the runs (k_big_fix), and every chunk rewrites
 // its range (k_big_write).
 constexpr uint32_t kSortCap = 4096;
-constexpr uint32_t kOver = 0xFFFFFFFFu;  // more than kSetMax distinct keys
 
 template <typename K>
 __device__ __forceinline__ K readlane_key(K v, uint32_t lane);
@@ -1260,7 +1264,7 @@ __device__ __forceinline__ uint64_t readlane_key<uint64_t>(uint64_t v, uint32_t 
 template <typename K>
 __device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, uint32_t c) {
   const uint32_t l = lane_id();
-  const uint32_t n = *sz;
+  const uint32_t n = wave_uniform(*sz);
   const uint64_t hit = ballot(l < n && sv[l] == v);
   if (hit != 0) {
     if (l == static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(hit)) - 1)) sc[l] += c;
@@ -1276,28 +1280,24 @@ __device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, 
   return true;
 }
 
-// The distinct keys of src[a .. b) and their multiplicities, by the whole
-// workgroup: each wave builds a set, wave 0 merges them into sval[0] /
-// scnt[0] / ssize[0]; *soverflow is set when there are more than kSetMax.
-// Every thread calls it; it starts and ends with a barrier.
-template <typename K, int THREADS>
-__device__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K (*sval)[kSetMax],
-                            uint32_t (*scnt)[kSetMax], uint32_t* ssize, uint32_t* soverflow) {
-  constexpr int W = THREADS / kWave;
-  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
-  if (l == 0) ssize[w] = 0;
-  if (t == 0) *soverflow = 0;
-  __syncthreads();
-  // The wave keeps the last key it met and that key's pending count in
-  // registers, and touches the set only when the key changes (a run of one
-  // heavy key costs a ballot per 64 keys).  Each wave reads kGroups groups
-  // of 64 keys per round, all loads in flight before the first is used.
+// The distinct keys of src[i] for the i in [a, b) that this wave visits
+// (groups of 64 from `first`, then every `step`), with multiplicities, added
+// to the wave's set sv / sc / *sz.  False when the set overflows (or *stop
+// turns nonzero: another wave's set overflowed).  The wave keeps the last
+// key it met and that key's pending count in registers, and touches the set
+// only when the key changes (a run of one heavy key costs a ballot per 64
+// keys); it reads kGroups groups of 64 keys per round, all loads in flight
+// before the first is used.
+template <typename K>
+__device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_t first, uint32_t b, uint32_t step, K* sv,
+                              uint32_t* sc, uint32_t* sz, const uint32_t* stop) {
   constexpr int kGroups = 8;
+  const uint32_t l = lane_id();
   K last = K(0);
   uint32_t pend = 0;
   bool ok = true;
-  for (uint32_t c0 = a + w * kWave * kGroups; c0 < b && ok; c0 += THREADS * kGroups) {
-    if (*soverflow) break;
+  for (uint32_t c0 = first; c0 < b && ok; c0 += step) {
+    if (stop != nullptr && wave_uniform(*stop)) return false;
     K kv[kGroups];
 #pragma unroll
     for (int gi = 0; gi < kGroups; ++gi) {
@@ -1320,7 +1320,7 @@ __device__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K
         const K v = readlane_key(key, leader);
         const uint64_t match = ballot(valid && key == v) & active;
         active &= ~match;
-        if (pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) {
+        if (pend != 0 && !set_add(sv, sc, sz, last, pend)) {
           ok = false;
           break;
         }
@@ -1329,19 +1329,38 @@ __device__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K
       }
     }
   }
-  if (ok && pend != 0 && !set_add(sval[w], scnt[w], &ssize[w], last, pend)) ok = false;
+  if (ok && pend != 0 && !set_add(sv, sc, sz, last, pend)) ok = false;
+  return ok;
+}
+
+// The distinct keys of src[a .. b) and their multiplicities, by the whole
+// workgroup: each wave builds a set, wave 0 merges them into sval[0] /
+// scnt[0] / ssize[0]; *soverflow is set when there are more than kSetMax.
+// Every thread calls it; it starts and ends with a barrier.
+template <typename K, int THREADS>
+__device__ __forceinline__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K (*sval)[kSetMax],
+                            uint32_t (*scnt)[kSetMax], uint32_t* ssize, uint32_t* soverflow) {
+  constexpr int W = THREADS / kWave;
+  constexpr uint32_t kGroup = kWave * 8;
+  const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
+  if (l == 0) ssize[w] = 0;
+  if (t == 0) *soverflow = 0;
+  __syncthreads();
+  const bool ok = wave_distinct<K>(src, a + w * kGroup, b, THREADS * 8, sval[w], scnt[w], &ssize[w], soverflow);
   if (!ok && l == 0) *soverflow = 1;
   __syncthreads();
-  if (w == 0 && !*soverflow) {
+  if (w == 0 && !wave_uniform(*soverflow)) {
     for (int x = 1; x < W; ++x) {
-      const uint32_t nx = ssize[x];
+      const uint32_t nx = wave_uniform(ssize[x]);
+      bool full = false;
       for (uint32_t e = 0; e < nx; ++e) {
         if (!set_add(sval[0], scnt[0], &ssize[0], sval[x][e], scnt[x][e])) {
           if (l == 0) *soverflow = 1;
+          full = true;
           break;
         }
       }
-      if (*soverflow) break;
+      if (full) break;
     }
   }
   __syncthreads();
@@ -1351,7 +1370,7 @@ __device__ void wg_distinct(const K* __restrict__ src, uint32_t a, uint32_t b, K
 // sval[1] / scnt[1] and their run starts into run0[0 .. nd].  Every thread
 // calls it (nd <= kSetMax <= THREADS).
 template <typename K>
-__device__ void rank_runs(uint32_t nd, K (*sval)[kSetMax], uint32_t (*scnt)[kSetMax], uint32_t* run0) {
+__device__ __forceinline__ void rank_runs(uint32_t nd, K (*sval)[kSetMax], uint32_t (*scnt)[kSetMax], uint32_t* run0) {
   const uint32_t t = threadIdx.x;
   K myv = 0;
   uint32_t myc = 0, rank = 0;
@@ -1425,11 +1444,57 @@ BigWork<K> big_work(uint32_t* base, uint64_t n) {
   return w;
 }
 
+// Long buckets of at most kWaveLong keys, one wave each: distinct keys
+// (ballots into the wave's set), then the runs in ascending order written
+// by the whole wave.  A bucket with more than kSetMax distinct keys moves to
+// the list of longer buckets (the workgroups of k_long_sort).
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_long_small(const uint32_t* __restrict__ offsets,
+                                                             uint32_t* __restrict__ ctr, uint32_t* __restrict__ list,
+                                                             K* __restrict__ keys) {
+  constexpr int W = kLongThreads / kWave;
+  __shared__ K sval[W][kSetMax];
+  __shared__ uint32_t scnt[W][kSetMax];
+  __shared__ uint32_t ssize[W];
+  const uint32_t w = threadIdx.x / kWave, l = lane_id();
+  const uint32_t total = ctr[0];
+  for (;;) {
+    // A plain load first: once the list is used up (or empty), the waves
+    // leave without queueing atomics on one address.
+    if (wave_uniform(ld_l2(&ctr[1])) >= total) break;
+    // Every lane takes part in the claim (lane 0 adds one, the others zero)
+    // and lane 0's old value is the wave's bucket.  No branch on the lane
+    // here: with `if (l == 0)` at the top of the loop, the compiler may send
+    // the other lanes back to the broadcast without lane 0 (see wave_uniform).
+    const uint32_t idx = readlane(atomicAdd(&ctr[1], l == 0 ? 1u : 0u), 0);
+    if (idx >= total) break;  // uniform over the wave
+    const uint32_t g = wave_uniform(list[idx]);
+    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+    if (l == 0) ssize[w] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (!wave_distinct<K>(keys + lo, 0, L, kWave * 8, sval[w], scnt[w], &ssize[w], nullptr)) {
+      if (l == 0) list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
+      continue;
+    }
+    const uint32_t nd = wave_uniform(ssize[w]);
+    if (nd <= 1) continue;  // one run already
+    // Lane e < nd holds distinct key e; its run starts after the smaller keys.
+    const K v = l < nd ? sval[w][l] : K(0);
+    const uint32_t c = l < nd ? scnt[w][l] : 0u;
+    uint32_t start = 0;
+    for (uint32_t j = 0; j < nd; ++j) start += sval[w][j] < v ? scnt[w][j] : 0u;
+    for (uint32_t e = 0; e < nd; ++e) {
+      const uint32_t rs = readlane(start, e), rc = readlane(c, e);
+      const K key = readlane_key(v, e);
+      for (uint32_t i = l; i < rc; i += kWave) keys[lo + rs + i] = key;
+    }
+  }
+}
+
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __restrict__ offsets,
-                                                            const uint32_t* __restrict__ long_list,
-                                                            const uint32_t* __restrict__ long_count,
-                                                            uint32_t* __restrict__ work, K* __restrict__ keys,
+                                                            uint32_t* __restrict__ ctr,
+                                                            const uint32_t* __restrict__ list, K* __restrict__ keys,
                                                             uint32_t* __restrict__ unsorted, BigWork<K> bw) {
   constexpr int W = kLongThreads / kWave;
   __shared__ K sval[W][kSetMax];
@@ -1440,13 +1505,13 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   __shared__ uint32_t sidx;
   __shared__ K sbuf[kSortCap];
   const uint32_t t = threadIdx.x;
-  const uint32_t total = *long_count;
+  const uint32_t total = ctr[2], cap = ctr[4];
   for (;;) {
-    if (t == 0) sidx = atomicAdd(work, 1u);
+    if (t == 0) sidx = ld_l2(&ctr[3]) < total ? atomicAdd(&ctr[3], 1u) : total;
     __syncthreads();
-    const uint32_t idx = sidx;
+    const uint32_t idx = wave_uniform(sidx);
     if (idx >= total) break;  // uniform: every thread read the same sidx
-    const uint32_t g = long_list[idx];
+    const uint32_t g = list[cap - 1 - idx];
     const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
     if (L > kBigChunk) {
       // Queued in chunks for the workgroups of k_big_scan.
@@ -1466,11 +1531,13 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
     }
 
     wg_distinct<K, kLongThreads>(keys + lo, 0, L, sval, scnt, ssize, &soverflow);
-    if (!soverflow && ssize[0] <= 1) {
+    const bool over = wave_uniform(soverflow) != 0;
+    const uint32_t nd0 = wave_uniform(ssize[0]);
+    if (!over && nd0 <= 1) {
       // one distinct key: the bucket is already one run
-    } else if (!soverflow) {
+    } else if (!over) {
       // rank the distinct keys, then rewrite the bucket as ascending runs
-      const uint32_t nd = ssize[0];
+      const uint32_t nd = nd0;
       rank_runs<K>(nd, sval, scnt, run0);
       // Positions only grow along a thread's loop: walk the run index.
       uint32_t a = 0;
@@ -1525,7 +1592,7 @@ __global__ __launch_bounds__(kLongThreads) void k_big_scan(const uint32_t* __res
     const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
     const uint32_t a = bw.chunk_k[c] * kBigChunk, b = min(L, a + kBigChunk);
     wg_distinct<K, kLongThreads>(keys + lo, a, b, sval, scnt, ssize, &soverflow);
-    const uint32_t nd = soverflow ? kOver : ssize[0];
+    const uint32_t nd = wave_uniform(soverflow) ? kOver : wave_uniform(ssize[0]);
     if (t == 0) bw.chunk_n[c] = nd;
     if (nd != kOver && t < nd) {
       bw.chunk_key[static_cast<size_t>(c) * kSetMax + t] = sval[0][t];
@@ -1558,8 +1625,9 @@ __global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __rest
     }
     __syncthreads();
     if (w == 0) {
-      for (uint32_t c = first; c < first + nch && !soverflow; ++c) {
-        const uint32_t nd = bw.chunk_n[c];
+      bool full = false;
+      for (uint32_t c = first; c < first + nch && !full; ++c) {
+        const uint32_t nd = wave_uniform(bw.chunk_n[c]);
         if (nd == kOver) {
           if (l == 0) soverflow = 1;
           break;
@@ -1568,6 +1636,7 @@ __global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __rest
           if (!set_add(sval[0], scnt[0], &ssize[0], bw.chunk_key[static_cast<size_t>(c) * kSetMax + e],
                        bw.chunk_cnt[static_cast<size_t>(c) * kSetMax + e])) {
             if (l == 0) soverflow = 1;
+            full = true;
             break;
           }
         }
@@ -1575,14 +1644,14 @@ __global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __rest
       }
     }
     __syncthreads();
-    if (soverflow) {
+    if (wave_uniform(soverflow)) {
       if (t == 0) {
         bw.run_n[bi] = kOver;
         const uint32_t u = atomicAdd(&unsorted[0], 1u);
         if (u < kMaxUnsorted) unsorted[1 + u] = g;
       }
     } else {
-      const uint32_t nd = ssize[0];
+      const uint32_t nd = wave_uniform(ssize[0]);
       rank_runs<K>(nd, sval, scnt, run0);
       if (t < nd) bw.run_key[static_cast<size_t>(bi) * kSetMax + t] = sval[1][t];
       if (t <= nd) bw.run0[static_cast<size_t>(bi) * (kSetMax + 1) + t] = run0[t];
@@ -1625,7 +1694,7 @@ __global__ __launch_bounds__(256) void k_find_long(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ long_list) {
   const uint32_t B = *nb;
   for (uint32_t g = blockIdx.x * 256u + threadIdx.x; g < B; g += gridDim.x * 256u)
-    if (offsets[g + 1] - offsets[g] > kLongT) note_long(long_count, long_list, g);
+    if (offsets[g + 1] - offsets[g] > kLongT) note_long(long_count, long_list, g, offsets[g + 1] - offsets[g]);
 }
 
 template <typename K, int THREADS, int ITEMS, int MAXD, int OP>
@@ -1819,29 +1888,29 @@ hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets
 }
 
 template <typename K>
-hipError_t long_sort_typed(const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
-                           uint32_t* work, K* keys, uint32_t* unsorted, uint32_t* big, uint64_t n, hipStream_t s) {
+hipError_t long_sort_typed(const uint32_t* offsets, uint32_t* ctr, uint32_t* list, K* keys, uint32_t* unsorted,
+                           uint32_t* big, uint64_t n, hipStream_t s) {
   const BigWork<K> bw = big_work<K>(big, n);
   hipError_t e = launch_fill_u32(bw.ctr, 2, 0u, s);
   if (e != hipSuccess) return e;
-  k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, long_list, long_count, work, keys, unsorted, bw);
+  k_long_small<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_big_scan<K><<<2 * kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
+  k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted, bw);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_big_scan<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_big_fix<K><<<kLongGrid / 2, kLongThreads, 0, s>>>(offsets, bw, unsorted);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_big_write<K><<<2 * kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
+  k_big_write<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
   return hipGetLastError();
 }
 
-hipError_t launch_long_sort(int kt, const uint32_t* offsets, const uint32_t* long_list, const uint32_t* long_count,
-                            uint32_t* work, void* keys, uint32_t* unsorted, uint32_t* big, uint64_t n,
-                            hipStream_t s) {
+hipError_t launch_long_sort(int kt, const uint32_t* offsets, uint32_t* long_ctr, uint32_t* long_list, void* keys,
+                            uint32_t* unsorted, uint32_t* big, uint64_t n, hipStream_t s) {
   if (kt == 0)
-    return long_sort_typed<uint32_t>(offsets, long_list, long_count, work, static_cast<uint32_t*>(keys), unsorted,
-                                     big, n, s);
-  return long_sort_typed<uint64_t>(offsets, long_list, long_count, work, static_cast<uint64_t*>(keys), unsorted, big,
-                                   n, s);
+    return long_sort_typed<uint32_t>(offsets, long_ctr, long_list, static_cast<uint32_t*>(keys), unsorted, big, n,
+                                     s);
+  return long_sort_typed<uint64_t>(offsets, long_ctr, long_list, static_cast<uint64_t*>(keys), unsorted, big, n, s);
 }
 
 }  // namespace hg
