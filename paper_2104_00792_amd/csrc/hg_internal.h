@@ -47,8 +47,8 @@ constexpr uint32_t kMaxUnsorted = 256;
 // Long buckets of at most kWaveLong keys are sorted by one wave each, longer
 // ones by a workgroup.  Their ids share one list (the short ones from the
 // front, the others from the back) of long_list_cap(n) entries, after
-// kLongCtr counter words: [0] short ones, [1] their work counter, [2] long
-// ones, [3] their work counter, [4] the list's length.
+// kLongCtr counter words: [0] short ones, [2] long ones, [3] the work
+// counter of the long ones, [4] the list's length ([1], [5..7] unused).
 constexpr uint32_t kWaveLong = 4096;
 constexpr uint32_t kLongCtr = 8;
 inline uint64_t long_list_cap(uint64_t n) { return 2 * (n / (kLongT + 1) + 1); }

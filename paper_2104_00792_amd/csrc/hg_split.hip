@@ -1062,6 +1062,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   __shared__ uint32_t soff[(1u << kMaxLog2W) + 1];
   __shared__ K skeys[KCAP];
   __shared__ PartDesc sd[kMaxP];
+  __shared__ uint32_t nwl;
   const uint32_t t = threadIdx.x;
   // A workgroup takes at most CH of a sub-bin's queries.  First launch:
   // workgroup b takes chunk 0 of sub-bin b and queues chunks 1.. of a sub-bin
@@ -1135,6 +1136,57 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       }
     }
     __syncthreads();
+    // Keys that do not fit LDS mean long buckets.  The runs of the window's
+    // sorted long buckets (at most kWinLong buckets of at most kSetMax runs)
+    // go to LDS, in the key area that is unused here: one wave per bucket
+    // finds each run's end by 64-way search.  Queries in those buckets are
+    // then counted from LDS, the others from global memory.
+    constexpr uint32_t kWinLong = 32;
+    uint32_t* lbkt = reinterpret_cast<uint32_t*>(skeys);  // window bucket of each table
+    uint32_t* lnr = lbkt + kWinLong;                      // its runs, or kOver
+    uint32_t* rcnt = lnr + kWinLong;                      // [kWinLong][kSetMax] run lengths
+    K* rkey = reinterpret_cast<K*>(rcnt + kWinLong * kSetMax);
+    static_assert((2 * kWinLong + kWinLong * kSetMax) * 4 + kWinLong * kSetMax * sizeof(K) <= KCAP * sizeof(K),
+                  "run tables fit the key area");
+    uint32_t nl = 0;
+    if (!in_lds) {
+      if (t == 0) nwl = 0;
+      __syncthreads();
+      for (uint32_t b = t; b < R; b += THREADS) {
+        if (soff[b + 1] - soff[b] > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + b, kMaxUnsorted)) {
+          const uint32_t s = atomicAdd(&nwl, 1u);
+          if (s < kWinLong) lbkt[s] = b;
+        }
+      }
+      __syncthreads();
+      nl = min(wave_uniform(nwl), kWinLong);
+      const uint32_t w = t / kWave, l = lane_id();
+      for (uint32_t s = w; s < nl; s += THREADS / kWave) {
+        const uint32_t b = wave_uniform(lbkt[s]), hi = wave_uniform(soff[b + 1]);
+        uint32_t p = wave_uniform(soff[b]), nr = 0;
+        while (p < hi && nr < kSetMax) {
+          const K v = tkeys[p];
+          // tkeys[lo2] == v; the run ends in (lo2, h2].
+          uint32_t lo2 = p, h2 = hi;
+          while (h2 - lo2 > 1) {
+            const uint32_t step = (h2 - lo2 + kWave - 1) / kWave;
+            const uint32_t pos = lo2 + (l + 1) * step;
+            const uint32_t c = popc64(ballot(pos < h2 && tkeys[pos] == v));
+            const uint32_t nlo = lo2 + c * step;
+            h2 = min(h2, nlo + step);
+            lo2 = nlo;
+          }
+          if (l == 0) {
+            rkey[s * kSetMax + nr] = v;
+            rcnt[s * kSetMax + nr] = h2 - p;
+          }
+          ++nr;
+          p = h2;
+        }
+        if (l == 0) lnr[s] = p < hi ? kOver : nr;
+      }
+      __syncthreads();
+    }
     // A thread remembers its last query and count: in a sub-bin that holds
     // a heavy key, most of a thread's queries repeat it.
     K last_q = K(0);
@@ -1149,8 +1201,24 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
             const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
             const uint32_t lo = soff[lb], hi = soff[lb + 1];
             const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-            last_c = in_lds ? count_equal(skeys, lo - ka, hi - ka, qv[u], srt)
-                            : count_equal(tkeys, lo, hi, qv[u], srt);
+            if (in_lds) {
+              last_c = count_equal(skeys, lo - ka, hi - ka, qv[u], srt);
+            } else {
+              uint32_t c = kOver;
+              if (srt) {
+                for (uint32_t s = 0; s < nl; ++s) {
+                  if (lbkt[s] != lb) continue;
+                  const uint32_t nr = lnr[s];
+                  if (nr != kOver) {
+                    c = 0;
+                    for (uint32_t r = 0; r < nr; ++r)
+                      if (rkey[s * kSetMax + r] == qv[u]) c = rcnt[s * kSetMax + r];
+                  }
+                  break;
+                }
+              }
+              last_c = c != kOver ? c : count_equal(tkeys, lo, hi, qv[u], srt);
+            }
             last_q = qv[u];
             have = true;
           }
@@ -1458,16 +1526,11 @@ __global__ __launch_bounds__(kLongThreads) void k_long_small(const uint32_t* __r
   __shared__ uint32_t ssize[W];
   const uint32_t w = threadIdx.x / kWave, l = lane_id();
   const uint32_t total = ctr[0];
-  for (;;) {
-    // A plain load first: once the list is used up (or empty), the waves
-    // leave without queueing atomics on one address.
-    if (wave_uniform(ld_l2(&ctr[1])) >= total) break;
-    // Every lane takes part in the claim (lane 0 adds one, the others zero)
-    // and lane 0's old value is the wave's bucket.  No branch on the lane
-    // here: with `if (l == 0)` at the top of the loop, the compiler may send
-    // the other lanes back to the broadcast without lane 0 (see wave_uniform).
-    const uint32_t idx = readlane(atomicAdd(&ctr[1], l == 0 ? 1u : 0u), 0);
-    if (idx >= total) break;  // uniform over the wave
+  // Wave i takes list entries i, i + (waves in the grid), ...: no claims
+  // through a shared counter (the buckets are at most kWaveLong keys, so a
+  // fixed deal stays balanced).  The loop is uniform over the wave.
+  const uint32_t waves = gridDim.x * W;
+  for (uint32_t idx = blockIdx.x * W + wave_uniform(w); idx < total; idx += waves) {
     const uint32_t g = wave_uniform(list[idx]);
     const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
     if (l == 0) ssize[w] = 0;
@@ -1507,7 +1570,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   const uint32_t t = threadIdx.x;
   const uint32_t total = ctr[2], cap = ctr[4];
   for (;;) {
-    if (t == 0) sidx = ld_l2(&ctr[3]) < total ? atomicAdd(&ctr[3], 1u) : total;
+    if (t == 0) sidx = atomicAdd(&ctr[3], 1u);
     __syncthreads();
     const uint32_t idx = wave_uniform(sidx);
     if (idx >= total) break;  // uniform: every thread read the same sidx
