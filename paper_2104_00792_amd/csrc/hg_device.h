@@ -165,6 +165,20 @@ __device__ __forceinline__ bool long_bucket_sorted(const uint32_t* unsorted, uin
   return true;
 }
 
+// Occurrences of q among the keys a[lo, hi) of a short bucket held in LDS.
+// The first four are read whatever the bucket's length (a[] has four spare
+// entries past its last key) and masked by it, so the common bucket of a few
+// keys costs two paired LDS reads and no loop; the rest follow in a loop.
+template <typename K>
+__device__ __forceinline__ uint32_t count_short(const K* a, uint32_t lo, uint32_t hi, K q) {
+  const uint32_t n = hi - lo;
+  const K x0 = a[lo], x1 = a[lo + 1], x2 = a[lo + 2], x3 = a[lo + 3];
+  uint32_t c = (x0 == q && n > 0 ? 1u : 0u) + (x1 == q && n > 1 ? 1u : 0u) + (x2 == q && n > 2 ? 1u : 0u) +
+               (x3 == q && n > 3 ? 1u : 0u);
+  for (uint32_t x = lo + 4; x < hi; ++x) c += a[x] == q ? 1u : 0u;
+  return c;
+}
+
 // Occurrences of q among a[lo, hi): a linear scan, or two binary searches
 // when the range is sorted.
 template <typename K, typename Ptr>

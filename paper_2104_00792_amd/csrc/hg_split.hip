@@ -17,6 +17,8 @@
 // Queries follow the same two splits, recording where each query went, are
 // counted against LDS-resident windows of the table, and return to their
 // input order by two gathers through those permutations.
+#include <type_traits>
+
 #include "hg_internal.h"
 #include "hg_tile.h"
 
@@ -712,6 +714,42 @@ __device__ __forceinline__ void note_long(uint32_t* ctr, uint32_t* list, uint32_
     list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
 }
 
+// The keys of one sub-bin, each with its position p < m packed as 16-bit
+// halves of pos (key j in half j & 1 of word j >> 1), staged in LDS in
+// position order and written to out[0 .. m) in whole lines, in chunks of
+// what the LDS block holds.  Every thread of the workgroup calls it; the LDS
+// block is free on entry (after a barrier).
+template <typename K, int THREADS, int REG>
+__device__ __forceinline__ void stage_out(uint32_t* lds, const uint32_t* pos, const K* v, uint32_t m,
+                                          K* __restrict__ out) {
+  constexpr uint32_t kStageKeys = kBuildWords * 4 / sizeof(K);
+  const uint32_t t = threadIdx.x;
+  K* stage = reinterpret_cast<K*>(lds);
+  if (m <= kStageKeys) {
+    // One chunk (the usual case): no range test per key.
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+      if (e < m) stage[(pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu] = v[j];
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < m; i += THREADS) out[i] = stage[i];
+    return;
+  }
+  for (uint32_t h0 = 0; h0 < m; h0 += kStageKeys) {
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+      const uint32_t p = (pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu;
+      if (e < m && p >= h0 && p < h0 + kStageKeys) stage[p - h0] = v[j];
+    }
+    __syncthreads();
+    const uint32_t len = min(kStageKeys, m - h0);
+    for (uint32_t i = t; i < len; i += THREADS) out[h0 + i] = stage[i];
+    __syncthreads();
+  }
+}
+
 // MINW: waves per SIMD to fit (8: two workgroups of 1024 threads per CU).
 template <typename K, int THREADS, int REG, int MINW>
 __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict__ in,
@@ -724,7 +762,6 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
                                                              uint32_t* __restrict__ heavy_count,
                                                              uint32_t* __restrict__ heavy_chunks,
                                                              uint32_t* __restrict__ heavy_bins) {
-  constexpr uint32_t kStageKeys = kBuildWords * 4 / sizeof(K);
   __shared__ uint32_t lds[kBuildWords];
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t wsum[THREADS / kWave];
@@ -735,6 +772,85 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   {
     const PartDesc* dsrc = plan->desc_by_seg ? desc + sb.seg : desc;
     for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
+  }
+
+  if (R <= kWideR && m <= 0xFFFFu) {
+    // The common sub-bin (at most 2^13 buckets): one 32-bit counter per
+    // bucket, so no key pays for packing.  Thread t scans counters 16t ..
+    // 16t + 15 in registers, which also shows it the long buckets; the
+    // offsets then leave in one coalesced pass.
+    static_assert(kWideR == 16u * THREADS, "sixteen counters per thread");
+    uint4* lds4 = reinterpret_cast<uint4*>(lds);
+    for (uint32_t i = t; i < kWideR / 4; i += THREADS) lds4[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    const bool regs = m <= static_cast<uint32_t>(THREADS * REG);
+    K v[REG];
+    uint32_t pos[(REG + 1) / 2];  // two 16-bit values per word: bucket, then position
+    if (regs && m > 0) {
+      const uint32_t last = m - 1;
+#pragma unroll
+      for (int j = 0; j < REG; ++j) v[j] = in[sb.kA + min(static_cast<uint32_t>(j) * THREADS + t, last)];
+#pragma unroll
+      for (int j = 0; j < REG; ++j) {
+        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
+        if (e < m) atomicAdd(&lds[lb], 1u);
+        if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
+      }
+    } else if (!regs) {
+      for (uint32_t e = t; e < m; e += THREADS) atomicAdd(&lds[bucket_of(in[sb.kA + e], log2P, sd) - sb.gA], 1u);
+    }
+    __syncthreads();
+    {
+      uint32_t c[16];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const uint4 q = lds4[4 * t + x];
+        c[4 * x] = q.x;
+        c[4 * x + 1] = q.y;
+        c[4 * x + 2] = q.z;
+        c[4 * x + 3] = q.w;
+      }
+      uint32_t sum = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sum += c[k];
+      uint32_t total;
+      uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        uint4 q;
+        q.x = ex;
+        q.y = q.x + c[4 * x];
+        q.z = q.y + c[4 * x + 1];
+        q.w = q.z + c[4 * x + 2];
+        ex = q.w + c[4 * x + 3];
+        lds4[4 * t + x] = q;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + 16u * t + k, c[k]);
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = sb.kA + lds[i];
+    __syncthreads();
+    if (!regs) {
+      for (uint32_t e = t; e < m; e += THREADS) {
+        const K key = in[sb.kA + e];
+        out[sb.kA + atomicAdd(&lds[bucket_of(key, log2P, sd) - sb.gA], 1u)] = key;
+      }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < REG; ++j) {
+      const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+      const uint32_t lb = (pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu;
+      uint32_t p = 0;
+      if (e < m) p = atomicAdd(&lds[lb], 1u);
+      pos[j >> 1] = (pos[j >> 1] & ~(0xFFFFu << ((j & 1) << 4))) | (p << ((j & 1) << 4));
+    }
+    __syncthreads();  // every position is known: the counters are dead
+    stage_out<K, THREADS, REG>(lds, pos, v, m, out + sb.kA);
+    return;
   }
 
   if (R <= kSMax && m <= 0xFFFFu) {
@@ -793,19 +909,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       pos[j >> 1] = (pos[j >> 1] & ~(0xFFFFu << ((j & 1) << 4))) | (p << ((j & 1) << 4));
     }
     __syncthreads();  // every position is known: the counters are dead
-    K* stage = reinterpret_cast<K*>(lds);
-    for (uint32_t h0 = 0; h0 < m; h0 += kStageKeys) {
-#pragma unroll
-      for (int j = 0; j < REG; ++j) {
-        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
-        const uint32_t p = (pos[j >> 1] >> ((j & 1) << 4)) & 0xFFFFu;
-        if (e < m && p >= h0 && p < h0 + kStageKeys) stage[p - h0] = v[j];
-      }
-      __syncthreads();
-      const uint32_t len = min(kStageKeys, m - h0);
-      for (uint32_t i = t; i < len; i += THREADS) out[sb.kA + h0 + i] = stage[i];
-      __syncthreads();
-    }
+    stage_out<K, THREADS, REG>(lds, pos, v, m, out + sb.kA);
     return;
   }
 
@@ -1060,7 +1164,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
                                                              uint32_t* __restrict__ c2) {
   constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);
   __shared__ uint32_t soff[(1u << kMaxLog2W) + 1];
-  __shared__ K skeys[KCAP];
+  __shared__ K skeys[KCAP + 4];  // 4 spare entries: count_short reads 4 keys of any bucket
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t nwl;
   const uint32_t t = threadIdx.x;
@@ -1187,49 +1291,60 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       }
       __syncthreads();
     }
-    // A thread remembers its last query and count: in a sub-bin that holds
-    // a heavy key, most of a thread's queries repeat it.
-    K last_q = K(0);
-    uint32_t last_c = 0;
-    bool have = false;
-    for (uint32_t c0 = 0;;) {
-#pragma unroll
-      for (int u = 0; u < kUQ; ++u) {
-        const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
-        if (e < m) {
-          if (!have || qv[u] != last_q) {
-            const uint32_t lb = bucket_of(qv[u], log2P, sd) - sb.gA;
-            const uint32_t lo = soff[lb], hi = soff[lb + 1];
-            const bool srt = hi - lo > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-            if (in_lds) {
-              last_c = count_equal(skeys, lo - ka, hi - ka, qv[u], srt);
-            } else {
-              uint32_t c = kOver;
-              if (srt) {
-                for (uint32_t s = 0; s < nl; ++s) {
-                  if (lbkt[s] != lb) continue;
-                  const uint32_t nr = lnr[s];
-                  if (nr != kOver) {
-                    c = 0;
-                    for (uint32_t r = 0; r < nr; ++r)
-                      if (rkey[s * kSetMax + r] == qv[u]) c = rcnt[s * kSetMax + r];
-                  }
-                  break;
-                }
-              }
-              last_c = c != kOver ? c : count_equal(tkeys, lo, hi, qv[u], srt);
-            }
-            last_q = qv[u];
-            have = true;
-          }
-          c2[qa + e] = last_c;
+    // Count of query v.  A short bucket (at most kLongT keys, unsorted) in
+    // LDS is read by count_short; a long one is rare and takes the slow
+    // branch (binary search when sorted, the run table when the window's keys
+    // are not in LDS).  The loop below is compiled once per case of in_lds,
+    // so the common case carries none of the other's code.
+    auto count_one = [&](K v, auto lds_case) -> uint32_t {
+      constexpr bool IN_LDS = decltype(lds_case)::value;
+      const uint32_t lb = bucket_of(v, log2P, sd) - sb.gA;
+      const uint32_t lo = soff[lb], hi = soff[lb + 1];
+      if (hi - lo <= kLongT) return IN_LDS ? count_short(skeys, lo - ka, hi - ka, v) : count_equal(tkeys, lo, hi, v, false);
+      const bool srt = long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
+      if (IN_LDS) return count_equal(skeys, lo - ka, hi - ka, v, srt);
+      if (srt) {
+        for (uint32_t s = 0; s < nl; ++s) {
+          if (lbkt[s] != lb) continue;
+          const uint32_t nr = lnr[s];
+          if (nr == kOver) break;
+          uint32_t c = 0;
+          for (uint32_t r = 0; r < nr; ++r)
+            if (rkey[s * kSetMax + r] == v) c = rcnt[s * kSetMax + r];
+          return c;
         }
       }
-      c0 += THREADS * kUQ;
-      if (c0 >= m) break;
+      return count_equal(tkeys, lo, hi, v, srt);
+    };
+    // A thread remembers its last query and count: in a sub-bin that holds
+    // a heavy key, most of a thread's queries repeat it.
+    auto run = [&](auto lds_case) {
+      K last_q = K(0);
+      uint32_t last_c = 0;
+      bool have = false;
+      for (uint32_t c0 = 0;;) {
 #pragma unroll
-      for (int u = 0; u < kUQ; ++u) qv[u] = q2[qa + min(c0 + static_cast<uint32_t>(u) * THREADS + t, m - 1)];
-    }
+        for (int u = 0; u < kUQ; ++u) {
+          const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
+          if (e < m) {
+            if (!have || qv[u] != last_q) {
+              last_c = count_one(qv[u], lds_case);
+              last_q = qv[u];
+              have = true;
+            }
+            c2[qa + e] = last_c;
+          }
+        }
+        c0 += THREADS * kUQ;
+        if (c0 >= m) break;
+#pragma unroll
+        for (int u = 0; u < kUQ; ++u) qv[u] = q2[qa + min(c0 + static_cast<uint32_t>(u) * THREADS + t, m - 1)];
+      }
+    };
+    if (in_lds)
+      run(std::true_type());
+    else
+      run(std::false_type());
     return;
   }
 

@@ -223,6 +223,14 @@ LONG_CASES = {
     # many distinct keys in buckets longer than 4096: left unsorted, scanned
     "unsorted_V3": lambda: (make_keys("uniform", 20000, np.uint64, 9), 3),
     "mixed_70x100_V2": lambda: (np.repeat(np.arange(70, dtype=np.uint64) * 977, 100), 2),
+    # 4096 buckets of about 256 distinct keys: every one overflows the
+    # wave's set and moves to the back of the shared long-bucket list, which
+    # then holds as many entries as the front
+    "many_bitonic_V4096": lambda: (make_keys("uniform", 1 << 20, np.uint64, 10), 4096),
+    # 2^14 buckets of about 120 keys with about 3 distinct values each, dealt
+    # to the waves of the wave-per-bucket pass (two buckets per wave)
+    "many_runs_V16384": lambda: ((np.arange(3 * 16384, dtype=np.uint64) * 2654435761)[
+        inputs.uniform_u32(2 * 1000000, 47) % (3 * 16384)], 16384),
     # buckets longer than 2^16 keys, shared by many workgroups in chunks:
     # 12 values in shuffled order over 4 buckets (a few runs per bucket), one
     # value 200000 times, 300 values over 2 buckets (too many to rewrite), and
