@@ -79,8 +79,12 @@ __host__ __device__ __forceinline__ uint32_t quot_by_recip(uint32_t h, uint32_t 
 
 __host__ __device__ __forceinline__ uint32_t mod_by_recip(uint32_t h, uint32_t V, uint32_t m32, uint64_t) {
   const uint32_t q = mulhi32(h, m32);
-  uint32_t r = h - q * V;
-  return r >= V ? r - V : r;
+  const uint32_t r = h - q * V;
+  // r < 2V and r <= h < 2^32: when r < V, r - V wraps to r + 2^32 - V > r,
+  // so the smaller of the two is the remainder either way (a subtract and a
+  // min instead of a compare, a select and a subtract).
+  const uint32_t s = r - V;
+  return s < r ? s : r;
 }
 
 __host__ __device__ __forceinline__ uint32_t mod_by_recip(uint64_t h, uint32_t V, uint32_t, uint64_t m64) {

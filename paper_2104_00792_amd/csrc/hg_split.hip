@@ -213,9 +213,15 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   }
 
   if (kCount) {
+    if (vec) {
+      // A whole tile (nearly every tile): no item is masked.
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-      if ((mask >> i) & 1u) atomicAdd(&hist[d[i]], 1u);
+      for (int i = 0; i < ITEMS; ++i) atomicAdd(&hist[d[i]], 1u);
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i)
+        if ((mask >> i) & 1u) atomicAdd(&hist[d[i]], 1u);
+    }
     __syncthreads();
     for (uint32_t dd = t; dd < D; dd += THREADS) counts[cb + dd * T + tl] = hist[dd];
     return;
