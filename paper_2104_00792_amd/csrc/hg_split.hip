@@ -33,6 +33,18 @@ __device__ __forceinline__ uint32_t bucket_of(K key, uint32_t log2P, const PartD
 
 // Index of the last segment whose prefix value is <= x (arr[0] == 0, arr is
 // non-decreasing over 0..nseg).
+// p[i] for a wave-uniform i, where p points into an array that earlier
+// launches wrote and this one only reads (the plan's arrays and scanned
+// counts).  The pointer is taken as a constant-address-space pointer, so
+// the load is a scalar one: the plan's arrays are reached through pointers
+// stored in the plan, and read as generic pointers they become per-wave
+// vector (flat) loads, two dependent round trips before any work starts.
+__device__ __forceinline__ uint32_t ld_uniform(const uint32_t* p, uint32_t i) {
+  typedef __attribute__((address_space(4))) const uint32_t ConstU32;
+  const ConstU32* q = reinterpret_cast<const ConstU32*>(reinterpret_cast<uintptr_t>(p));
+  return q[wave_uniform(i)];
+}
+
 __device__ __forceinline__ uint32_t find_segment(const uint32_t* arr, uint32_t nseg, uint32_t x) {
   uint32_t lo = 0, hi = nseg;
   while (hi - lo > 1) {
@@ -122,14 +134,14 @@ __device__ __forceinline__ bool tile_loc(const SegPlan* plan, uint32_t nd, uint3
     const uint32_t G = plan->total_tiles;
     if (blockIdx.x >= G) return false;
     const uint32_t b = xcd_tile(blockIdx.x, G);
-    L.seg = plan->tile_seg[b];
-    L.tl = b - plan->tile_first[L.seg];
-    L.D = plan->D[L.seg];
-    L.T = plan->T[L.seg];
-    L.k0 = plan->key0[L.seg];
-    L.k1 = plan->key0[L.seg + 1];
-    L.cb = plan->cbase[L.seg];
-    L.gs = plan->g0[L.seg];
+    L.seg = ld_uniform(plan->tile_seg, b);
+    L.tl = b - ld_uniform(plan->tile_first, L.seg);
+    L.D = ld_uniform(plan->D, L.seg);
+    L.T = ld_uniform(plan->T, L.seg);
+    L.k0 = ld_uniform(plan->key0, L.seg);
+    L.k1 = ld_uniform(plan->key0, L.seg + 1);
+    L.cb = ld_uniform(plan->cbase, L.seg);
+    L.gs = ld_uniform(plan->g0, L.seg);
   } else {
     L.tl = xcd_tile(blockIdx.x, gridDim.x);
   }
@@ -593,15 +605,22 @@ struct SubBin {
   uint32_t gA, gB, kA, kB, seg;
 };
 
+// kScalar: read the plan through scalar loads (ld_uniform).  Measured at
+// 2^28 keys: the probe gains (0.85 -> 0.81 ms), the LDS build loses (0.55
+// -> 0.65 ms; its waits on LDS operations also wait on scalar loads, and it
+// is bound by instruction issue), so the build keeps vector loads.
+template <bool kScalar>
 __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* scan2, uint32_t b) {
-  const uint32_t seg = plan->sb_seg[b];
-  const uint32_t d = b - plan->sb_first[seg];
-  const uint32_t D = plan->D[seg], T = plan->T[seg];
+  auto at = [](const uint32_t* p, uint32_t i) { return kScalar ? ld_uniform(p, i) : p[i]; };
+  const uint32_t seg = at(plan->sb_seg, b);
+  const uint32_t d = b - at(plan->sb_first, seg);
+  const uint32_t D = at(plan->D, seg), T = at(plan->T, seg);
   SubBin s;
-  s.gA = plan->g0[seg] + (d << plan->log2S);
-  s.gB = (d + 1 == D) ? plan->g0[seg + 1] : s.gA + (1u << plan->log2S);
-  s.kA = T != 0 ? scan2[plan->cbase[seg] + d * T] : plan->key0[seg];
-  s.kB = (d + 1 < D) ? (T != 0 ? scan2[plan->cbase[seg] + (d + 1) * T] : plan->key0[seg]) : plan->key0[seg + 1];
+  s.gA = at(plan->g0, seg) + (d << plan->log2S);
+  s.gB = (d + 1 == D) ? at(plan->g0, seg + 1) : s.gA + (1u << plan->log2S);
+  s.kA = T != 0 ? at(scan2, at(plan->cbase, seg) + d * T) : at(plan->key0, seg);
+  s.kB = (d + 1 < D) ? (T != 0 ? at(scan2, at(plan->cbase, seg) + (d + 1) * T) : at(plan->key0, seg))
+                     : at(plan->key0, seg + 1);
   s.seg = seg;
   return s;
 }
@@ -773,7 +792,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   __shared__ uint32_t wsum[THREADS / kWave];
   const uint32_t t = threadIdx.x;
   if (blockIdx.x >= plan->total_subbins) return;  // whole workgroup
-  const SubBin sb = sub_bin(plan, scan2, blockIdx.x);
+  const SubBin sb = sub_bin<false>(plan, scan2, blockIdx.x);
   const uint32_t R = sb.gB - sb.gA, m = sb.kB - sb.kA;
   {
     const PartDesc* dsrc = plan->desc_by_seg ? desc + sb.seg : desc;
@@ -1017,7 +1036,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_count(const K* __restrict__ i
   const uint32_t items = heavy_count[0];
   for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
     const uint32_t b = heavy_chunks[2 * w], k = heavy_chunks[2 * w + 1];
-    const SubBin sb = sub_bin(plan, scan2, b);
+    const SubBin sb = sub_bin<false>(plan, scan2, b);
     const uint32_t R = sb.gB - sb.gA;
     const uint32_t c0 = sb.kA + k * kHeavyChunk, c1 = min(sb.kB, c0 + kHeavyChunk);
     __syncthreads();  // the previous chunk is done with hist and sd
@@ -1052,7 +1071,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_scan(const SegPlan* __restric
   const uint32_t t = threadIdx.x;
   const uint32_t nb = heavy_count[1];
   for (uint32_t j = blockIdx.x; j < nb; j += gridDim.x) {
-    const SubBin sb = sub_bin(plan, scan2, heavy_bins[j]);
+    const SubBin sb = sub_bin<false>(plan, scan2, heavy_bins[j]);
     const uint32_t R = sb.gB - sb.gA;
     __syncthreads();
     for (uint32_t i = t; i < R; i += THREADS) c[i] = offsets[sb.gA + i];
@@ -1076,7 +1095,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_scatter(const K* __restrict__
   const uint32_t items = heavy_count[0];
   for (uint32_t w = blockIdx.x; w < items; w += gridDim.x) {
     const uint32_t b = heavy_chunks[2 * w], k = heavy_chunks[2 * w + 1];
-    const SubBin sb = sub_bin(plan, scan2, b);
+    const SubBin sb = sub_bin<false>(plan, scan2, b);
     const uint32_t R = sb.gB - sb.gA;
     const uint32_t c0 = sb.kA + k * kHeavyChunk, c1 = min(sb.kB, c0 + kHeavyChunk);
     __syncthreads();
@@ -1122,7 +1141,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_fix(const SegPlan* __restrict
   const uint32_t t = threadIdx.x;
   const uint32_t nb = heavy_count[1];
   for (uint32_t j = blockIdx.x; j < nb; j += gridDim.x) {
-    const SubBin sb = sub_bin(plan, scan2, heavy_bins[j]);
+    const SubBin sb = sub_bin<false>(plan, scan2, heavy_bins[j]);
     const uint32_t R = sb.gB - sb.gA;
     __syncthreads();
     for (uint32_t i = t; i < R; i += THREADS) c[i] = offsets[sb.gA + i];  // bucket ends
@@ -1189,7 +1208,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
     b = blockIdx.x;
     chunk = 0;
   }
-  const SubBin sb = sub_bin(qplan, qscan2, b);
+  const SubBin sb = sub_bin<true>(qplan, qscan2, b);
   if (!from_queue && t == 0 && sb.kB - sb.kA > CH) {
     const uint32_t extra = (sb.kB - sb.kA - 1) / CH;  // chunks after the first
     const uint32_t at = atomicAdd(&queue[0], extra);
