@@ -31,8 +31,15 @@ __device__ __forceinline__ uint32_t bucket_of(K key, uint32_t log2P, const PartD
   return global_bucket(h, sd[part_of(h, log2P)]);
 }
 
-// Index of the last segment whose prefix value is <= x (arr[0] == 0, arr is
-// non-decreasing over 0..nseg).
+// x must be in registers here: a load issued above cannot sink below this
+// point (the compiler otherwise moves loads down to their first use, past
+// barriers they do not depend on, and the workgroup pays two round trips
+// instead of one).
+template <typename T>
+__device__ __forceinline__ void in_regs(T& x) {
+  asm volatile("" : "+v"(x));
+}
+
 // p[i] for a wave-uniform i, where p points into an array that earlier
 // launches wrote and this one only reads (the plan's arrays and scanned
 // counts).  The pointer is taken as a constant-address-space pointer, so
@@ -45,6 +52,8 @@ __device__ __forceinline__ uint32_t ld_uniform(const uint32_t* p, uint32_t i) {
   return q[wave_uniform(i)];
 }
 
+// Index of the last segment whose prefix value is <= x (arr[0] == 0, arr is
+// non-decreasing over 0..nseg).
 __device__ __forceinline__ uint32_t find_segment(const uint32_t* arr, uint32_t nseg, uint32_t x) {
   uint32_t lo = 0, hi = nseg;
   while (hi - lo > 1) {
@@ -187,6 +196,12 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   const bool vec = head == 0 && tail == static_cast<uint32_t>(TILE) &&
                    (reinterpret_cast<uintptr_t>(in + base) & 15) == 0;
 
+  // The tile's keys are requested first: they depend on nothing below, and
+  // their round trip then overlaps the descriptor copy and the barrier.
+  K v[ITEMS];
+  uint32_t d[ITEMS];
+  const uint32_t mask = load_items<K, THREADS, ITEMS>(in, base, head, tail, vec, v);
+
   if (DIG != DIG_PART) {
     // A batched table's segment brings its own descriptor (P == 1 there).
     const PartDesc* dsrc = (plan != nullptr && plan->desc_by_seg) ? desc + seg : desc;
@@ -197,15 +212,14 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
     for (uint32_t i = t; i <= D; i += THREADS) srange[i] = bounds[i];
   }
   for (uint32_t i = t; i < D; i += THREADS) hist[i] = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) in_regs(v[i]);
   __syncthreads();
 
   // Per-item values are computed for every item, valid or not (an invalid
   // item's key is 0, its digit in range); only memory effects are masked.
   // Conditional assignments to these arrays would make the compiler carry
   // them as whole vectors through every branch.
-  K v[ITEMS];
-  uint32_t d[ITEMS];
-  const uint32_t mask = load_items<K, THREADS, ITEMS>(in, base, head, tail, vec, v);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     if (DIG == DIG_PART) {
