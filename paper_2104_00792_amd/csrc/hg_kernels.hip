@@ -114,6 +114,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_spine(uint32_t* __restrict__ bs
   }
 }
 
+// kPrefix: the chunk's prefix is the sum of block_sums[0 .. blockIdx.x),
+// added up here by the whole workgroup (the block sums are not scanned
+// first); otherwise block_sums holds the scanned prefixes.
+template <bool kPrefix>
 __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, const uint32_t* len_dev,
                                                       uint64_t len_bound, const uint32_t* __restrict__ block_sums) {
   constexpr int kPer = kScanChunk / kBlock;  // 16
@@ -129,6 +133,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
     const uint64_t e = base + i;
     buf[i + i / kPer] = e < len ? a[e] : 0u;
   }
+  uint32_t prefix = 0;
+  if (kPrefix) {
+    uint32_t part = 0;
+    for (uint32_t i = t; i < blockIdx.x; i += kBlock) part += block_sums[i];
+    block_exclusive_sum<kBlock>(part, wtot, prefix);
+  } else {
+    prefix = block_sums[blockIdx.x];
+  }
   __syncthreads();
   uint32_t x[kPer];
   uint32_t s = 0;
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
     s += x[j];
   }
   uint32_t total;
-  uint32_t run = block_sums[blockIdx.x] + block_exclusive_sum<kBlock>(s, wtot, total);
+  uint32_t run = prefix + block_exclusive_sum<kBlock>(s, wtot, total);
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const uint32_t i = t * kPer + j;
@@ -454,10 +466,19 @@ hipError_t launch_scan_exclusive(uint32_t* a, const uint32_t* len_dev, uint64_t 
   k_scan_reduce<<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // Up to kScanFusedBlocks chunks, each down-sweep workgroup adds up the
+  // sums before its chunk itself (at most that many loads, from L2): one
+  // launch and one single-workgroup kernel fewer.  Longer scans scan the
+  // block sums first.
+  constexpr uint32_t kScanFusedBlocks = 4096;
+  if (nb <= kScanFusedBlocks) {
+    k_scan_down<true><<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
+    return hipGetLastError();
+  }
   k_scan_spine<<<1, kBlock, 0, s>>>(block_sums, nb);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_scan_down<<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
+  k_scan_down<false><<<nb, kBlock, 0, s>>>(a, len_dev, len_bound, block_sums);
   return hipGetLastError();
 }
 
