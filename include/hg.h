@@ -348,6 +348,11 @@ const char* hg_last_error(void);
  * `cap` entries (name, launches, total milliseconds) and returns the number
  * of kernels seen.  hg_profile_reset clears the totals. */
 hg_status hg_profile_enable(int on);
+/* While `name` is not NULL, only launches of that name are bracketed (the
+ * others run without events); NULL brackets every launch again.  The name
+ * is copied.  A timing run can so keep the events of the one kernel it
+ * reports and nothing else on the stream. */
+hg_status hg_profile_only(const char* name);
 hg_status hg_profile_collect(void);
 int hg_profile_read(const char** names, uint64_t* launches, double* total_ms,
                     int cap);

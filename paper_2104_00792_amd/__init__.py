@@ -147,6 +147,8 @@ def lib() -> ctypes.CDLL:
     L.hg_last_error.restype = ctypes.c_char_p
     L.hg_profile_enable.argtypes = [i32]
     L.hg_profile_enable.restype = i32
+    L.hg_profile_only.argtypes = [ctypes.c_char_p]
+    L.hg_profile_only.restype = i32
     L.hg_profile_collect.argtypes = []
     L.hg_profile_collect.restype = i32
     L.hg_profile_read.argtypes = [ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(u64),
@@ -471,11 +473,16 @@ class profile:
     """Per-kernel HIP-event timing of the library's launches.
 
     ``with profile() as p: ...`` then ``p.results`` maps kernel name to
-    (launches, total milliseconds)."""
+    (launches, total milliseconds).  ``profile(only="lds_probe")`` brackets
+    the launches of that name only."""
+
+    def __init__(self, only: str | None = None):
+        self.only = only
 
     def __enter__(self):
         L = lib()
         L.hg_profile_reset()
+        _check(L.hg_profile_only(self.only.encode() if self.only else None), "hg_profile_only")
         _check(L.hg_profile_enable(1), "hg_profile_enable")
         self.results = {}
         return self
@@ -483,6 +490,7 @@ class profile:
     def __exit__(self, *exc):
         L = lib()
         L.hg_profile_enable(0)
+        L.hg_profile_only(None)
         _check(L.hg_profile_collect(), "hg_profile_collect")
         cap = 64
         names = (ctypes.c_char_p * cap)()

@@ -237,6 +237,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+std::string g_prof_only;  // empty: every launch
 std::vector<ProfRec> g_pending;
 std::vector<hipEvent_t> g_events;
 std::map<std::string, std::pair<uint64_t, double>> g_totals;
@@ -259,7 +260,7 @@ class ProfScope {
   ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
     if (t_measure) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || (!g_prof_only.empty() && g_prof_only != name_)) return;
     a_ = take_event();
     b_ = take_event();
     if (a_ && b_) (void)hipEventRecord(a_, s_);
@@ -1228,6 +1229,12 @@ const char* hg_last_error(void) { return t_err.c_str(); }
 hg_status hg_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = on != 0;
+  return HG_OK;
+}
+
+hg_status hg_profile_only(const char* name) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_only = name != nullptr ? name : "";
   return HG_OK;
 }
 
