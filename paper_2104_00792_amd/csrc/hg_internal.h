@@ -79,8 +79,10 @@ hipError_t launch_long_sort(int kt, const uint32_t* offsets, uint32_t* long_ctr,
 
 inline int l2_tile_keys(int kt) { return kL2Threads * (kt == 0 ? 8 : 4); }
 // Level-2 tiles of a segment start at its first key rounded down to this
-// many keys (16 bytes or more), so interior tiles take vector loads.
-constexpr uint32_t kTileAlign = 4;
+// many keys: interior tiles take vector loads, and every tile's keys, slots
+// (u16) and counts start on a 128-byte line, so that no wave's access
+// straddles one more line than it fills.
+constexpr uint32_t kTileAlign = 64;
 
 // Segments of the level-2 split and sub-bins of the LDS stages, computed on
 // the device (no host round trip).  Segment s holds keys key0[s] .. key0[s+1]
