@@ -472,8 +472,10 @@ hg_status alloc_split(Allocs& mem, uint64_t n, hg_key_type kt, const SplitParams
   w.tiles1 = hg::div_up(n, hg::kL1Tile);
   w.max_tiles2 = max_l2_tiles(n, tile2, sp.nd1);
   w.max_subbins = hg::div_up(bound, 1ull << sp.log2S) + sp.nd1;
-  w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(hg::kMaxD2) * w.max_tiles2,
-                                                           0xFFFFFFFFull));
+  // A segment has at most kMaxD2 sub-bins; a coarse range of 2^sh1 buckets
+  // (mode 1) at most 2^(sh1 - log2S).
+  const uint64_t maxd2 = sp.mode == 1 ? std::min<uint64_t>(hg::kMaxD2, 1ull << (sp.sh1 - sp.log2S)) : hg::kMaxD2;
+  w.max_counts2 = static_cast<uint32_t>(std::min<uint64_t>(maxd2 * w.max_tiles2, 0xFFFFFFFFull));
   const uint64_t len1 = static_cast<uint64_t>(std::max(sp.nd1, P)) * w.tiles1;
   const uint64_t scan_max = std::max<uint64_t>(std::max<uint64_t>(len1, w.max_counts2), extra_scan);
   void *c1 = nullptr, *bs = nullptr, *pl = nullptr, *c2 = nullptr, *b1 = nullptr, *b2 = nullptr;
