@@ -640,9 +640,10 @@ __device__ __forceinline__ SubBin sub_bin(const SegPlan* plan, const uint32_t* s
 }
 
 // ------------------------------------------------------------- LDS build
-// A sub-bin of R <= kSMax buckets and m <= 65535 keys is sorted in LDS with
-// 16-bit counters, two per word (bucket i in half i & 1 of word i >> 1).  The
-// same LDS then stages the sorted keys so that they leave in whole lines.
+// A sub-bin of m <= 65535 keys is sorted in LDS: with one 32-bit counter per
+// bucket when R <= kWideR (the common sub-bin), else with 16-bit counters,
+// two per word (bucket i in half i & 1 of word i >> 1), up to R <= kSMax.
+// The same LDS then stages the sorted keys so that they leave in whole lines.
 constexpr uint32_t kBuildWords = 8448;  // 33 KiB: the counters, then the staging area (four
                                         // workgroups per CU with the descriptors)
 constexpr uint32_t kSMax = 1u << 14;     // 16-bit counters for up to this many buckets
