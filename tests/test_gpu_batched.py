@@ -71,6 +71,10 @@ CASES = {
     "many_small": [int(x) for x in np.random.default_rng(3).integers(0, 300, 300)],
     "multi_subbin": [(1 << 16) + 5, 3, (1 << 15) - 1, 40000],
     "all_empty": [0, 0, 0],
+    # 8390000 buckets at 2^13 per sub-bin: the sub-bin count is capped at
+    # 1024, so the last sub-bin holds 9584 buckets and takes the build's
+    # 16-bit counters (every other sub-bin takes the 32-bit ones)
+    "capped_last_subbin": [8390000, 1000],
 }
 
 
