@@ -1,0 +1,59 @@
+"""Host-side logic of bench.py, on the CPU: the one-GPU guard, the
+algorithmic bytes per launch (the per-unit figures of the kernel table), and
+that counter figures are reported only for the kernel sources they were
+taken on."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("args, env", [(["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "2"})])
+def test_more_than_one_gpu_is_refused(args, env):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                       timeout=120, env=dict(os.environ, **env))
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_bytes_per_unit_of_each_launch():
+    n = q = B = 1 << 20
+    per = lambda k, ks=4: bench.algorithmic_bytes(k, n, q, B, ks, 16) / n  # noqa: E731
+    assert per("part_count") == 4 and per("split1_count") == 4 and per("split2_count") == 4
+    assert per("split1_scatter") == 8 and per("split2_scatter") == 8
+    assert per("lds_build") == 12                      # key in, key out, offset out (B == n)
+    assert per("qsplit1_scatter") == 10 and per("qsplit2_scatter") == 10
+    assert per("lds_probe") == 16                      # query, offset, table key, count
+    assert per("qgather1") == 10 and per("qgather2") == 10
+    assert per("lds_build", ks=8) == 20 and per("lds_probe", ks=8) == 24
+    assert bench.algorithmic_bytes("no_such_launch", n, q, B, 4, 16) == 0.0
+
+
+def test_headline_step_moves_104_bytes_per_key_and_query():
+    n = q = B = 1 << 28
+    launches = ["part_count", "split1_count", "split1_scatter", "split2_count", "split2_scatter", "lds_build",
+                "qsplit1_count", "qsplit1_scatter", "qsplit2_count", "qsplit2_scatter", "lds_probe", "qgather2",
+                "qgather1"]
+    total = sum(bench.algorithmic_bytes(k, n, q, B, 4, 16) for k in launches)
+    assert total == 104 * n
+
+
+def test_traffic_is_read_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_traffic("w", "lds_probe") is None  # no summary at all
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    f = prof / "traffic_w.txt"
+    f.write_text(f"# comment\nkernel_source_sha256_16 = {bench.kernel_source_hash()}\n"
+                 "hbm_bytes_per_launch.lds_probe = 4319000000\n")
+    assert bench.read_traffic("w", "lds_probe") == 4319000000.0
+    assert bench.read_traffic("w", "qgather1") is None  # kernel not in the summary
+    f.write_text("kernel_source_sha256_16 = 0000000000000000\nhbm_bytes_per_launch.lds_probe = 4319000000\n")
+    assert bench.read_traffic("w", "lds_probe") is None  # taken on other sources
