@@ -1191,6 +1191,13 @@ __device__ __forceinline__ void copy_to_lds(T* __restrict__ dst, const T* __rest
 }
 
 constexpr uint32_t kProbeKeyBytes = 40 * 1024;
+// Offsets and keys of a probe window share one LDS block: the offsets take
+// Wb + 1 words, rounded up to 16 bytes, and the keys the rest.  A window of
+// fewer than 2^kMaxLog2W buckets (64-bit keys, or several keys per bucket)
+// so holds more keys than kProbeKeyBytes, which is what a window whose heavy
+// bucket overflows the expected count needs.
+constexpr uint32_t kProbeOffWords = (1u << kMaxLog2W) + 4;
+constexpr uint32_t kProbeLdsWords = kProbeOffWords + kProbeKeyBytes / 4 + 8;
 
 template <typename K, int THREADS, int REG, int MINW>
 __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict__ q2,
@@ -1202,9 +1209,9 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
                                                              const uint32_t* __restrict__ unsorted, uint32_t log2W,
                                                              uint32_t* __restrict__ queue, bool from_queue,
                                                              uint32_t* __restrict__ c2) {
-  constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);
-  __shared__ uint32_t soff[(1u << kMaxLog2W) + 1];
-  __shared__ K skeys[KCAP + 4];  // 4 spare entries: count_short reads 4 keys of any bucket
+  constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);  // keys in LDS at the largest window
+  __shared__ __align__(16) uint32_t sbuf[kProbeLdsWords];
+  static_assert((kProbeLdsWords - kProbeOffWords) * 4 / sizeof(K) - 4 >= KCAP, "the largest window keeps KCAP keys");
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t nwl;
   const uint32_t t = threadIdx.x;
@@ -1236,6 +1243,13 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   const uint32_t R = sb.gB - sb.gA, m = min(CH, sb.kB - qa);
   const uint32_t Wb = 1u << log2W;
   const uint32_t nuns = unsorted[0];
+  // Keys at the block's start (a fixed address, as the counting loops read
+  // them), offsets at its end.
+  const uint32_t off_words = (Wb + 4) & ~3u;  // log2W <= kMaxLog2W: at most kProbeOffWords
+  uint32_t* const soff = sbuf + (kProbeLdsWords - off_words);
+  K* const skeys = reinterpret_cast<K*>(sbuf);
+  // 4 spare entries: count_short reads 4 keys of any bucket.
+  const uint32_t kcap = (kProbeLdsWords - off_words) * 4 / static_cast<uint32_t>(sizeof(K)) - 4;
   {
     const PartDesc* dsrc = qplan->desc_by_seg ? desc + sb.seg : desc;
     for (uint32_t i = t; i < P; i += THREADS) sd[i] = dsrc[i];
@@ -1261,7 +1275,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
     // The key loads wait for the key range; the loads above are in flight
     // meanwhile.
     const uint32_t ka = offsets[sb.gA], nk = offsets[sb.gB] - ka;
-    const bool in_lds = nk <= KCAP;
+    const bool in_lds = nk <= kcap;
     const bool load_keys = in_lds && nk > 0;
     if (load_keys) {
 #pragma unroll
@@ -1278,6 +1292,8 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
         const uint32_t i = static_cast<uint32_t>(u) * THREADS + t;
         if (i < nk) skeys[i] = xk[u];
       }
+      // Keys past the registers' share (a window smaller than 2^kMaxLog2W).
+      for (uint32_t i = kUK * THREADS + t; i < nk; i += THREADS) skeys[i] = tkeys[ka + i];
     }
     __syncthreads();
     // Keys that do not fit LDS mean long buckets.  The runs of the window's
@@ -1408,7 +1424,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       copy_to_lds<THREADS, 8>(soff, offsets + sb.gA + w0, wl + 1);
       __syncthreads();
       const uint32_t ka = soff[0], nk = soff[wl] - ka;
-      const bool in_lds = nk <= KCAP;
+      const bool in_lds = nk <= kcap;
       if (in_lds) copy_to_lds<THREADS, 8>(skeys, tkeys + ka, nk);
       __syncthreads();
       // Output addresses are rebuilt in every window from one register (the

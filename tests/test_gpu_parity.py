@@ -267,6 +267,24 @@ def test_long_buckets(gpu, case, dtype, build):
 
 
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("P", [1, 16])
+def test_probe_windows_around_the_lds_key_capacity(gpu, dtype, P):
+    """Two keys per bucket (V = n/2) and twelve heavy keys of 500 to 15000
+    copies each: a probe window sized for about 4096 (u64) or 8192 (u32)
+    keys then holds up to several times that, so windows fall on both sides
+    of what fits LDS beside their offsets (up to 8192 u64 or 14340 u32 keys
+    when the window has fewer buckets than the largest), and their counts
+    come from LDS, from global memory and from the run tables."""
+    base = make_keys("uniform", 1 << 20, dtype, 61)
+    heavy = make_keys("uniform", 12, dtype, 62)
+    copies = np.linspace(500, 15000, 12).astype(np.int64)
+    keys = np.concatenate([base, np.repeat(heavy, copies)])
+    keys = keys[inputs.uniform_u32(keys.size, 63).argsort(kind="stable")]
+    queries = np.concatenate([np.repeat(heavy, 50), base[::40], make_keys("uniform", 20000, dtype, 64)])
+    check_table(gpu, keys, P=P, num=1, den=2, queries=queries)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
 @pytest.mark.parametrize("shift", [0, 1, 3])
 def test_sorted_probe_output_alignment(gpu, dtype, shift):
     """The last gather of the sorted probe stores whole vectors when the
