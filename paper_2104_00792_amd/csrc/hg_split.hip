@@ -1296,85 +1296,140 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       for (uint32_t i = kUK * THREADS + t; i < nk; i += THREADS) skeys[i] = tkeys[ka + i];
     }
     __syncthreads();
-    // Keys that do not fit LDS mean long buckets.  The runs of the window's
-    // sorted long buckets (at most kWinLong buckets of at most kSetMax runs)
-    // go to LDS, in the key area that is unused here: one wave per bucket
-    // finds each run's end by 64-way search.  Queries in those buckets are
-    // then counted from LDS, the others from global memory.
+    // Keys that do not fit LDS mean long buckets (more than kLongT keys).  If
+    // there are at most kWinLong of them they are listed in bucket order with
+    // their key ranges, and one wave per sorted one finds each run's end by
+    // 64-way search and keeps the runs (at most kSetMax) in LDS.  When the
+    // short buckets' keys then fit beside those tables they are staged too,
+    // compacted: the offsets are rewritten to compacted positions, with
+    // kLongMark on a long bucket's own offset.  Only queries into a long
+    // bucket without runs then read global memory.
     constexpr uint32_t kWinLong = 32;
-    uint32_t* lbkt = reinterpret_cast<uint32_t*>(skeys);  // window bucket of each table
+    uint32_t* lbkt = reinterpret_cast<uint32_t*>(skeys);  // window bucket of each long bucket, ascending
     uint32_t* lnr = lbkt + kWinLong;                      // its runs, or kOver
-    uint32_t* rcnt = lnr + kWinLong;                      // [kWinLong][kSetMax] run lengths
+    uint32_t* llo = lnr + kWinLong;                       // its key range in the table
+    uint32_t* lhi = llo + kWinLong;
+    uint32_t* rcnt = lhi + kWinLong;  // [kWinLong][kSetMax] run lengths
     K* rkey = reinterpret_cast<K*>(rcnt + kWinLong * kSetMax);
-    static_assert((2 * kWinLong + kWinLong * kSetMax) * 4 + kWinLong * kSetMax * sizeof(K) <= KCAP * sizeof(K),
-                  "run tables fit the key area");
+    constexpr uint32_t kTableBytes = (4 * kWinLong + kWinLong * kSetMax) * 4 + kWinLong * kSetMax * sizeof(K);
+    static_assert(kTableBytes % sizeof(K) == 0 && kTableBytes <= KCAP * sizeof(K), "run tables fit the key area");
+    K* const sshort = skeys + kTableBytes / sizeof(K);  // staged short-bucket keys
+    constexpr uint32_t kLongMark = 0x80000000u;
     uint32_t nl = 0;
+    bool staged = false;
     if (!in_lds) {
       if (t == 0) nwl = 0;
       __syncthreads();
       for (uint32_t b = t; b < R; b += THREADS) {
-        if (soff[b + 1] - soff[b] > kLongT && long_bucket_sorted(unsorted, nuns, sb.gA + b, kMaxUnsorted)) {
+        if (soff[b + 1] - soff[b] > kLongT) {
           const uint32_t s = atomicAdd(&nwl, 1u);
           if (s < kWinLong) lbkt[s] = b;
         }
       }
       __syncthreads();
-      nl = min(wave_uniform(nwl), kWinLong);
+      const uint32_t nall = wave_uniform(nwl);
+      nl = min(nall, kWinLong);
+      // Bucket order: thread s ranks the s-th listed bucket among the others.
+      uint32_t mine = 0, rank = 0;
+      if (t < nl) {
+        mine = lbkt[t];
+        for (uint32_t j = 0; j < nl; ++j) rank += lbkt[j] < mine ? 1u : 0u;
+      }
+      __syncthreads();
+      if (t < nl) {
+        lbkt[rank] = mine;
+        llo[rank] = soff[mine];
+        lhi[rank] = soff[mine + 1];
+      }
+      __syncthreads();
       const uint32_t w = t / kWave, l = lane_id();
       for (uint32_t s = w; s < nl; s += THREADS / kWave) {
-        const uint32_t b = wave_uniform(lbkt[s]), hi = wave_uniform(soff[b + 1]);
-        uint32_t p = wave_uniform(soff[b]), nr = 0;
-        while (p < hi && nr < kSetMax) {
-          const K v = tkeys[p];
-          // tkeys[lo2] == v; the run ends in (lo2, h2].
-          uint32_t lo2 = p, h2 = hi;
-          while (h2 - lo2 > 1) {
-            const uint32_t step = (h2 - lo2 + kWave - 1) / kWave;
-            const uint32_t pos = lo2 + (l + 1) * step;
-            const uint32_t c = popc64(ballot(pos < h2 && tkeys[pos] == v));
-            const uint32_t nlo = lo2 + c * step;
-            h2 = min(h2, nlo + step);
-            lo2 = nlo;
+        const uint32_t b = wave_uniform(lbkt[s]), hi = wave_uniform(lhi[s]);
+        uint32_t p = wave_uniform(llo[s]), nr = 0;
+        if (long_bucket_sorted(unsorted, nuns, sb.gA + b, kMaxUnsorted)) {
+          while (p < hi && nr < kSetMax) {
+            const K v = tkeys[p];
+            // tkeys[lo2] == v; the run ends in (lo2, h2].
+            uint32_t lo2 = p, h2 = hi;
+            while (h2 - lo2 > 1) {
+              const uint32_t step = (h2 - lo2 + kWave - 1) / kWave;
+              const uint32_t pos = lo2 + (l + 1) * step;
+              const uint32_t c = popc64(ballot(pos < h2 && tkeys[pos] == v));
+              const uint32_t nlo = lo2 + c * step;
+              h2 = min(h2, nlo + step);
+              lo2 = nlo;
+            }
+            if (l == 0) {
+              rkey[s * kSetMax + nr] = v;
+              rcnt[s * kSetMax + nr] = h2 - p;
+            }
+            ++nr;
+            p = h2;
           }
-          if (l == 0) {
-            rkey[s * kSetMax + nr] = v;
-            rcnt[s * kSetMax + nr] = h2 - p;
-          }
-          ++nr;
-          p = h2;
         }
         if (l == 0) lnr[s] = p < hi ? kOver : nr;
       }
+      uint32_t nlong = 0;  // keys of the listed long buckets
+      for (uint32_t s = 0; s < nl; ++s) nlong += lhi[s] - llo[s];
+      const uint32_t cap_short = kcap - kTableBytes / static_cast<uint32_t>(sizeof(K));  // 4 spare kept
+      staged = wave_uniform(nall <= kWinLong && nk - nlong <= cap_short ? 1u : 0u) != 0;
+      if (staged) {
+        // Offsets in compacted positions: less the window's first key and
+        // the keys of the long buckets before the bucket.
+        for (uint32_t b = t; b <= R; b += THREADS) {
+          uint32_t before = 0, mark = 0;
+          for (uint32_t s = 0; s < nl; ++s) {
+            const uint32_t g = lbkt[s];
+            before += g < b ? lhi[s] - llo[s] : 0u;
+            mark |= g == b ? kLongMark : 0u;
+          }
+          soff[b] = (soff[b] - ka - before) | mark;
+        }
+        // The short buckets' keys: the stretches around the long buckets.
+        uint32_t from = ka, to = 0;
+        for (uint32_t s = 0; s <= nl; ++s) {
+          const uint32_t end = s < nl ? wave_uniform(llo[s]) : ka + nk;
+          for (uint32_t i = t; i < end - from; i += THREADS) sshort[to + i] = tkeys[from + i];
+          to += end - from;
+          if (s < nl) from = wave_uniform(lhi[s]);
+        }
+      }
       __syncthreads();
     }
-    // Count of query v.  A short bucket (at most kLongT keys, unsorted) in
-    // LDS is read by count_short; a long one is rare and takes the slow
-    // branch (binary search when sorted, the run table when the window's keys
-    // are not in LDS).  The loop below is compiled once per case of in_lds,
-    // so the common case carries none of the other's code.
-    auto count_one = [&](K v, auto lds_case) -> uint32_t {
-      constexpr bool IN_LDS = decltype(lds_case)::value;
+    // Count of query v.  Mode 0: the window's keys are in LDS; a short bucket
+    // (at most kLongT keys, unsorted) is read by count_short, a long one by
+    // binary search when sorted.  Mode 1: short buckets staged, long ones
+    // listed.  Mode 2: short buckets in global memory.  The loop below is
+    // compiled once per mode, so the common case carries none of the others'
+    // code.
+    auto count_one = [&](K v, auto mode) -> uint32_t {
+      constexpr int MODE = decltype(mode)::value;
       const uint32_t lb = bucket_of(v, log2P, sd) - sb.gA;
       const uint32_t lo = soff[lb], hi = soff[lb + 1];
-      if (hi - lo <= kLongT) return IN_LDS ? count_short(skeys, lo - ka, hi - ka, v) : count_equal(tkeys, lo, hi, v, false);
-      const bool srt = long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted);
-      if (IN_LDS) return count_equal(skeys, lo - ka, hi - ka, v, srt);
-      if (srt) {
-        for (uint32_t s = 0; s < nl; ++s) {
-          if (lbkt[s] != lb) continue;
-          const uint32_t nr = lnr[s];
-          if (nr == kOver) break;
+      if (MODE == 0) {
+        if (hi - lo <= kLongT) return count_short(skeys, lo - ka, hi - ka, v);
+        return count_equal(skeys, lo - ka, hi - ka, v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
+      }
+      if (MODE == 1 && !(lo & kLongMark)) return count_short(sshort, lo, hi & ~kLongMark, v);
+      if (MODE == 2 && hi - lo <= kLongT) return count_equal(tkeys, lo, hi, v, false);
+      // A long bucket: its runs, else a scan of its keys in global memory.
+      for (uint32_t s = 0; s < nl; ++s) {
+        if (lbkt[s] != lb) continue;
+        const uint32_t nr = lnr[s];
+        if (nr != kOver) {
           uint32_t c = 0;
           for (uint32_t r = 0; r < nr; ++r)
             if (rkey[s * kSetMax + r] == v) c = rcnt[s * kSetMax + r];
           return c;
         }
+        return count_equal(tkeys, llo[s], lhi[s], v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
       }
-      return count_equal(tkeys, lo, hi, v, srt);
+      if (MODE == 1) return 0;  // not reached: every long bucket is listed
+      return count_equal(tkeys, lo, hi, v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
     };
     // A thread remembers its last query and count: in a sub-bin that holds
     // a heavy key, most of a thread's queries repeat it.
-    auto run = [&](auto lds_case) {
+    auto run = [&](auto mode) {
       K last_q = K(0);
       uint32_t last_c = 0;
       bool have = false;
@@ -1384,7 +1439,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
           const uint32_t e = c0 + static_cast<uint32_t>(u) * THREADS + t;
           if (e < m) {
             if (!have || qv[u] != last_q) {
-              last_c = count_one(qv[u], lds_case);
+              last_c = count_one(qv[u], mode);
               last_q = qv[u];
               have = true;
             }
@@ -1398,9 +1453,11 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       }
     };
     if (in_lds)
-      run(std::true_type());
+      run(std::integral_constant<int, 0>());
+    else if (staged)
+      run(std::integral_constant<int, 1>());
     else
-      run(std::false_type());
+      run(std::integral_constant<int, 2>());
     return;
   }
 

@@ -284,6 +284,43 @@ def test_probe_windows_around_the_lds_key_capacity(gpu, dtype, P):
     check_table(gpu, keys, P=P, num=1, den=2, queries=queries)
 
 
+def keys_in_buckets(dtype, V, buckets, per_bucket, seed):
+    """per_bucket distinct keys for each of the given buckets of a plain
+    table with V buckets (chosen from seeded candidates by the oracle's
+    hash), as one array per bucket."""
+    gen = inputs.uniform_u32 if dtype == np.uint32 else inputs.uniform_u64
+    cand = np.unique(gen(max(2 * per_bucket, 20) * V, seed))
+    _, b = oracle.hash_bucket(cand, V)
+    out = [cand[b == g][:per_bucket] for g in buckets]
+    assert all(x.size == per_bucket for x in out)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("case", ["over_32_long", "staged_with_unsorted"])
+def test_probe_window_with_many_or_unsorted_long_buckets(gpu, dtype, case):
+    """Plain table, V = 2^17 buckets for 2^18 uniform keys, plus heavy keys
+    placed in the first probe window (buckets below 1024).  over_32_long: 40
+    long buckets there (more than the window's list holds), so the window
+    counts its short buckets from global memory and 8 long buckets have no
+    runs.  staged_with_unsorted: a bucket of 100 distinct keys x 50 (left
+    unsorted), one of 80 x 20 (sorted, too many keys for runs) and one of
+    3 x 3000 (runs); the short buckets are staged in LDS beside them."""
+    V = 1 << 17
+    base = make_keys("uniform", 1 << 18, dtype, 71)
+    if case == "over_32_long":
+        heavy = np.concatenate(keys_in_buckets(dtype, V, list(range(3, 1000, 24))[:40], 1, 72))
+        extra = np.repeat(heavy, 300)
+    else:
+        a, b, c = keys_in_buckets(dtype, V, [7, 300, 600], 100, 73)
+        heavy = np.concatenate([a, b[:80], c[:3]])
+        extra = np.concatenate([np.repeat(a, 50), np.repeat(b[:80], 20), np.repeat(c[:3], 3000)])
+    keys = np.concatenate([base, extra])
+    keys = keys[inputs.uniform_u32(keys.size, 74).argsort(kind="stable")]
+    queries = np.concatenate([np.repeat(heavy, 20), base[::10], make_keys("uniform", 20000, dtype, 75)])
+    check_table(gpu, keys, V=V, queries=queries)
+
+
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
 @pytest.mark.parametrize("shift", [0, 1, 3])
 def test_sorted_probe_output_alignment(gpu, dtype, shift):
