@@ -790,6 +790,44 @@ __device__ __forceinline__ void stage_out(uint32_t* lds, const uint32_t* pos, co
   }
 }
 
+// f(key, e) for each e < m of thread t's stride (t, t + THREADS, ...), with
+// U loads in flight per thread: a lane past the end re-reads the last key
+// and skips the call.  m > 0.
+template <int THREADS, int U, typename K, typename F>
+__device__ __forceinline__ void for_keys(const K* __restrict__ a, uint32_t m, uint32_t t, F&& f) {
+  for (uint32_t e0 = 0; e0 < m; e0 += THREADS * U) {
+    K x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = a[min(e0 + static_cast<uint32_t>(u) * THREADS + t, m - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = e0 + static_cast<uint32_t>(u) * THREADS + t;
+      if (e < m) f(x[u], e);
+    }
+  }
+}
+
+// Adds one to LDS counter b (kPacked: 16-bit half b & 1 of word b >> 1) for
+// every active lane and returns the counter's value before the lane's own
+// add.  The lanes that share the bucket of the wave's first active lane (in
+// a skewed sub-bin, most often its heavy key) add once, together: LDS
+// serialises adds to one address lane by lane.  The others add singly.
+template <bool kPacked>
+__device__ __forceinline__ uint32_t lds_add_grouped(uint32_t* c, uint32_t b) {
+  const uint32_t w = kPacked ? b >> 1 : b, sh = kPacked ? (b & 1u) << 4 : 0u;
+  const uint32_t lead = wave_uniform(b);
+  const bool in_group = b == lead;
+  const uint64_t group = ballot(in_group);
+  const uint32_t rank = popc64(group & lanemask_lt());
+  uint32_t old = 0;
+  // The wave's first active lane is in the group, with rank 0.
+  if (in_group && rank == 0) old = atomicAdd(&c[w], popc64(group) << sh);
+  const uint32_t base = wave_uniform(old);
+  if (!in_group) old = atomicAdd(&c[w], 1u << sh);
+  const uint32_t v = in_group ? base : old;
+  return (kPacked ? (v >> sh) & 0xFFFFu : v) + (in_group ? rank : 0u);
+}
+
 // MINW: waves per SIMD to fit (8: two workgroups of 1024 threads per CU).
 template <typename K, int THREADS, int REG, int MINW>
 __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict__ in,
@@ -805,6 +843,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   __shared__ uint32_t lds[kBuildWords];
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t wsum[THREADS / kWave];
+  constexpr int kFlight = 8;  // loads in flight per thread in the loops over oversized sub-bins
   const uint32_t t = threadIdx.x;
   if (blockIdx.x >= plan->total_subbins) return;  // whole workgroup
   const SubBin sb = sub_bin<false>(plan, scan2, blockIdx.x);
@@ -823,25 +862,8 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     uint4* lds4 = reinterpret_cast<uint4*>(lds);
     for (uint32_t i = t; i < kWideR / 4; i += THREADS) lds4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    const bool regs = m <= static_cast<uint32_t>(THREADS * REG);
-    K v[REG];
-    uint32_t pos[(REG + 1) / 2];  // two 16-bit values per word: bucket, then position
-    if (regs && m > 0) {
-      const uint32_t last = m - 1;
-#pragma unroll
-      for (int j = 0; j < REG; ++j) v[j] = in[sb.kA + min(static_cast<uint32_t>(j) * THREADS + t, last)];
-#pragma unroll
-      for (int j = 0; j < REG; ++j) {
-        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
-        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
-        if (e < m) atomicAdd(&lds[lb], 1u);
-        if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
-      }
-    } else if (!regs) {
-      for (uint32_t e = t; e < m; e += THREADS) atomicAdd(&lds[bucket_of(in[sb.kA + e], log2P, sd) - sb.gA], 1u);
-    }
-    __syncthreads();
-    {
+    // Counters to exclusive offsets, in LDS (the scatter's cursors) and out.
+    auto scan_counters = [&]() {
       uint32_t c[16];
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
@@ -869,17 +891,39 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
 #pragma unroll
       for (int k = 0; k < 16; ++k)
         if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + 16u * t + k, c[k]);
-    }
-    __syncthreads();
-    for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = sb.kA + lds[i];
-    __syncthreads();
-    if (!regs) {
-      for (uint32_t e = t; e < m; e += THREADS) {
-        const K key = in[sb.kA + e];
-        out[sb.kA + atomicAdd(&lds[bucket_of(key, log2P, sd) - sb.gA], 1u)] = key;
-      }
+      __syncthreads();
+      for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = sb.kA + lds[i];
+      __syncthreads();
+    };
+    if (m > static_cast<uint32_t>(THREADS * REG)) {
+      // More keys than the registers hold: two passes over them in global
+      // memory, positions straight to global memory.  A branch of its own,
+      // so that nothing of it stays live across the register path's scan.
+      for_keys<THREADS, kFlight>(in + sb.kA, m, t,
+                                 [&](K key, uint32_t) { lds_add_grouped<false>(lds, bucket_of(key, log2P, sd) - sb.gA); });
+      __syncthreads();
+      scan_counters();
+      for_keys<THREADS, kFlight>(in + sb.kA, m, t, [&](K key, uint32_t) {
+        out[sb.kA + lds_add_grouped<false>(lds, bucket_of(key, log2P, sd) - sb.gA)] = key;
+      });
       return;
     }
+    K v[REG];
+    uint32_t pos[(REG + 1) / 2];  // two 16-bit values per word: bucket, then position
+    if (m > 0) {
+      const uint32_t last = m - 1;
+#pragma unroll
+      for (int j = 0; j < REG; ++j) v[j] = in[sb.kA + min(static_cast<uint32_t>(j) * THREADS + t, last)];
+#pragma unroll
+      for (int j = 0; j < REG; ++j) {
+        const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
+        const uint32_t lb = bucket_of(v[j], log2P, sd) - sb.gA;
+        if (e < m) atomicAdd(&lds[lb], 1u);
+        if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
+      }
+    }
+    __syncthreads();
+    scan_counters();
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = static_cast<uint32_t>(j) * THREADS + t;
@@ -916,10 +960,8 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
         if (j & 1) pos[j >> 1] |= lb << 16; else pos[j >> 1] = lb;
       }
     } else if (!regs) {
-      for (uint32_t e = t; e < m; e += THREADS) {
-        const uint32_t lb = bucket_of(in[sb.kA + e], log2P, sd) - sb.gA;
-        atomicAdd(&lds[lb >> 1], 1u << ((lb & 1u) << 4));
-      }
+      for_keys<THREADS, kFlight>(in + sb.kA, m, t,
+                                 [&](K key, uint32_t) { lds_add_grouped<true>(lds, bucket_of(key, log2P, sd) - sb.gA); });
     }
     __syncthreads();
     lds_exclusive_scan16<THREADS>(lds, R, wsum);
@@ -932,12 +974,9 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     __syncthreads();
     if (!regs) {
       // Oversized sub-bin: positions go straight to global memory.
-      for (uint32_t e = t; e < m; e += THREADS) {
-        const K key = in[sb.kA + e];
-        const uint32_t lb = bucket_of(key, log2P, sd) - sb.gA, sh = (lb & 1u) << 4;
-        const uint32_t p = (atomicAdd(&lds[lb >> 1], 1u << sh) >> sh) & 0xFFFFu;
-        out[sb.kA + p] = key;
-      }
+      for_keys<THREADS, kFlight>(in + sb.kA, m, t, [&](K key, uint32_t) {
+        out[sb.kA + lds_add_grouped<true>(lds, bucket_of(key, log2P, sd) - sb.gA)] = key;
+      });
       return;
     }
 #pragma unroll
