@@ -716,23 +716,26 @@ __device__ __forceinline__ void lds_exclusive_scan32(uint32_t* c, uint32_t R, ui
 // first valid lane's share one atomic (a bucket holding one heavy key then
 // costs one atomic per wave).  With kReturn, each lane gets a distinct old
 // value (its position).
-template <bool kReturn>
+template <bool kReturn, bool kPacked = false>
 __device__ __forceinline__ uint32_t lds_agg_add(uint32_t* ctr, uint32_t idx, bool valid) {
+  // kPacked: counter idx is the 16-bit half idx & 1 of word idx >> 1.
   const uint64_t act = ballot(valid);
   if (act == 0) return 0;
   const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(act)) - 1);
   const uint32_t li = readlane(idx, leader);
   const bool in = valid && idx == li;
   const uint64_t same = ballot(in);
+  const uint32_t sh = kPacked ? (idx & 1u) << 4 : 0u;
+  const uint32_t w = kPacked ? idx >> 1 : idx;
   uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(&ctr[li], popc64(same));
+  if (lane_id() == leader) base = atomicAdd(&ctr[w], popc64(same) << sh);
   uint32_t pos = 0;
   if (kReturn) {
     base = readlane(base, leader);
-    if (in) pos = base + popc64(same & lanemask_lt());
-    else if (valid) pos = atomicAdd(&ctr[idx], 1u);
+    if (in) pos = (kPacked ? (base >> sh) & 0xFFFFu : base) + popc64(same & lanemask_lt());
+    else if (valid) pos = kPacked ? (atomicAdd(&ctr[w], 1u << sh) >> sh) & 0xFFFFu : atomicAdd(&ctr[w], 1u);
   } else if (valid && !in) {
-    atomicAdd(&ctr[idx], 1u);
+    atomicAdd(&ctr[w], 1u << sh);
   }
   return pos;
 }
@@ -807,27 +810,6 @@ __device__ __forceinline__ void for_keys(const K* __restrict__ a, uint32_t m, ui
   }
 }
 
-// Adds one to LDS counter b (kPacked: 16-bit half b & 1 of word b >> 1) for
-// every active lane and returns the counter's value before the lane's own
-// add.  The lanes that share the bucket of the wave's first active lane (in
-// a skewed sub-bin, most often its heavy key) add once, together: LDS
-// serialises adds to one address lane by lane.  The others add singly.
-template <bool kPacked>
-__device__ __forceinline__ uint32_t lds_add_grouped(uint32_t* c, uint32_t b) {
-  const uint32_t w = kPacked ? b >> 1 : b, sh = kPacked ? (b & 1u) << 4 : 0u;
-  const uint32_t lead = wave_uniform(b);
-  const bool in_group = b == lead;
-  const uint64_t group = ballot(in_group);
-  const uint32_t rank = popc64(group & lanemask_lt());
-  uint32_t old = 0;
-  // The wave's first active lane is in the group, with rank 0.
-  if (in_group && rank == 0) old = atomicAdd(&c[w], popc64(group) << sh);
-  const uint32_t base = wave_uniform(old);
-  if (!in_group) old = atomicAdd(&c[w], 1u << sh);
-  const uint32_t v = in_group ? base : old;
-  return (kPacked ? (v >> sh) & 0xFFFFu : v) + (in_group ? rank : 0u);
-}
-
 // MINW: waves per SIMD to fit (8: two workgroups of 1024 threads per CU).
 template <typename K, int THREADS, int REG, int MINW>
 __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict__ in,
@@ -900,11 +882,11 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       // memory, positions straight to global memory.  A branch of its own,
       // so that nothing of it stays live across the register path's scan.
       for_keys<THREADS, kFlight>(in + sb.kA, m, t,
-                                 [&](K key, uint32_t) { lds_add_grouped<false>(lds, bucket_of(key, log2P, sd) - sb.gA); });
+                                 [&](K key, uint32_t) { lds_agg_add<false>(lds, bucket_of(key, log2P, sd) - sb.gA, true); });
       __syncthreads();
       scan_counters();
       for_keys<THREADS, kFlight>(in + sb.kA, m, t, [&](K key, uint32_t) {
-        out[sb.kA + lds_add_grouped<false>(lds, bucket_of(key, log2P, sd) - sb.gA)] = key;
+        out[sb.kA + lds_agg_add<true>(lds, bucket_of(key, log2P, sd) - sb.gA, true)] = key;
       });
       return;
     }
@@ -961,7 +943,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       }
     } else if (!regs) {
       for_keys<THREADS, kFlight>(in + sb.kA, m, t,
-                                 [&](K key, uint32_t) { lds_add_grouped<true>(lds, bucket_of(key, log2P, sd) - sb.gA); });
+                                 [&](K key, uint32_t) { lds_agg_add<false, true>(lds, bucket_of(key, log2P, sd) - sb.gA, true); });
     }
     __syncthreads();
     lds_exclusive_scan16<THREADS>(lds, R, wsum);
@@ -975,7 +957,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     if (!regs) {
       // Oversized sub-bin: positions go straight to global memory.
       for_keys<THREADS, kFlight>(in + sb.kA, m, t, [&](K key, uint32_t) {
-        out[sb.kA + lds_add_grouped<true>(lds, bucket_of(key, log2P, sd) - sb.gA)] = key;
+        out[sb.kA + lds_agg_add<true, true>(lds, bucket_of(key, log2P, sd) - sb.gA, true)] = key;
       });
       return;
     }
