@@ -87,6 +87,29 @@ def test_batched_tables(gpu, case, dtype):
     check_batch(gpu, keys, o, queries, qo)
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+def test_batched_heavy_key_in_the_16bit_subbin(gpu, dtype):
+    """The capped_last_subbin table (8390000 keys; its last sub-bin of 9584
+    buckets takes 16-bit counters) with 5000 copies of one key whose bucket
+    lies in that sub-bin: the sub-bin then holds about 14600 keys, more than
+    the registers take, so the loop path counts and scatters it on packed
+    counters, with the copies' counter adds grouped."""
+    V = 8390000
+    gen = inputs.uniform_u32 if dtype == np.uint32 else inputs.uniform_u64
+    cand = gen(200000, 91)
+    _, b = oracle.hash_bucket(cand, V)
+    heavy = cand[b >= 1023 * 8192][0]
+    table = np.concatenate([gen(V - 5000, 92), np.full(5000, heavy, dtype)])
+    table = table[inputs.uniform_u32(V, 93).argsort(kind="stable")]
+    small = gen(1000, 94)
+    keys = np.concatenate([table, small])
+    o = np.array([0, V, V + 1000], np.uint32)
+    q0 = np.concatenate([np.full(10, heavy, dtype), table[::50]])
+    queries = np.concatenate([q0, small])
+    qo = np.array([0, q0.size, queries.size], np.uint32)
+    check_batch(gpu, keys, o, queries, qo)
+
+
 @pytest.mark.parametrize("num, den", [(1, 2), (3, 2), (4, 1)])
 def test_batched_ratios_and_duplicates(gpu, num, den):
     sizes = [3000, 0, 12000, 500, 1]
