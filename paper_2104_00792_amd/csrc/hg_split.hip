@@ -825,6 +825,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
   __shared__ uint32_t lds[kBuildWords];
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t wsum[THREADS / kWave];
+  __shared__ uint32_t lbase[2];  // this sub-bin's first entries in the long-bucket list, front and back
   constexpr int kFlight = 8;  // loads in flight per thread in the loops over oversized sub-bins
   const uint32_t t = threadIdx.x;
   if (blockIdx.x >= plan->total_subbins) return;  // whole workgroup
@@ -858,22 +859,74 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       uint32_t sum = 0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) sum += c[k];
-      uint32_t total;
-      uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
+      if constexpr (sizeof(K) == 4) {
+        // 32-bit keys: the register path holds this kernel at 64 VGPRs
+        // (eight waves per SIMD), with no room for the reservation below,
+        // so each long bucket appends itself.
+        uint32_t total;
+        uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        uint4 q;
-        q.x = ex;
-        q.y = q.x + c[4 * x];
-        q.z = q.y + c[4 * x + 1];
-        q.w = q.z + c[4 * x + 2];
-        ex = q.w + c[4 * x + 3];
-        lds4[4 * t + x] = q;
+        for (int x = 0; x < 4; ++x) {
+          uint4 q;
+          q.x = ex;
+          q.y = q.x + c[4 * x];
+          q.z = q.y + c[4 * x + 1];
+          q.w = q.z + c[4 * x + 2];
+          ex = q.w + c[4 * x + 3];
+          lds4[4 * t + x] = q;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + 16u * t + k, c[k]);
+        __syncthreads();
+      } else {
+        // One scan carries three sums: keys (bits 0-15, at most
+        // m <= 65535), long buckets for the front of the long-bucket list
+        // (bits 16-25) and for its back (bits 26-31); a long bucket has more
+        // than kLongT keys, so there are at most 1008 of them.  The
+        // workgroup then reserves its entries with one atomic per end
+        // instead of one per bucket: atomics on one address are served one
+        // at a time, and a skewed table has long buckets in almost every
+        // sub-bin.  Bit k of marks: bucket 16t + k is long; bit 16 + k: it
+        // goes to the back (more than kWaveLong keys).
+        uint32_t marks = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          marks |= (c[k] > kLongT ? 1u : 0u) << k;
+          marks |= (c[k] > kWaveLong ? 1u : 0u) << (16 + k);
+        }
+        const uint32_t nback = __popc(marks >> 16), nfront = __popc(marks & 0xFFFFu) - nback;
+        uint32_t total;
+        const uint32_t exs = block_exclusive_sum<THREADS>(sum | (nfront << 16) | (nback << 26), wsum, total);
+        uint32_t ex = exs & 0xFFFFu;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          uint4 q;
+          q.x = ex;
+          q.y = q.x + c[4 * x];
+          q.z = q.y + c[4 * x + 1];
+          q.w = q.z + c[4 * x + 2];
+          ex = q.w + c[4 * x + 3];
+          lds4[4 * t + x] = q;
+        }
+        const uint32_t tfront = (total >> 16) & 0x3FFu, tback = total >> 26;
+        if (t == 0) {
+          if (tfront != 0) lbase[0] = atomicAdd(&long_count[0], tfront);
+          if (tback != 0) lbase[1] = atomicAdd(&long_count[2], tback);
+        }
+        __syncthreads();
+        if (marks != 0) {
+          uint32_t f = lbase[0] + ((exs >> 16) & 0x3FFu), b = lbase[1] + (exs >> 26);
+          for (uint32_t left = marks & 0xFFFFu; left != 0; left &= left - 1) {
+            const uint32_t k = static_cast<uint32_t>(__ffs(left)) - 1;
+            const uint32_t g = sb.gA + 16u * t + k;
+            if ((marks >> (16 + k)) & 1u)
+              long_list[long_count[4] - 1 - b++] = g;
+            else
+              long_list[f++] = g;
+          }
+        }
       }
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-        if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + 16u * t + k, c[k]);
-      __syncthreads();
       for (uint32_t i = t; i < R; i += THREADS) offsets[sb.gA + i] = sb.kA + lds[i];
       __syncthreads();
     };
