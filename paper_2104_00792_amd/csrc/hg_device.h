@@ -183,8 +183,8 @@ __device__ __forceinline__ uint32_t count_short(const K* a, uint32_t lo, uint32_
   return c;
 }
 
-// Occurrences of q among a[lo, hi): a linear scan, or two binary searches
-// when the range is sorted.
+// Occurrences of q among a[lo, hi): a linear scan, or, when the range is
+// sorted, a look at its two ends and at most two binary searches.
 template <typename K, typename Ptr>
 __device__ __forceinline__ uint32_t count_equal(Ptr a, uint32_t lo, uint32_t hi, K q, bool sorted) {
   if (!sorted) {
@@ -192,15 +192,27 @@ __device__ __forceinline__ uint32_t count_equal(Ptr a, uint32_t lo, uint32_t hi,
     for (uint32_t x = lo; x < hi; ++x) c += a[x] == q ? 1u : 0u;
     return c;
   }
+  if (lo >= hi) return 0;
+  // Both ends in one round trip: a bucket of one value (a heavy key alone
+  // in its bucket, the common long bucket of a skewed table) or a query
+  // outside the bucket's range needs no search.
+  const K first = a[lo], last = a[hi - 1];
+  if (first == last) return first == q ? hi - lo : 0u;
+  if (q < first || q > last) return 0;
   uint32_t l = lo, h = hi;  // first position with a[x] >= q
-  while (l < h) {
-    const uint32_t mid = l + ((h - l) >> 1);
-    if (a[mid] < q) l = mid + 1; else h = mid;
+  if (first != q) {
+    while (l < h) {
+      const uint32_t mid = l + ((h - l) >> 1);
+      if (a[mid] < q) l = mid + 1; else h = mid;
+    }
   }
-  uint32_t u = l, uh = hi;  // first position with a[x] > q
-  while (u < uh) {
-    const uint32_t mid = u + ((uh - u) >> 1);
-    if (a[mid] <= q) u = mid + 1; else uh = mid;
+  uint32_t u = hi, uh = hi;  // first position with a[x] > q
+  if (last != q) {
+    u = l;
+    while (u < uh) {
+      const uint32_t mid = u + ((uh - u) >> 1);
+      if (a[mid] <= q) u = mid + 1; else uh = mid;
+    }
   }
   return u - l;
 }
