@@ -1370,14 +1370,14 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       for (uint32_t i = kUK * THREADS + t; i < nk; i += THREADS) skeys[i] = tkeys[ka + i];
     }
     __syncthreads();
-    // Keys that do not fit LDS mean long buckets (more than kLongT keys).  If
-    // there are at most kWinLong of them they are listed in bucket order with
-    // their key ranges, and one wave per sorted one finds each run's end by
-    // 64-way search and keeps the runs (at most kSetMax) in LDS.  When the
-    // short buckets' keys then fit beside those tables they are staged too,
-    // compacted: the offsets are rewritten to compacted positions, with
-    // kLongMark on a long bucket's own offset.  Only queries into a long
-    // bucket without runs then read global memory.
+    // Keys that do not fit LDS mean long buckets (more than kLongT keys).  Up
+    // to kWinLong of them are listed in bucket order with their key ranges,
+    // and one wave per sorted one finds each run's end by 64-way search and
+    // keeps the runs (at most kSetMax) in LDS.  When every long bucket is
+    // listed and the short buckets' keys fit beside those tables, they are
+    // staged too, compacted: the offsets are rewritten to compacted
+    // positions, with kLongMark on a long bucket's own offset.  Only queries
+    // into a long bucket without runs then read global memory.
     constexpr uint32_t kWinLong = 32;
     uint32_t* lbkt = reinterpret_cast<uint32_t*>(skeys);  // window bucket of each long bucket, ascending
     uint32_t* lnr = lbkt + kWinLong;                      // its runs, or kOver
