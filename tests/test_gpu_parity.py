@@ -322,6 +322,24 @@ def test_probe_window_with_many_or_unsorted_long_buckets(gpu, dtype, case):
 
 
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("values, copies", [
+    ([100, 200, 300], [3000, 2000, 1000]),  # three runs: first, middle and last value
+    ([100, 300], [2500, 2500]),             # two runs: either end equals the query
+    ([100], [5000]),                        # one run: both ends equal
+])
+def test_sorted_long_bucket_counts_from_its_ends(gpu, dtype, values, copies):
+    """One bucket (V = 1) of a few values, rewritten as ascending runs.
+    Queries equal to its first, last and middle values, below, above and
+    between them: the count in a sorted bucket looks at both ends first and
+    searches only when it must, in LDS (sorted probe) and in global memory
+    (direct probe)."""
+    keys = np.repeat(np.array(values, dtype), copies)
+    keys = keys[inputs.uniform_u32(keys.size, 81).argsort(kind="stable")]
+    queries = np.repeat(np.array([100, 200, 300, 50, 400, 150, 250, 0], dtype), 7)
+    check_table(gpu, keys, V=1, queries=queries)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
 @pytest.mark.parametrize("shift", [0, 1, 3])
 def test_sorted_probe_output_alignment(gpu, dtype, shift):
     """The last gather of the sorted probe stores whole vectors when the
