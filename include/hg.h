@@ -220,10 +220,10 @@ hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt,
                            uint32_t* d_part_offsets, hipStream_t stream);
 
 /* hg_bin_partition_balanced -- the hash-range split with count-balanced
- * ranges (Algorithm 2, Phases 1 and 2; Sec. 4.1 "Phase 1: Multi-GPU Data
+ * ranges (Algorithm 2, Phases 1 and 2; Sec. 3.3 "Phase 1: Multi-GPU Data
  * Partitioning"), P ranges for P devices.
  *   H(k) = hash(k) mod hash_range, 1 <= hash_range < 2^32 (the hash range
- *   HR of Sec. 4.1, e.g. the global table size).  The range is cut into
+ *   HR of Sec. 3.3, e.g. the global table size).  The range is cut into
  *   bins of BinSize = ceil(HR / num_bins) consecutive values, bin =
  *   floor(H / BinSize), ceil(HR / BinSize) bins; num_bins 0 takes
  *   ceil(sqrt(HR)) (the paper's O(sqrt(HR))), num_bins <= 2^14.

@@ -35,9 +35,9 @@
 //
 // Pins (what ties this file to something other than itself) live in the
 // test suite: published MurmurHash3 test vectors and a library MurmurHash3
-// for fmix32, an inverse round trip for fmix64's structure, brute force on
-// tiny inputs for the CSR, and invariants at every size.  fmix64's constants
-// are pinned only by the published definition ("parity unpinned" for them).
+// for fmix32, SMHasher's published verification value of MurmurHash3_x64_128
+// for fmix64, Python-integer remainders for the bucket map, brute force on
+// tiny inputs for the CSR, and invariants at every size.
 
 #include <algorithm>
 #include <cstdint>
@@ -287,7 +287,7 @@ int orc_bin_partition(const void* keys, uint64_t n, int kt, uint32_t P,
   return ORC_OK;
 }
 
-// Step O6: the count-balanced split of Algorithm 2, Phases 1 and 2 (Sec. 4.1,
+// Step O6: the count-balanced split of Algorithm 2, Phases 1 and 2 (Sec. 3.3,
 // "Phase 1: Multi-GPU Data Partitioning" and "Phase 2"), one partition per
 // device.  The reduced hash H = hash mod HR covers the hash range HR; the
 // range is cut into bins of BinSize = ceil(HR / num_bins) consecutive values

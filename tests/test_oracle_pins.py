@@ -4,10 +4,13 @@
   MurmurHash3 (scikit-learn's murmurhash3_32, called, never read), both through
   a MurmurHash3_x86_32 built here around the oracle's finalizer; plus a round
   trip through an inverse derived from the mathematics.
-* fmix64: the same inverse round trip.  No installed library exposes the
-  64-bit finalizer, so its constants are pinned only by the published
-  definition ("parity unpinned" for those constants; oracle/GPU parity is
-  unaffected).
+* fmix64: the published SMHasher verification value of MurmurHash3_x64_128,
+  computed through a MurmurHash3_x64_128 built here around the oracle's 64-bit
+  finalizer (the x86_32 verification value checks the procedure); plus the
+  inverse round trip.
+* Bucket map (Algorithm 1, first loop): every bucket equals the hash modulo V
+  in Python integers, for 32- and 64-bit hashes and divisors at the edges of
+  the 32-bit range.
 * CSR build (Algorithm 1, CSR of Sec. 3.1, Algorithm 2 Phase 2): brute force
   from the definition on tiny inputs, invariants at moderate size, the V = 1
   special case (the table is sort(A)).
@@ -65,6 +68,56 @@ def murmur3_x86_32(data: bytes, seed: int) -> int:
         h ^= k
     h ^= len(data)
     return oracle.fmix32(h)
+
+
+def rotl64(x, r):
+    return ((x << r) | (x >> (64 - r))) & M64
+
+
+def murmur3_x64_128(data: bytes, seed: int) -> bytes:
+    """MurmurHash3_x64_128 (Appleby): body, tail and the final mixing of the
+    two halves written here, the 64-bit finalizer taken from the oracle.
+    Returns the 16-byte digest (h1 then h2, little-endian)."""
+    c1, c2 = 0x87C37B91114253D5, 0x4CF5AD432745937F
+    h1 = h2 = seed & M32
+    nblocks = len(data) // 16
+    for i in range(nblocks):
+        k1 = int.from_bytes(data[16 * i:16 * i + 8], "little")
+        k2 = int.from_bytes(data[16 * i + 8:16 * i + 16], "little")
+        k1 = rotl64((k1 * c1) & M64, 31)
+        h1 ^= (k1 * c2) & M64
+        h1 = (rotl64(h1, 27) + h2) & M64
+        h1 = (h1 * 5 + 0x52DCE729) & M64
+        k2 = rotl64((k2 * c2) & M64, 33)
+        h2 ^= (k2 * c1) & M64
+        h2 = (rotl64(h2, 31) + h1) & M64
+        h2 = (h2 * 5 + 0x38495AB5) & M64
+    tail = data[16 * nblocks:]
+    k1 = int.from_bytes(tail[:8], "little")
+    k2 = int.from_bytes(tail[8:], "little")
+    if len(tail) > 8:
+        h2 ^= (rotl64((k2 * c2) & M64, 33) * c1) & M64
+    if tail:
+        h1 ^= (rotl64((k1 * c1) & M64, 31) * c2) & M64
+    h1 ^= len(data)
+    h2 ^= len(data)
+    h1 = (h1 + h2) & M64
+    h2 = (h2 + h1) & M64
+    h1 = oracle.fmix64(h1)
+    h2 = oracle.fmix64(h2)
+    h1 = (h1 + h2) & M64
+    h2 = (h2 + h1) & M64
+    return h1.to_bytes(8, "little") + h2.to_bytes(8, "little")
+
+
+def smhasher_verification(digest) -> int:
+    """SMHasher's verification value of a hash function `digest(data, seed)
+    -> bytes`: the keys {}, {0}, {0,1}, ... of 0..255 bytes hashed with seed
+    256 - length, their digests concatenated and hashed with seed 0; the
+    first four bytes of that digest, little-endian."""
+    key = bytes(range(256))
+    cat = b"".join(digest(key[:i], 256 - i) for i in range(256))
+    return int.from_bytes(digest(cat, 0)[:4], "little")
 
 
 def modinv_pow2(c: int, bits: int) -> int:
@@ -150,6 +203,44 @@ def pin_murmur3_against_library():
         # murmurhash3_32 of an int hashes its 4 little-endian bytes
         ref = murmurhash3_32(int(np.int32(np.uint32(k))), seed=int(s), positive=True)
         assert murmur3_x86_32(int(k).to_bytes(4, "little"), s) == ref, (k, s)
+
+
+def pin_smhasher_verification_values():
+    """fmix64's constants through the published verification value of
+    MurmurHash3_x64_128; the x86_32 value checks the procedure."""
+    impl = {"MurmurHash3_x86_32": lambda d, s: murmur3_x86_32(d, s).to_bytes(4, "little"),
+            "MurmurHash3_x64_128": murmur3_x64_128}
+    seen = set()
+    with open(os.path.join(GOLDEN, "smhasher_verification.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, bits, want = line.split()
+            got = smhasher_verification(impl[name])
+            assert len(impl[name](b"", 0)) * 8 == int(bits), name
+            assert got == int(want, 16), (name, hex(got))
+            seen.add(name)
+    assert seen == set(impl)
+
+
+def pin_bucket_map():
+    """The bucket of Algorithm 1 is the hash modulo V: each bucket the
+    oracle reports equals the Python-integer remainder of the full hash
+    (all 64 bits of a 64-bit hash), for divisors at the edges of the 32-bit
+    range and random ones, on 32- and 64-bit keys."""
+    rng = np.random.default_rng(11)
+    divisors = [1, 2, 3, 7, (1 << 16) + 1, (1 << 31) - 1, 1 << 31, (1 << 31) + 1, (1 << 32) - 2, (1 << 32) - 1]
+    divisors += [int(x) for x in rng.integers(1, 1 << 32, size=6, dtype=np.uint64)]
+    for dt, fmix in ((np.uint32, oracle.fmix32), (np.uint64, oracle.fmix64)):
+        top = (1 << 32) if dt == np.uint32 else (1 << 64)
+        keys = np.concatenate([np.array([0, 1, top - 1, top // 2], dtype=np.uint64),
+                               rng.integers(0, 1 << 63, size=3000, dtype=np.uint64) * np.uint64(2) +
+                               rng.integers(0, 2, size=3000, dtype=np.uint64)]).astype(dt)
+        want_h = [fmix(int(k)) for k in keys.tolist()]
+        for V in divisors:
+            h, b = oracle.hash_bucket(keys, V)
+            assert h.tolist() == want_h, (dt, V)
+            assert b.tolist() == [x % V for x in want_h], (dt, V)
 
 
 def pin_fmix32_inverse_round_trip():
@@ -345,7 +436,8 @@ def pin_build_like():
                     assert where[key] == b
 
 
-PINS = [pin_murmur3_published_vectors, pin_murmur3_against_library, pin_fmix32_inverse_round_trip,
+PINS = [pin_murmur3_published_vectors, pin_murmur3_against_library, pin_smhasher_verification_values,
+        pin_bucket_map, pin_fmix32_inverse_round_trip,
         pin_fmix64_inverse_round_trip, pin_csr_brute_force, pin_csr_invariants, pin_counts, pin_partition,
         pin_balanced_worked_example, pin_balanced_split_definition, pin_build_like]
 
@@ -363,6 +455,9 @@ MUTANTS = {
     "fmix32_constant": ("h *= 0x85ebca6bu;", "h *= 0x85ebca6cu;"),
     "fmix64_shift": ("  k ^= k >> 33;\n  k *= 0xff51afd7ed558ccdull;", "  k ^= k >> 31;\n  k *= 0xff51afd7ed558ccdull;"),
     "fmix64_constant": ("k *= 0xc4ceb9fe1a85ec53ull;", "k *= 0xc4ceb9fe1a85ec55ull;"),
+    "fmix64_first_constant": ("k *= 0xff51afd7ed558ccdull;", "k *= 0xff51afd7ed558ccfull;"),
+    "bucket_map_truncated_hash": ("bucket_out[i] = static_cast<uint32_t>(h % V);",
+                                  "bucket_out[i] = static_cast<uint32_t>(h) % static_cast<uint32_t>(V);"),
     "partition_low_bits": ("return static_cast<uint32_t>(h >> (w - log2P));",
                            "return static_cast<uint32_t>(h & ((1ull << log2P) - 1));"),
     "bucket_dropped_hash_bit": ("h[i] % V[p_of[i]]", "(h[i] >> 1) % V[p_of[i]]"),
