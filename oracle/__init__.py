@@ -23,6 +23,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hg_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle_hg.so")
+# The same source built for all host cores (OpenMP, GNU parallel-mode sort).
+_LIB_PAR = os.path.join(_HERE, "liboracle_hg_par.so")
 
 KT_U32 = 0
 KT_U64 = 1
@@ -30,10 +32,13 @@ KT_U64 = 1
 _lib = None
 
 
-def compile_oracle(src: str, out: str) -> str:
-    """Compile an oracle source file with g++ (no HIP, no GPU headers)."""
+def compile_oracle(src: str, out: str, parallel: bool = False) -> str:
+    """Compile an oracle source file with g++ (no HIP, no GPU headers).
+    ``parallel``: the all-core build of the same source (OpenMP loops and the
+    GNU parallel-mode std::sort)."""
     tmp = out + ".tmp"
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", src, "-o", tmp]
+    extra = ["-fopenmp", "-D_GLIBCXX_PARALLEL"] if parallel else []
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", *extra, src, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -42,6 +47,8 @@ def compile_oracle(src: str, out: str) -> str:
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         compile_oracle(_SRC, _LIB)
+    if force or not os.path.exists(_LIB_PAR):
+        compile_oracle(_SRC, _LIB_PAR, parallel=True)
     return _LIB
 
 
@@ -82,6 +89,30 @@ def use_library(path: str | None):
     Used only by the planted-mistake tests."""
     global _lib
     _lib = None if path is None else load_library(path)
+
+
+class all_cores:
+    """``with oracle.all_cores(): ...`` runs the oracle calls inside on the
+    all-core build of the same source (``threads`` OpenMP threads; None: the
+    OpenMP default), then returns to the single-threaded build."""
+
+    def __init__(self, threads: int | None = None):
+        self.threads = threads
+
+    def __enter__(self):
+        global _lib
+        if not os.path.exists(_LIB_PAR):
+            compile_oracle(_SRC, _LIB_PAR, parallel=True)
+        self._saved = _lib
+        if self.threads is not None:
+            os.environ["OMP_NUM_THREADS"] = str(self.threads)
+        _lib = load_library(_LIB_PAR)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
 
 
 def _kt(a: np.ndarray) -> int:

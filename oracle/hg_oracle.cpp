@@ -33,6 +33,12 @@
 // remainder (never a multiply-shift range reduction); partitions by the top
 // hash bits; V_p >= 1 always; n = 0 is a legal empty table.
 //
+// Threads.  Built plainly (g++ -O2) every loop runs on one thread.  The
+// all-core build compiles this same file with -fopenmp -D_GLIBCXX_PARALLEL:
+// std::sort then runs as the GNU parallel-mode sort, and the two loops
+// marked `omp parallel for` (independent iterations, each writing only its
+// own element) are shared among the threads.  Nothing else changes.
+//
 // Pins (what ties this file to something other than itself) live in the
 // test suite: published MurmurHash3 test vectors and a library MurmurHash3
 // for fmix32, SMHasher's published verification value of MurmurHash3_x64_128
@@ -210,6 +216,7 @@ int orc_build(const void* keys, uint64_t n, int kt, uint32_t P, uint32_t num,
   // O1 (cont.): the bucket of every key inside its partition's table.
   typedef std::tuple<uint32_t, uint32_t, uint64_t> Tup;  // (p, b, key)
   std::vector<Tup> t(n);
+#pragma omp parallel for schedule(static)
   for (uint64_t i = 0; i < n; ++i) {
     const uint32_t b = static_cast<uint32_t>(h[i] % V[p_of[i]]);
     t[i] = Tup(p_of[i], b, key_at(keys, kt, i));
@@ -253,6 +260,7 @@ int orc_count(const void* keys, uint64_t n, int kt, const void* queries,
   std::vector<uint64_t> a(n);
   for (uint64_t i = 0; i < n; ++i) a[i] = key_at(keys, kt, i);
   std::sort(a.begin(), a.end());
+#pragma omp parallel for schedule(static)
   for (uint64_t j = 0; j < q; ++j) {
     const uint64_t x = key_at(queries, kt, j);
     const auto r = std::equal_range(a.begin(), a.end(), x);

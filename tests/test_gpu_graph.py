@@ -92,8 +92,11 @@ def test_batched_build_and_count_replay(gpu):
 
 
 def test_tuning_knobs_do_not_change_the_table(gpu):
-    """log2_subbin and split_bits change speed only: offsets, bucket contents
-    and counts are the same for every setting."""
+    """log2_subbin and split_bits change speed only: for every setting the
+    partition offsets, bucket bases, offsets, bucket contents and counts are
+    the oracle's.  (10, 7) makes level-1 segments smaller than a partition's
+    table, so the build splits by coarse bucket ranges (it launches the
+    partition count first); the other settings split by partition."""
     import torch
 
     import oracle
@@ -101,22 +104,27 @@ def test_tuning_knobs_do_not_change_the_table(gpu):
     hg = gpu
     n = (1 << 22) + 777
     raw = inputs.uniform_u32(n, 0xD5)
+    raw_q = inputs.queries_hit50(raw, n, 0xD6)
     keys = to_dev(raw)
-    queries = to_dev(inputs.queries_hit50(raw, n, 0xD6))
-    ref_offs = ref_keys = ref_counts = None
-    for sub, bits in [(0, 0), (11, 7), (12, 9), (13, 10), (10, 8)]:
-        t = hg.hg_build(keys, P=16, log2_subbin=sub, split_bits=bits)
-        _, _, offs, tk = t.export()
-        c = hg.hg_count(t, queries)
-        torch.cuda.synchronize()
+    queries = to_dev(raw_q)
+    ref = oracle.build_table(raw, P=16)
+    want = oracle.count(raw, raw_q)
+    coarse = {}
+    for sub, bits in [(0, 0), (11, 7), (12, 9), (13, 10), (10, 8), (10, 7)]:
+        with hg.profile() as prof:
+            t = hg.hg_build(keys, P=16, log2_subbin=sub, split_bits=bits)
+            po, bb, offs, tk = t.export()
+            c = hg.hg_count(t, queries)
+            torch.cuda.synchronize()
+        coarse[(sub, bits)] = "part_count" in prof.results
         offs, tk, c = offs.cpu().numpy(), tk.cpu().numpy(), c.cpu().numpy()
-        canon = oracle.canonicalize(offs, tk)
-        if ref_offs is None:
-            ref_offs, ref_keys, ref_counts = offs, canon, c
-        assert np.array_equal(offs, ref_offs), (sub, bits)
-        assert np.array_equal(canon, ref_keys), (sub, bits)
-        assert np.array_equal(c, ref_counts), (sub, bits)
+        assert np.array_equal(po.cpu().numpy(), ref["part_offsets"]), (sub, bits)
+        assert np.array_equal(bb.cpu().numpy(), ref["bucket_base"]), (sub, bits)
+        assert np.array_equal(offs, ref["offsets"]), (sub, bits)
+        assert np.array_equal(oracle.canonicalize(offs, tk), ref["keys"]), (sub, bits)
+        assert np.array_equal(c, want), (sub, bits)
         t.free()
+    assert coarse[(10, 7)] and not coarse[(0, 0)], coarse
 
 
 def test_batched_subbin_knob(gpu):
