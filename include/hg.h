@@ -219,6 +219,24 @@ hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt,
                            uint32_t P, void* d_out_keys,
                            uint32_t* d_part_offsets, hipStream_t stream);
 
+/* hg_bin_partition_noalloc -- hg_bin_partition for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs and errors as
+ * hg_bin_partition; it allocates nothing (no hipMalloc, hipFree or pool
+ * call).  Its per-tile counts and scan sums live in a fixed scratch array of
+ * 2^20 + 1024 words (4 MiB + 4 KiB) inside the library, one per device, kept
+ * until the process ends: it holds P * ceil(n / 4096) <= 2^20 tile counts
+ * and the scan's sums, i.e. n <= 2^28 keys for P = 16 or n <= 2^24 for
+ * P = 256.  Larger requests return HG_ERR_INVALID_ARG (before anything is
+ * enqueued).  Calls that
+ * overlap on one device (other streams, other threads) share that array and
+ * race: order them on one stream.  Every call rewrites all the scratch it
+ * reads, so nothing has to be cleared between calls. */
+hg_status hg_bin_partition_noalloc(const void* d_keys, uint64_t n,
+                                   hg_key_type kt, uint32_t P,
+                                   void* d_out_keys, uint32_t* d_part_offsets,
+                                   hipStream_t stream);
+
 /* hg_bin_partition_balanced -- the hash-range split with count-balanced
  * ranges (Algorithm 2, Phases 1 and 2; Sec. 3.3 "Phase 1: Multi-GPU Data
  * Partitioning"), P ranges for P devices.

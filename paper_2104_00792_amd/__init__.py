@@ -18,6 +18,7 @@ import os
 
 __all__ = [
     "HGError", "Table", "hg_build", "hg_build_like", "hg_intersect", "hg_count", "hg_query", "hg_bin_partition",
+    "hg_bin_partition_noalloc",
     "hg_hash_bucket", "hg_bin_partition_balanced", "hg_build_batched", "hg_count_batched", "hg_query_batched", "hg_trim_pool",
     "hg_set_allocator", "hg_workspace_size", "torch_allocator", "lib", "lib_path", "profile",
 ]
@@ -124,6 +125,8 @@ def lib() -> ctypes.CDLL:
     L.hg_query_batched.restype = i32
     L.hg_bin_partition.argtypes = [vp, u64, i32, u32, vp, vp, vp]
     L.hg_bin_partition.restype = i32
+    L.hg_bin_partition_noalloc.argtypes = [vp, u64, i32, u32, vp, vp, vp]
+    L.hg_bin_partition_noalloc.restype = i32
     L.hg_bin_partition_balanced.argtypes = [vp, u64, i32, u32, u64, u32, vp, vp, vp, vp]
     L.hg_bin_partition_balanced.restype = i32
     L.hg_hash_bucket.argtypes = [vp, u64, i32, u64, vp, vp, vp]
@@ -435,6 +438,16 @@ def hg_bin_partition(keys, P: int, out=None, part_offsets=None, stream=None):
         part_offsets = torch.empty(P + 1, dtype=torch.uint32, device=keys.device)
     _check(lib().hg_bin_partition(_dev_ptr(keys), keys.numel(), kt, P, _dev_ptr(out), _dev_ptr(part_offsets),
                                   _stream(stream)), "hg_bin_partition")
+    return out, part_offsets
+
+
+def hg_bin_partition_noalloc(keys, P: int, out, part_offsets, stream=None):
+    """hg_bin_partition into caller-given outputs with no device allocation
+    by the library (its scratch is a fixed array of 2^20 + 1024 words per
+    device, so P * ceil(n / 4096) <= 2^20).  Returns (out, part_offsets)."""
+    kt = _key_type(keys)
+    _check(lib().hg_bin_partition_noalloc(_dev_ptr(keys), keys.numel(), kt, P, _dev_ptr(out), _dev_ptr(part_offsets),
+                                          _stream(stream)), "hg_bin_partition_noalloc")
     return out, part_offsets
 
 

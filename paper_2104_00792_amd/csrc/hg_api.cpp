@@ -1048,6 +1048,77 @@ hg_status hg_bin_partition(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   return HG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of hg_bin_partition_noalloc: the per-tile partition counts,
+// then the scan's block sums.  Every device the library runs on holds its own
+// copy until the process ends.  In host code `scratch` is only a stand-in for
+// the symbol; the device address comes from hipGetSymbolAddress, once per
+// device (scratch_on).
+constexpr uint64_t kScratchWords = (uint64_t(1) << 20) + 1024;  // 4 MiB + 4 KiB
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+std::mutex g_scratch_mu;
+std::map<int, uint32_t*> g_scratch_ptr;
+
+// The address of device `dev`'s scratch (that device must be current).
+hipError_t scratch_on(int dev, uint32_t** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  *out = static_cast<uint32_t*>(p);
+  return hipSuccess;
+}
+
+// hg_bin_partition_noalloc takes at most kScratchCounts tile counts; padded
+// to 256 bytes and followed by the scan's block sums they fit the scratch.
+constexpr uint64_t kScratchCounts = uint64_t(1) << 20;
+static_assert(kScratchCounts + kScratchCounts / hg::kScanChunk + 1 <= kScratchWords, "scratch holds counts and sums");
+
+}  // namespace
+
+extern "C" {
+
+hg_status hg_bin_partition_noalloc(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t P, void* d_out_keys,
+                                   uint32_t* d_part_offsets, hipStream_t stream) {
+  hg_status st = check_n_P(n, kt, P);
+  if (st != HG_OK) return st;
+  if (d_part_offsets == nullptr) return fail(HG_ERR_INVALID_ARG, "null part_offsets");
+  if (n > 0 && (d_keys == nullptr || d_out_keys == nullptr)) return fail(HG_ERR_INVALID_ARG, "null keys");
+  const uint64_t need = static_cast<uint64_t>(P) * hg::div_up(n, hg::kTileKeys);
+  if (need > kScratchCounts)
+    return fail(HG_ERR_INVALID_ARG,
+                "hg_bin_partition_noalloc: n = %llu keys in P = %u partitions need %llu tile counts of scratch "
+                "(P * ceil(n / %d)), more than its %llu; use hg_bin_partition",
+                (unsigned long long)n, P, (unsigned long long)need, hg::kTileKeys,
+                (unsigned long long)kScratchCounts);
+  int dev = 0;
+  HG_TRY(hipGetDevice(&dev), "hipGetDevice");
+  uint32_t* ws = nullptr;
+  HG_TRY(scratch_on(dev, &ws), "hipGetSymbolAddress(scratch)");
+  const uint32_t n32 = static_cast<uint32_t>(n);
+  const uint32_t num_tiles = hg::div_up(n, hg::kTileKeys);
+  const uint64_t elems = static_cast<uint64_t>(P) * num_tiles;
+  // The count pass writes every (partition, tile) entry and the scan every
+  // block sum, so nothing left by an earlier call is read.
+  uint32_t* tile_counts = ws;
+  uint32_t* bsums = ws + (elems + 63) / 64 * 64;
+  st = run_partition(d_keys, n32, kt, log2_of(P), num_tiles, tile_counts, bsums, d_out_keys, stream);
+  if (st != HG_OK) return st;
+  HG_LAUNCH("part_offsets", stream,
+            hg::launch_layout(tile_counts, num_tiles, P, n32, 1, 1, 0, d_part_offsets, nullptr, nullptr, stream));
+  return HG_OK;
+}
+
 hg_status hg_bin_partition_balanced(const void* d_keys, uint64_t n, hg_key_type kt, uint32_t P, uint64_t hash_range,
                                     uint32_t num_bins, void* d_out_keys, uint32_t* d_part_offsets,
                                     uint32_t* d_bin_splits, hipStream_t stream) {

@@ -124,6 +124,22 @@ def test_bin_partition_rejects(lib):
     assert lib.hg_bin_partition(FAKE, 10, 0, 1024, FAKE, FAKE, None) == HG_ERR_UNSUPPORTED
 
 
+def test_bin_partition_noalloc_rejects(lib):
+    """Argument errors, including a request larger than the fixed scratch
+    (P * ceil(n / 4096) above 2^20), come back before any HIP call."""
+    f = lib.hg_bin_partition_noalloc
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    assert f(FAKE, 10, 0, 3, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert f(FAKE, 10, 0, 16, FAKE, None, None) == HG_ERR_INVALID_ARG
+    assert f(None, 10, 0, 16, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert f(FAKE, 1 << 32, 0, 16, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert f(FAKE, 10, 0, 1024, FAKE, FAKE, None) == HG_ERR_UNSUPPORTED
+    assert f(FAKE, (1 << 28) + 1, 0, 16, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+    assert "scratch" in lib.hg_last_error().decode()
+    assert f(FAKE, (1 << 24) + 1, 1, 256, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
+
+
 def test_hash_bucket_rejects(lib):
     assert lib.hg_hash_bucket(FAKE, 10, 0, 0, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
     assert lib.hg_hash_bucket(FAKE, 10, 0, 1 << 32, FAKE, FAKE, None) == HG_ERR_INVALID_ARG
