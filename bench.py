@@ -33,7 +33,8 @@ DESCRIPTIONS = {
                     "local tables V_p=n_p; 2^28 queries at 50% hit",
     "plain_u32_2^28": "n=2^28 uint32 keys uniform; plain table V=n; 2^28 queries at 50% hit",
     "plain_u32_2^20": "n=2^20 uint32 keys uniform; plain table V=n; 2^20 queries at 50% hit",
-    "zipf_u64_2^27": "n=2^27 uint64 keys Zipf(1.0) over 2^20 values; fmix64; V=n/2; 2^27 Zipf queries",
+    "zipf_u64_2^27": "n=2^27 uint64 keys Zipf(1.0) over 2^20 values (value of rank r = the SplitMix64 output "
+                     "mixer of r, a bijection like fmix64); hash fmix64; V=n/2; 2^27 Zipf queries",
     "batched_u32_4096": "4096 uint32 tables, sizes log-uniform in [2^10, 2^20] (622M keys), per-table seeds, "
                         "V_t = n_t; each probed by n_t queries at 50% hit; one hg_build_batched + "
                         "hg_count_batched per step",
@@ -59,11 +60,66 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> float:
-    """Bytes the kernel's function must move per launch, independent of how
-    the kernel moves them (n keys of ks bytes, q queries, B buckets).  Split
-    passes run once on the keys (build) and once on the queries (probe); with
-    q == n both launches move the same bytes."""
+def survey_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> float:
+    """Algorithmic bytes per launch of a kernel under the scope table's model
+    of the path (HBM bytes per key and per query of each step of the method,
+    with the O(V_p) working sets of a partition group in the Infinity Cache),
+    charged to the kernel that carries that step out.  Kernels that carry
+    out no step of the model (the second split level and its gather, the
+    coarse-range count) are charged 0: their bytes are this design's
+    overhead.  Per 32-bit key: partition count 4, partition scatter 8, local
+    histogram 4, offsets 4 per bucket, local scatter 8 (28 per key with
+    V = n); per query: count + stable scatter 12, probe in partition order 8
+    (query in, count out; table reads from the cache), un-partition 12."""
+    cnt = 4  # counts are u32 in the model
+    part = P > 1
+    table = {
+        # sorted build: a2 and a4 exist only with partitions
+        "part_count": ks * n if part else 0,              # a2: read keys
+        "split1_count": 0 if part else ks * n,            # plain table: a5 reads the keys; else overhead
+        "split1_scatter": 2 * ks * n if part else 0,      # a4: keys in, buffer out
+        "split2_count": ks * n if part else 0,            # a5: read the buffer
+        "split2_scatter": 0,
+        "lds_build": 2 * ks * n + 4 * B,                  # a7 read + write keys, a6 offsets
+        # sorted probe
+        "qsplit1_count": ks * q,                          # a9 count
+        "qsplit1_scatter": 2 * ks * q,                    # a9 stable scatter
+        "qsplit2_count": 0,
+        "qsplit2_scatter": 0,
+        "lds_probe": ks * q + cnt * q,                    # probe in partition order
+        "qgather2": 0,
+        "qgather1": (ks + 2 * cnt) * q,                   # un-partition
+        # batched tables: each table is a plain table
+        "bsplit_count": ks * n,
+        "blds_build": 2 * ks * n + 4 * B,
+        "bqsplit_count": ks * q,
+        "bqsplit_scatter": 2 * ks * q,
+        "blds_probe": ks * q + cnt * q,
+        "bqgather": (ks + 2 * cnt) * q,
+        # atomic build and direct probe (small tables): the streaming part
+        "bucket_hist": ks * n,
+        "bucket_scan": 4 * B,
+        "bucket_scatter": 2 * ks * n,
+        "probe_count": ks * q + cnt * q,
+        "probe_found": ks * q + q,
+    }
+    return float(table.get(kernel, 0))
+
+
+def survey_step_bytes(n: int, q: int, B: int, ks: int, P: int) -> float:
+    """The model's bytes for one build + probe step (sum over its steps):
+    60 per key and query pair for 32-bit keys, P > 1 and V = n."""
+    build = (3 * ks * n if P > 1 else 0) + ks * n + 4 * B + 2 * ks * n
+    probe = (5 * ks + 3 * 4) * q
+    return float(build + probe)
+
+
+def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int, cb: int = 4) -> float:
+    """Bytes the kernel's own function must move per launch in this design,
+    independent of how the kernel moves them (n keys of ks bytes, q
+    queries, B buckets; cb = bytes per count passed between the probe's
+    kernels, 1 for a table without long buckets, else 4).  Split passes run
+    once on the keys (build) and once on the queries (probe)."""
     table = {
         # build, sorted path
         "part_count": ks * n,                       # read keys
@@ -77,17 +133,17 @@ def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> f
         "qsplit1_scatter": (2 * ks + 2) * q,        # queries in and out, 16-bit tile slots out
         "qsplit2_count": ks * q,
         "qsplit2_scatter": (2 * ks + 2) * q,
-        "lds_probe": ks * q + 4 * B + ks * n + 4 * q,  # queries, offsets, table keys, counts out
-        "qgather2": 10 * q,                         # tile slots, counts in, counts out
-        "qgather1": 10 * q,
+        "lds_probe": ks * q + 4 * B + ks * n + cb * q,  # queries, offsets, table keys, counts out
+        "qgather2": (2 + 2 * cb) * q,               # tile slots, counts in, counts out
+        "qgather1": (2 + cb + 4) * q,               # tile slots, counts in, u32 counts out
         # batched tables
         "bsplit_count": ks * n,
         "bsplit_scatter": 2 * ks * n,
         "blds_build": 2 * ks * n + 4 * B,
         "bqsplit_count": ks * q,
         "bqsplit_scatter": (2 * ks + 2) * q,
-        "blds_probe": ks * q + 4 * B + ks * n + 4 * q,
-        "bqgather": 10 * q,
+        "blds_probe": ks * q + 4 * B + ks * n + cb * q,
+        "bqgather": (2 + cb + 4) * q,
         # atomic path and direct probe
         "zero_counts": 4 * (B + 1),                 # counters written
         "bucket_hist": ks * n + 4 * B,              # keys in, counters out once
@@ -100,9 +156,9 @@ def algorithmic_bytes(kernel: str, n: int, q: int, B: int, ks: int, P: int) -> f
     return float(table.get(kernel, 0))
 
 
-def read_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when absent or taken on another kernel source."""
+def read_traffic_file(workload: str) -> dict | None:
+    """The committed rocprofv3 counter summary of a workload as key -> value
+    strings, or None when absent or taken on another kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -115,24 +171,78 @@ def read_traffic(workload: str, kernel: str):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    return vals
+
+
+def read_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when absent or taken on another kernel source."""
+    vals = read_traffic_file(workload)
+    if vals is None:
+        return None
     key = f"hbm_bytes_per_launch.{kernel}"
     return float(vals[key]) if key in vals else None
 
 
-def cpu_baseline(workload: str, n_sample: int):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload: str, n_one: int, n_all: int):
+    """The oracle, as it stands, on bounded samples of the same workload: the
+    plain build on one thread, and the same source built for all host cores
+    (OpenMP, GNU parallel-mode sort) on the threads OpenMP takes."""
     import oracle
     from paper_2104_00792_amd import inputs
 
-    keys, queries, opts = inputs.make_workload(workload, n=n_sample)
-    t0 = time.perf_counter()
-    oracle.build_table(keys, P=opts["P"], num=opts["num"], den=opts["den"])
-    oracle.count(keys, queries)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"{workload} recipe at n=q={n_sample}: oracle build (sort of (p,b,key) tuples + "
-                      f"run-length) + oracle count (sorted copy + equal_range), single thread, "
-                      f"{dt:.1f} s"}
+    def run(n):
+        keys, queries, opts = inputs.make_workload(workload, n=n)
+        t0 = time.perf_counter()
+        oracle.build_table(keys, P=opts["P"], num=opts["num"], den=opts["den"])
+        oracle.count(keys, queries)
+        return time.perf_counter() - t0
+
+    dt1 = run(n_one)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    with oracle.all_cores(threads):
+        dt_all = run(n_all)
+    what = ("oracle build (sort of (p,b,key) tuples + run-length) + oracle count (sorted copy + "
+            "equal_range)")
+    return {"value": n_all / dt_all, "unit": "keys/s", "cores": threads, "kind": "oracle",
+            "sample": f"{workload} recipe at n=q={n_all}: {what}, all-core build of the oracle on {threads} "
+                      f"threads, {dt_all:.1f} s",
+            "single_thread": {"value": n_one / dt1, "unit": "keys/s", "cores": 1,
+                              "sample": f"same recipe at n=q={n_one}, single thread, {dt1:.1f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def full_size_parity(workload: str, table, counts) -> dict | None:
+    """Compare one step's outputs with the digests of the oracle's outputs
+    at this workload's full size (tests/golden/fullsize_digests.json,
+    written from the oracle alone).  None when no digest exists for it."""
+    import importlib.util
+
+    path = os.path.join(ROOT, "tests", "golden", "fullsize.py")
+    spec = importlib.util.spec_from_file_location("fullsize", path)
+    fs = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fs)
+    want = fs.load().get(workload)
+    if want is None or want["inputs"]["n"] != table.n or want["inputs"]["q"] != counts.numel():
+        return None
+    po, bb, offs, tk = table.export()
+    got = fs.digest(po.cpu().numpy(), bb.cpu().numpy(), offs.cpu().numpy(), tk.cpu().numpy(),
+                    counts.cpu().numpy())
+    fields = fs.compare(got, want)
+    return {"match": all(fields.values()), "fields": fields,
+            "against": "digests of the oracle's outputs at full size (offsets and counts bit for bit, "
+                       "bucket contents as an order-free multiset hash), tests/golden/fullsize_digests.json"}
 
 
 def main():
@@ -143,7 +253,9 @@ def main():
     ap.add_argument("--workload", default="p16_u32_2^28", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--n", type=int, default=None, help="override the key count (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
+    ap.add_argument("--no-parity", action="store_true", help="skip the full-size parity check")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="keys of the single-thread oracle sample")
+    ap.add_argument("--cpu-sample-all", type=int, default=1 << 26, help="keys of the all-core oracle sample")
     ap.add_argument("--requests", type=int, default=100000, help="serving: requests in the stream")
     ap.add_argument("--tables", type=int, default=4096, help="batched: number of tables")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -191,7 +303,8 @@ def main():
         step()
     torch.cuda.synchronize()
     t_probe = hg.hg_build(keys, P=opts["P"], ratio=(opts["num"], opts["den"]))
-    B = t_probe.info()["num_buckets"]
+    info = t_probe.info()
+    B = info["num_buckets"]
     ws, tb = hg.hg_workspace_size(hg.HG_OP_BUILD, n=n, key_type=0 if ks == 4 else 1, P=opts["P"],
                                   ratio=(opts["num"], opts["den"]))
     wq, _ = hg.hg_workspace_size(hg.HG_OP_COUNT, n=q, table=t_probe)
@@ -199,11 +312,20 @@ def main():
 
     log(f"timing {args.steps} steps")
     sizes = dict(n=n, q=q, B=B, ks=ks, P=opts["P"])
-    sec, kernels, roof = timed_with_roofline(hg, step, args.steps, sizes, args.workload)
+    sec, kernels, roof = timed_with_roofline(hg, step, args.steps, sizes, args.workload,
+                                             cb=info["probe_count_bytes"])
     ms_per_step = sec * 1000.0
     value = n / sec
     log("graph replays")
     graph = graph_timing(step, ws + tb + wq, counts, args.steps)
+    parity = None
+    if not args.no_parity:
+        log("full-size parity against the oracle's digests")
+        t_chk = hg.hg_build(keys, P=opts["P"], ratio=(opts["num"], opts["den"]))
+        hg.hg_count(t_chk, queries, out=counts)
+        torch.cuda.synchronize()
+        parity = full_size_parity(args.workload, t_chk, counts)
+        t_chk.free()
 
     result = {
         "metric": METRIC,
@@ -224,6 +346,8 @@ def main():
         "graph": dict(graph, keys_per_s=n / (graph["ms_per_step"] / 1000.0)),
         "kernels": kernels,
     }
+    if parity is not None:
+        result["parity"] = parity
     if args.calibrate_copy:
         src = torch.ones(1 << 26, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
@@ -232,36 +356,59 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        log(f"cpu baseline on a sample of {args.cpu_sample}")
-        result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
+        log(f"cpu baseline on samples of {args.cpu_sample} (one thread) and {args.cpu_sample_all} (all cores)")
+        result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_sample_all)
     print(json.dumps(result), flush=True)
 
 
-def timed_with_roofline(hg, step, steps: int, sizes: dict, workload: str):
+def timed_with_roofline(hg, step, steps: int, sizes: dict, workload: str, cb: int = 4):
     """Per-kernel table from one pass with every launch bracketed by HIP
     events; then the timed pass, with events around the dominant kernel's
     launches only (the events of the other launches cost the step about
-    3%).  Returns (seconds per step, kernel table, roofline entry); the
-    roofline's `achieved` comes from the dominant kernel's events of the
-    timed pass."""
+    3%).  Returns (seconds per step, kernel table, roofline entry).
+
+    The dominant kernel is the slowest one that carries out a step of the
+    scope table's model; `achieved` is that step's model bytes per launch
+    (survey_bytes) over the kernel's average launch time in the timed pass.
+    `kernel_model` gives the same kernel's rate under this design's own
+    bytes (algorithmic_bytes), and `step` the whole step against the
+    model's bytes per step, with the counter total of the committed
+    profile beside it when that profile matches the kernel sources."""
     with hg.profile() as prof_all:
         timed(step, steps, 0)
-    kernels = kernel_table(prof_all.results, steps, sizes)
-    dom = max((k for k in kernels if algorithmic_bytes(k, **sizes) > 0), key=lambda k: kernels[k]["ms_per_step"])
+    kernels = kernel_table(prof_all.results, steps, sizes, cb)
+    dom = max((k for k in kernels if survey_bytes(k, **sizes) > 0), key=lambda k: kernels[k]["ms_per_step"])
     with hg.profile(only=dom) as prof:
         sec = timed(step, steps, 0)
     launches, total_ms = prof.results[dom]
-    achieved = algorithmic_bytes(dom, **sizes) / (total_ms / launches / 1000.0) / 1e9
+    avg_s = total_ms / launches / 1000.0
+    achieved = survey_bytes(dom, **sizes) / avg_s / 1e9
+    own = algorithmic_bytes(dom, **sizes, cb=cb) / avg_s / 1e9
+    step_bytes = survey_step_bytes(**sizes)
+    step_gbs = step_bytes / sec / 1e9
+    vals = read_traffic_file(workload)
+    counter = float(vals["hbm_bytes_per_step"]) if vals and "hbm_bytes_per_step" in vals else None
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(workload, dom)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(workload, dom),
+            "traffic_scale": ({"fetch": float(vals["fetch_scale"]), "write": float(vals["write_scale"])}
+                              if vals else None),
+            "kernel_model": {"bytes_per_launch": algorithmic_bytes(dom, **sizes, cb=cb), "achieved": round(own, 1),
+                             "frac": round(own / HBM_PEAK_GBS, 4)},
+            "step": {"alg_bytes": step_bytes, "alg_bytes_per_pair": round(step_bytes / sizes["n"], 2),
+                     "achieved": round(step_gbs, 1), "frac": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "counter_bytes": counter,
+                     "counter_achieved": round(counter / sec / 1e9, 1) if counter else None,
+                     "counter_frac": round(counter / sec / 1e9 / HBM_PEAK_GBS, 4) if counter else None,
+                     "design_bytes": sum(algorithmic_bytes(k, **sizes, cb=cb) * v["launches_per_step"]
+                                         for k, v in kernels.items())}}
     return sec, kernels, roof
 
 
-def kernel_table(prof_results: dict, steps: int, sizes: dict) -> dict:
+def kernel_table(prof_results: dict, steps: int, sizes: dict, cb: int = 4) -> dict:
     out = {}
     for name, (launches, total_ms) in prof_results.items():
         avg = total_ms / launches
-        ab = algorithmic_bytes(name, **sizes)
+        ab = algorithmic_bytes(name, **sizes, cb=cb)
         out[name] = {"launches_per_step": launches // steps, "avg_ms": round(avg, 5),
                      "ms_per_step": round(total_ms / steps, 5),
                      "alg_GBs": round(ab / (avg / 1000.0) / 1e9, 1) if avg > 0 and ab else None}

@@ -116,6 +116,11 @@ typedef struct hg_table_desc {
   const uint32_t* d_offsets;      /* B + 1                                  */
   const uint32_t* d_part_offsets; /* P + 1                                  */
   const uint32_t* d_bucket_base;  /* P + 1                                  */
+  uint32_t probe_count_bytes;     /* width of the counts that a sorted probe
+                                     passes between its kernels: 1 when no
+                                     bucket holds more than 64 keys (no key
+                                     then occurs more often), else 4        */
+  uint32_t reserved;
 } hg_table_desc;
 
 /* hg_build -- build a static table from all n keys (Algorithm 1; with
@@ -270,9 +275,10 @@ hg_status hg_hash_bucket(const void* d_keys, uint64_t n, hg_key_type kt,
                          uint64_t V, uint64_t* d_hash, uint32_t* d_bucket,
                          hipStream_t stream);
 
-/* hg_table_info -- fill *desc.  Reading num_buckets waits for the table's
- * build to finish (it is computed on the device); the other fields do not
- * wait.  The device pointers stay owned by the table. */
+/* hg_table_info -- fill *desc.  Reading num_buckets and probe_count_bytes
+ * waits for the table's build to finish (both are computed on the device);
+ * the other fields do not wait.  The device pointers stay owned by the
+ * table. */
 hg_status hg_table_info(const hg_table* table, hg_table_desc* desc);
 
 /* hg_table_export -- copy the table's arrays into caller-owned device

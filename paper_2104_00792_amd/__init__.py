@@ -82,6 +82,8 @@ class _TableDesc(ctypes.Structure):
         ("d_offsets", ctypes.c_void_p),
         ("d_part_offsets", ctypes.c_void_p),
         ("d_bucket_base", ctypes.c_void_p),
+        ("probe_count_bytes", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -225,7 +227,8 @@ class Table:
         _check(lib().hg_table_info(self.handle, ctypes.byref(d)), "hg_table_info")
         return {"n": d.n, "num_buckets": d.num_buckets, "P": d.P, "key_type": d.key_type,
                 "d_keys": d.d_keys, "d_offsets": d.d_offsets,
-                "d_part_offsets": d.d_part_offsets, "d_bucket_base": d.d_bucket_base}
+                "d_part_offsets": d.d_part_offsets, "d_bucket_base": d.d_bucket_base,
+                "probe_count_bytes": d.probe_count_bytes}
 
     def export(self, stream=None):
         """Device copies of (part_offsets, bucket_base, offsets, keys)."""

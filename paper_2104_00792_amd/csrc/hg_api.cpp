@@ -46,7 +46,7 @@ struct hg_table {
   uint32_t* d_part_offsets; // P + 1
   uint32_t* d_bucket_base;  // P + 1
   hg::PartDesc* d_desc;     // P
-  uint32_t* d_unsorted;     // 1 + kMaxUnsorted: long buckets left unsorted
+  uint32_t* d_unsorted;     // kUnsortedWords: long buckets left unsorted, has-long word
   int split_mode;           // level-1 split: 0 by partition, 1 by coarse bucket range
   uint32_t sh1;             // coarse range 2^sh1 buckets (mode 1)
   uint32_t nd1;             // level-1 digits
@@ -58,6 +58,7 @@ struct hg_table {
   std::mutex mu;
   bool have_num_buckets;
   uint64_t num_buckets;
+  uint32_t has_long;  // read with num_buckets
 };
 
 namespace {
@@ -599,12 +600,15 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q, t->log2P, t->P, t->d_desc,
                                  t->d_offsets, t->d_keys, t->d_unsorted, log2W, static_cast<uint32_t*>(qv), c2, s));
   // The level-1 buffer is dead once the level-2 split has read it: it takes
-  // the counts in level-1 order (q words fit in q keys).
+  // the counts in level-1 order (q words fit in q keys).  Counts travel as
+  // bytes between these kernels when the table has no long bucket.
   uint32_t* c1 = static_cast<uint32_t*>(w.buf1);
   HG_LAUNCH("qgather2", s,
-            hg::launch_tile_gather(kt, 2, perm2, c2, q, w.max_tiles2, w.plan, 0, w.counts2, c1, false, s));
+            hg::launch_tile_gather(kt, 2, perm2, c2, q, w.max_tiles2, w.plan, 0, w.counts2, t->d_unsorted, c1,
+                                   hg::GATHER_STAGE, s));
   HG_LAUNCH("qgather1", s,
-            hg::launch_tile_gather(kt, 1, perm1, c1, q, 0, nullptr, sp.nd1, w.counts1, out, !count, s));
+            hg::launch_tile_gather(kt, 1, perm1, c1, q, 0, nullptr, sp.nd1, w.counts1, t->d_unsorted, out,
+                                   count ? hg::GATHER_COUNT : hg::GATHER_FOUND, s));
   return HG_OK;
 }
 
@@ -713,7 +717,8 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
                                  t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound),
                                  static_cast<uint32_t*>(qv), c2, s));
   HG_LAUNCH("bqgather", s,
-            hg::launch_tile_gather(kt, 2, perm, c2, q32, w.max_tiles2, w.plan, 0, w.counts2, d_out, !count, s));
+            hg::launch_tile_gather(kt, 2, perm, c2, q32, w.max_tiles2, w.plan, 0, w.counts2, t->d_unsorted, d_out,
+                                   count ? hg::GATHER_COUNT : hg::GATHER_FOUND, s));
   return HG_OK;
 }
 
@@ -767,7 +772,7 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
   Allocs mem(stream);
   void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr;
   const size_t meta_bytes =
-      2 * sizeof(uint32_t) * (P + 1) + 8 + sizeof(hg::PartDesc) * P + sizeof(uint32_t) * (1 + hg::kMaxUnsorted);
+      2 * sizeof(uint32_t) * (P + 1) + 8 + sizeof(hg::PartDesc) * P + sizeof(uint32_t) * hg::kUnsortedWords;
   HG_TRY(mem.get(&keys_out, n * ks), "allocate table keys");
   HG_TRY(mem.get(&offsets, (bound + 1) * sizeof(uint32_t)), "allocate table offsets");
   HG_TRY(mem.get(&meta, meta_bytes), "allocate table metadata");
@@ -856,6 +861,7 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
   t->like_id = like != nullptr ? like->id : 0;
   t->have_num_buckets = false;
   t->num_buckets = 0;
+  t->has_long = 0;
   t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
   *out = t;
   return HG_OK;
@@ -940,7 +946,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   void *keys_out = nullptr, *offsets = nullptr, *meta = nullptr, *longv = nullptr;
   const size_t meta_bytes =
       2 * sizeof(uint32_t) * (static_cast<size_t>(T) + 1) + 8 + sizeof(hg::PartDesc) * T +
-      sizeof(uint32_t) * (1 + hg::kMaxUnsorted);
+      sizeof(uint32_t) * hg::kUnsortedWords;
   HG_TRY(mem.get(&keys_out, std::max<uint64_t>(n, 1) * ks), "allocate table keys");
   HG_TRY(mem.get(&offsets, (bound + 1) * sizeof(uint32_t)), "allocate table offsets");
   HG_TRY(mem.get(&meta, meta_bytes), "allocate table metadata");
@@ -1010,6 +1016,7 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   t->like_id = 0;
   t->have_num_buckets = false;
   t->num_buckets = 0;
+  t->has_long = 0;
   t->blocks = {mem.release(keys_out), mem.release(offsets), mem.release(meta)};
   *out = t;
   return HG_OK;
@@ -1188,11 +1195,14 @@ hg_status hg_table_info(const hg_table* table, hg_table_desc* desc) {
   {
     std::lock_guard<std::mutex> lk(t->mu);
     if (!t->have_num_buckets) {
-      uint32_t nb = 0;
+      uint32_t nb = 0, hl = 0;
       HG_TRY(hipMemcpyAsync(&nb, t->d_bucket_base + t->P, sizeof(nb), hipMemcpyDeviceToHost, t->stream),
              "read bucket count");
+      HG_TRY(hipMemcpyAsync(&hl, t->d_unsorted + hg::kHasLongWord, sizeof(hl), hipMemcpyDeviceToHost, t->stream),
+             "read long-bucket word");
       HG_TRY(hipStreamSynchronize(t->stream), "wait for build");
       t->num_buckets = nb;
+      t->has_long = hl;
       t->have_num_buckets = true;
     }
   }
@@ -1204,6 +1214,8 @@ hg_status hg_table_info(const hg_table* table, hg_table_desc* desc) {
   desc->d_offsets = t->d_offsets;
   desc->d_part_offsets = t->d_part_offsets;
   desc->d_bucket_base = t->d_bucket_base;
+  desc->probe_count_bytes = t->has_long ? 4u : 1u;
+  desc->reserved = 0;
   return HG_OK;
 }
 

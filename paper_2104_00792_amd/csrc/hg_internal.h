@@ -44,6 +44,14 @@ constexpr uint32_t kProbeKeyCapBytes = 40 * 1024;  // table keys of one window i
 // long bucket is scanned).
 constexpr uint32_t kLongT = 64;
 constexpr uint32_t kMaxUnsorted = 256;
+// The table's `unsorted` block also holds, after the ids, one word that the
+// long-bucket pass sets to 1 when the table has any long bucket, else 0.
+// Without long buckets no key occurs more than kLongT times, so a sorted
+// probe carries its counts between kernels as bytes (launch_lds_probe,
+// launch_tile_gather).
+constexpr uint32_t kUnsortedWords = 2 + kMaxUnsorted;
+constexpr uint32_t kHasLongWord = 1 + kMaxUnsorted;
+static_assert(kLongT < 256, "a count of a table without long buckets fits a byte");
 // Long buckets of at most kWaveLong keys are sorted by one wave each, longer
 // ones by a workgroup.  Their ids share one list (the short ones from the
 // front, the others from the back) of long_list_cap(n) entries, after
@@ -138,9 +146,14 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 // Inverse of a split (same level, tiles, plan and scanned counts) applied to
 // u32 values: out[i] = src[position of key i after the split], or that value
 // != 0 as bytes.  perm as written by the split's SCATTER.
-hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const uint32_t* src, uint32_t n,
-                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan, void* out,
-                              bool found, hipStream_t s);
+// out_kind: GATHER_STAGE writes the values in the width they came in (bytes
+// when the table has no long bucket, see kHasLongWord; else u32), for a
+// further gather; GATHER_COUNT writes u32 counts, GATHER_FOUND bytes 0/1.
+// `unsorted` is the table's block that holds the long-bucket word.
+enum GatherOut { GATHER_STAGE = 0, GATHER_COUNT = 1, GATHER_FOUND = 2 };
+hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const void* src, uint32_t n,
+                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan,
+                              const uint32_t* unsorted, void* out, int out_kind, hipStream_t s);
 
 // Count-balanced ranges (Algorithm 2, Phase 1): kMaxBins bins at most.
 constexpr uint32_t kMaxBins = 1u << 14;
@@ -189,14 +202,15 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
 
 // Queries of one sub-bin, at most probe_chunk_keys() per workgroup (a
 // sub-bin with more is shared through a queue): windows of 2^log2W buckets
-// of the table (offsets and keys) in LDS; counts in the split order.
+// of the table (offsets and keys) in LDS; counts in the split order, as
+// bytes when the table has no long bucket (kHasLongWord), else as u32.
 // Workspace: queue[1 + 2 * (q / probe_chunk_keys() + 1)].
 constexpr int kProbeReg = 20;
 uint32_t probe_chunk_keys();
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
                             uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
-                            uint32_t* queue, uint32_t* c2, hipStream_t s);
+                            uint32_t* queue, void* c2, hipStream_t s);
 
 // kt: 0 = 32-bit keys, 1 = 64-bit keys.
 hipError_t launch_fill_u32(uint32_t* p, uint64_t len, uint32_t value, hipStream_t s);

@@ -317,20 +317,24 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   }
 }
 
-// The inverse of a split applied to per-key values (u32), one split tile per
+// The inverse of a split applied to per-key counts, one split tile per
 // workgroup, on the tiles of the split itself: the tile's digit runs of
 // `src` (split order; run of digit d at the scanned count of (d, tile), its
 // length up to the next entry) are copied into LDS in the tile's digit order,
-// then out[i] = stage[perm[i]] for the tile's keys in input order, or
-// (stage[perm[i]] != 0) as bytes.  Every global access reads or writes
-// consecutive elements: a run, the slots, the output.
-template <int THREADS, int ITEMS, int MAXD, bool FOUND>
+// then out[i] = stage[perm[i]] for the tile's keys in input order: in the
+// width they came in (OUT == GATHER_STAGE), as u32 (GATHER_COUNT), or as
+// (stage[perm[i]] != 0) bytes (GATHER_FOUND).  The counts come as bytes when
+// the table has no long bucket, else as u32.  Every global access reads or
+// writes consecutive elements: a run, the slots, the output.
+template <int THREADS, int ITEMS, int MAXD, int OUT>
 __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gather(
-    const uint16_t* __restrict__ perm, const uint32_t* __restrict__ src, uint32_t n,
-    const SegPlan* __restrict__ plan, uint32_t nd, const uint32_t* __restrict__ scan, void* __restrict__ out) {
+    const uint16_t* __restrict__ perm, const void* __restrict__ src, uint32_t n,
+    const SegPlan* __restrict__ plan, uint32_t nd, const uint32_t* __restrict__ scan,
+    const uint32_t* __restrict__ unsorted, void* __restrict__ out) {
   constexpr int TILE = THREADS * ITEMS;
   constexpr int kDPT = (MAXD + THREADS - 1) / THREADS;
   constexpr int kW = THREADS / kWave;
+  constexpr bool FOUND = OUT == GATHER_FOUND;
   static_assert(ITEMS % 4 == 0, "four slots per 8-byte load");
   __shared__ uint32_t dstart[MAXD + 1];
   __shared__ uint32_t delta[MAXD];  // src index of a slot minus the slot
@@ -342,10 +346,13 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
   if (!tile_loc(plan, nd, n, TILE, L)) return;  // whole workgroup
   const uint32_t cnt = L.tail - L.head;         // at least 1: a tile holds keys
   const uint32_t first = L.base + L.head;       // input order: elements first + e, e < cnt
-  const uintptr_t oa = FOUND ? reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + first)
-                             : reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + first);
+  // Counts as bytes in src, and in out for a further gather.
+  const bool narrow = unsorted[kHasLongWord] == 0;
+  const bool out_bytes = FOUND || (OUT == GATHER_STAGE && narrow);
+  const uintptr_t oa = out_bytes ? reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + first)
+                                 : reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + first);
   const bool vec = cnt == static_cast<uint32_t>(TILE) && (first & 3u) == 0 &&
-                   (reinterpret_cast<uintptr_t>(perm + first) & 7u) == 0 && (oa & (FOUND ? 3u : 15u)) == 0;
+                   (reinterpret_cast<uintptr_t>(perm + first) & 7u) == 0 && (oa & (out_bytes ? 3u : 15u)) == 0;
 
   // The slots of the tile's keys (input order) are needed last but depend on
   // nothing: they are requested first, four per thread and load.
@@ -405,8 +412,13 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
     const uint32_t j = min(static_cast<uint32_t>(i) * THREADS + t, cnt - 1);
     v[i] = delta[sdg[j]] + j;
   }
+  if (narrow) {
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) v[i] = src[v[i]];
+    for (int i = 0; i < ITEMS; ++i) v[i] = static_cast<const uint8_t*>(src)[v[i]];
+  } else {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) v[i] = static_cast<const uint32_t*>(src)[v[i]];
+  }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t j = static_cast<uint32_t>(i) * THREADS + t;
@@ -424,6 +436,8 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
       if (FOUND)
         *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + e) =
             (a != 0 ? 1u : 0u) | (b != 0 ? 0x100u : 0u) | (cc != 0 ? 0x10000u : 0u) | (dd != 0 ? 0x1000000u : 0u);
+      else if (out_bytes)  // byte counts below 256
+        *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(out) + e) = a | (b << 8) | (cc << 16) | (dd << 24);
       else
         *reinterpret_cast<uint4*>(static_cast<uint32_t*>(out) + e) = make_uint4(a, b, cc, dd);
     }
@@ -433,6 +447,8 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
     const uint32_t x = stage[perm[first + e]];
     if (FOUND)
       static_cast<uint8_t*>(out)[first + e] = x != 0 ? 1 : 0;
+    else if (out_bytes)
+      static_cast<uint8_t*>(out)[first + e] = static_cast<uint8_t>(x);
     else
       static_cast<uint32_t*>(out)[first + e] = x;
   }
@@ -1282,7 +1298,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
                                                              const K* __restrict__ tkeys,
                                                              const uint32_t* __restrict__ unsorted, uint32_t log2W,
                                                              uint32_t* __restrict__ queue, bool from_queue,
-                                                             uint32_t* __restrict__ c2) {
+                                                             void* __restrict__ c2v) {
   constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);  // keys in LDS at the largest window
   __shared__ __align__(16) uint32_t sbuf[kProbeLdsWords];
   static_assert((kProbeLdsWords - kProbeOffWords) * 4 / sizeof(K) - 4 >= KCAP, "the largest window keeps KCAP keys");
@@ -1317,6 +1333,11 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   const uint32_t R = sb.gB - sb.gA, m = min(CH, sb.kB - qa);
   const uint32_t Wb = 1u << log2W;
   const uint32_t nuns = unsorted[0];
+  // Counts leave as bytes when the table has no long bucket (every count is
+  // then at most kLongT), else as u32.
+  const bool narrow = unsorted[kHasLongWord] == 0;
+  uint8_t* const c2b = static_cast<uint8_t*>(c2v);
+  uint32_t* const c2 = static_cast<uint32_t*>(c2v);
   // Keys at the block's start (a fixed address, as the counting loops read
   // them), offsets at its end.
   const uint32_t off_words = (Wb + 4) & ~3u;  // log2W <= kMaxLog2W: at most kProbeOffWords
@@ -1517,7 +1538,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
               last_q = qv[u];
               have = true;
             }
-            c2[qa + e] = last_c;
+            if (narrow)
+              c2b[qa + e] = static_cast<uint8_t>(last_c);
+            else
+              c2[qa + e] = last_c;
           }
         }
         c0 += THREADS * kUQ;
@@ -1593,7 +1617,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
           const uint32_t lo = offsets[g], hi = offsets[g + 1];
           c = count_equal(tkeys, lo, hi, qv[j], long_bucket_sorted(unsorted, nuns, g, kMaxUnsorted));
         }
-        c2[qa + e] = c;
+        if (narrow)
+          c2b[qa + e] = static_cast<uint8_t>(c);
+        else
+          c2[qa + e] = c;
       }
     }
   }
@@ -1821,13 +1848,17 @@ BigWork<K> big_work(uint32_t* base, uint64_t n) {
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_long_small(const uint32_t* __restrict__ offsets,
                                                              uint32_t* __restrict__ ctr, uint32_t* __restrict__ list,
-                                                             K* __restrict__ keys) {
+                                                             K* __restrict__ keys, uint32_t* __restrict__ unsorted) {
   constexpr int W = kLongThreads / kWave;
   __shared__ K sval[W][kSetMax];
   __shared__ uint32_t scnt[W][kSetMax];
   __shared__ uint32_t ssize[W];
   const uint32_t w = threadIdx.x / kWave, l = lane_id();
   const uint32_t total = ctr[0];
+  // Whether the table has a long bucket: some bucket was listed, at the
+  // front (ctr[0], not changed here) or at the back (ctr[2], which this
+  // kernel only raises, and only when ctr[0] is nonzero).
+  if (blockIdx.x == 0 && threadIdx.x == 0) unsorted[kHasLongWord] = (total | ctr[2]) != 0 ? 1u : 0u;
   // Wave i takes list entries i, i + (waves in the grid), ...: no claims
   // through a shared counter (the buckets are at most kWaveLong keys, so a
   // fixed deal stays balanced).  The loop is uniform over the wave.
@@ -2133,28 +2164,36 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
 }
 
 template <int THREADS, int ITEMS, int MAXD>
-hipError_t tile_gather(dim3 grid, const uint16_t* perm, const uint32_t* src, uint32_t n, const SegPlan* plan,
-                       uint32_t nd, const uint32_t* scan, void* out, bool found, hipStream_t s) {
-  if (found)
-    k_tile_gather<THREADS, ITEMS, MAXD, true><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan, out);
+hipError_t tile_gather(dim3 grid, const uint16_t* perm, const void* src, uint32_t n, const SegPlan* plan,
+                       uint32_t nd, const uint32_t* scan, const uint32_t* unsorted, void* out, int out_kind,
+                       hipStream_t s) {
+  if (out_kind == GATHER_FOUND)
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_FOUND><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                              unsorted, out);
+  else if (out_kind == GATHER_COUNT)
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_COUNT><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                              unsorted, out);
   else
-    k_tile_gather<THREADS, ITEMS, MAXD, false><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan, out);
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_STAGE><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                              unsorted, out);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const uint32_t* src, uint32_t n,
-                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan, void* out,
-                              bool found, hipStream_t s) {
+hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const void* src, uint32_t n,
+                              uint32_t max_tiles, const SegPlan* plan, uint32_t nd, const uint32_t* scan,
+                              const uint32_t* unsorted, void* out, int out_kind, hipStream_t s) {
   if (level == 1) {
     const uint32_t tiles = div_up(n, kL1Tile);
     if (tiles == 0) return hipSuccess;
     if (nd > 256) return hipErrorInvalidValue;
-    return tile_gather<kL1Tile / 8, 8, 256>(dim3(tiles), perm, src, n, nullptr, nd, scan, out, found, s);
+    return tile_gather<kL1Tile / 8, 8, 256>(dim3(tiles), perm, src, n, nullptr, nd, scan, unsorted, out, out_kind,
+                                            s);
   }
   if (max_tiles == 0) return hipSuccess;
   if (kt == 0)
-    return tile_gather<kL2Threads, 8, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, out, found, s);
-  return tile_gather<kL2Threads, 4, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, out, found, s);
+    return tile_gather<kL2Threads, 8, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out, out_kind,
+                                              s);
+  return tile_gather<kL2Threads, 4, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out, out_kind, s);
 }
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
@@ -2222,7 +2261,7 @@ uint32_t probe_chunk_keys() { return kLdsThreads * kProbeReg; }
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
                             uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
-                            uint32_t* queue, uint32_t* c2, hipStream_t s) {
+                            uint32_t* queue, void* c2, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   const uint32_t max_queued = q / probe_chunk_keys() + 1;
   hipError_t e = launch_fill_u32(queue, 1, 0u, s);
@@ -2258,7 +2297,7 @@ hipError_t long_sort_typed(const uint32_t* offsets, uint32_t* ctr, uint32_t* lis
   const BigWork<K> bw = big_work<K>(big, n);
   hipError_t e = launch_fill_u32(bw.ctr, 2, 0u, s);
   if (e != hipSuccess) return e;
-  k_long_small<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys);
+  k_long_small<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted, bw);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -45,6 +45,37 @@ def test_headline_step_moves_104_bytes_per_key_and_query():
     assert total == 104 * n
 
 
+def test_narrow_counts_take_92_bytes_per_pair():
+    """Without long buckets the probe passes its counts as bytes: the probe
+    writes 1 B instead of 4, the level-2 gather moves 2 + 1 + 1, the last
+    gather 2 + 1 + 4."""
+    n = q = B = 1 << 28
+    launches = ["part_count", "split1_count", "split1_scatter", "split2_count", "split2_scatter", "lds_build",
+                "qsplit1_count", "qsplit1_scatter", "qsplit2_count", "qsplit2_scatter", "lds_probe", "qgather2",
+                "qgather1"]
+    assert sum(bench.algorithmic_bytes(k, n, q, B, 4, 16, cb=1) for k in launches) == 92 * n
+    assert bench.algorithmic_bytes("qgather2", n, q, B, 4, 16, cb=1) == 4 * q
+    assert bench.algorithmic_bytes("qgather1", n, q, B, 4, 16, cb=1) == 7 * q
+
+
+@pytest.mark.parametrize("P, per_pair", [(16, 60), (1, 48)])
+def test_model_bytes_per_step_and_per_kernel(P, per_pair):
+    """The scope table's model: 28 B per key (partition count 4, scatter 8,
+    local histogram 4, offsets 4, local scatter 8) + 32 B per query for the
+    partitioned build; 16 + 32 for a plain table.  The per-kernel charges
+    add up to the step's bytes, and the dominant probe pass is charged
+    8 B per query."""
+    n = q = B = 1 << 24
+    launches = ["part_count", "split1_count", "split1_scatter", "split2_count", "split2_scatter", "lds_build",
+                "qsplit1_count", "qsplit1_scatter", "qsplit2_count", "qsplit2_scatter", "lds_probe", "qgather2",
+                "qgather1"]
+    assert bench.survey_step_bytes(n, q, B, 4, P) == per_pair * n
+    assert sum(bench.survey_bytes(k, n, q, B, 4, P) for k in launches) == per_pair * n
+    assert bench.survey_bytes("lds_probe", n, q, B, 4, P) == 8 * q
+    # 64-bit keys, V = n / 2 (the Zipf workload): 8 + 2 + 16 per key, 52 per query
+    assert bench.survey_step_bytes(n, q, n // 2, 8, 1) == 78 * n
+
+
 def test_traffic_is_read_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.read_traffic("w", "lds_probe") is None  # no summary at all

@@ -374,6 +374,30 @@ def test_heavy_subbins_shared_by_workgroups(gpu, dtype, P):
     check_table(gpu, keys, P=P, queries=queries, build="sorted")
 
 
+@pytest.mark.parametrize("copies, width", [(64, 1), (65, 4)])
+def test_probe_count_width_at_the_long_bucket_threshold(gpu, copies, width):
+    """A key repeated `copies` times in a table whose other keys avoid its
+    bucket: with 64 copies no bucket is long, the table reports 1-byte probe
+    counts and the count 64 passes through them exactly; with 65 the bucket
+    is long and the counts are 4 bytes wide.  Both probes give the oracle's
+    counts."""
+    n = 1 << 20
+    x = np.uint32(0x1234567)
+    _, bx = oracle.hash_bucket(np.array([x], np.uint32), n)
+    base = make_keys("uniform", n + 4096, np.uint32, 91)
+    _, b = oracle.hash_bucket(base, n)
+    base = base[(b != bx[0]) & (base != x)][: n - copies]
+    keys = np.concatenate([base, np.full(copies, x, np.uint32)])
+    keys = keys[inputs.uniform_u32(keys.size, 92).argsort(kind="stable")]
+    ref = oracle.build_table(keys, V=n)
+    assert int(np.diff(ref["offsets"].astype(np.int64)).max()) == copies
+    t = gpu.hg_build(to_dev(keys), num_buckets=n, flags=BUILDS["sorted"])
+    assert t.info()["probe_count_bytes"] == width
+    t.free()
+    queries = np.concatenate([np.full(100, x, np.uint32), inputs.queries_hit50(keys, 1 << 20, 93)])
+    check_table(gpu, keys, V=n, queries=queries)
+
+
 def test_trim_pool_keeps_tables_valid(gpu):
     """Trimming the library's pool hands back only memory no table holds."""
     import torch
