@@ -38,6 +38,8 @@ DESCRIPTIONS = {
     "batched_u32_4096": "4096 uint32 tables, sizes log-uniform in [2^10, 2^20] (622M keys), per-table seeds, "
                         "V_t = n_t; each probed by n_t queries at 50% hit; one hg_build_batched + "
                         "hg_count_batched per step",
+    "copy_ceiling": "device-to-device streaming ceilings of the GPU with torch's own kernels: copy, fill and a "
+                    "read-only sum over 1 GiB buffers (HIP events around each launch)",
     "serving": "Poisson stream of requests, 30% builds (uint32, sizes log-uniform in [2^10, 2^24]) and 70% probes "
                "(sizes log-uniform in [2^8, 2^22], 50% hits) against earlier tables; 200 GB HBM cap with LRU "
                "eviction; 4 concurrent slots; open loop at 0.8 of the closed-loop capacity",
@@ -283,6 +285,8 @@ def main():
         return run_batched(args, dev)
     if args.workload == "serving":
         return run_serving(args, dev)
+    if args.workload == "copy_ceiling":
+        return run_ceiling(args, dev)
 
     w = inputs.WORKLOADS[args.workload]
     n = w["n"] if args.n is None else args.n
@@ -525,6 +529,40 @@ def run_batched(args, dev):
         "kernels": kernels,
     }
     print(json.dumps(result), flush=True)
+
+
+def run_ceiling(args, dev):
+    """What plain streaming reaches on this GPU: torch's copy (read + write),
+    fill (write) and sum (read) of 1 GiB, each timed with HIP events over
+    `steps` launches after one warm-up."""
+    import torch
+
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    out = torch.empty((), dtype=torch.int64, device=dev)
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        return {"ms": round(ms, 4), "GBs": round(moved / (ms / 1000.0) / 1e9, 1),
+                "frac_of_peak": round(moved / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    res = {"copy": rate(lambda: b.copy_(a), 2 * nbytes), "fill": rate(lambda: b.fill_(7), nbytes),
+           "read_sum": rate(lambda: torch.sum(a, 0, dtype=torch.int64, out=out), nbytes)}
+    best = max(v["GBs"] for v in res.values())
+    print(json.dumps({"metric": "streaming ceiling GB/s", "value": best, "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": 1, "ms_per_step": res["copy"]["ms"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+                      "config": {"workload": f"copy_ceiling: {DESCRIPTIONS['copy_ceiling']}", "bytes": nbytes},
+                      "ceilings": res, "peak": HBM_PEAK_GBS}), flush=True)
 
 
 def run_serving(args, dev):
