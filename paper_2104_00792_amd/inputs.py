@@ -182,6 +182,43 @@ def queries_hit50_t(keys, q: int, seed: int, device):
     return torch.where(hit, picked, miss.view(torch.int64)).view(torch.uint64)
 
 
+def table_queries_t(table_n: int, table_seed: int, q: int, seed: int, device):
+    """queries_hit50_t over the keys uniform_u32_t(table_n, table_seed),
+    without drawing that key array: a hit at position p takes key p of the
+    table's stream directly (the streams are counter-based)."""
+    import torch
+
+    wa = splitmix64_t(seed, 0, q, device, step=2, offset=0)
+    wb = splitmix64_t(seed, 0, q, device, step=2, offset=1)
+    miss = _to_u32(wb)
+    if table_n == 0:
+        return miss
+    pos = _lsr((wa & 0xFFFFFFFF) * table_n, 32)
+    picked = _to_u32(_mix_t((pos + 1) * _s64(int(GAMMA)) + _s64(table_seed)))
+    return torch.where(wa < 0, picked.view(torch.int32), miss.view(torch.int32)).view(torch.uint32)
+
+
+def table_queries(table_n: int, table_seed: int, q: int, seed: int) -> np.ndarray:
+    """numpy twin of table_queries_t: queries_hit50(uniform_u32(table_n,
+    table_seed), q, seed) without the key array."""
+    out = np.empty(q, np.uint32)
+    for c0 in range(0, q, _CHUNK):
+        c1 = min(q, c0 + _CHUNK)
+        w = splitmix64(seed, 2 * c0, 2 * (c1 - c0))
+        wa, wb = w[0::2], w[1::2]
+        miss = (wb >> np.uint64(32)).astype(np.uint32)
+        if table_n == 0:
+            out[c0:c1] = miss
+            continue
+        hit = (wa >> np.uint64(63)).astype(bool)
+        pos = ((wa & np.uint64(0xFFFFFFFF)) * np.uint64(table_n)) >> np.uint64(32)
+        z = (pos + np.uint64(1)) * GAMMA
+        z += np.uint64(table_seed & 0xFFFFFFFFFFFFFFFF)
+        picked = (_mix(z) >> np.uint64(32)).astype(np.uint32)
+        out[c0:c1] = np.where(hit, picked, miss)
+    return out
+
+
 def zipf_u64_t(n: int, K: int, seed: int, device, s: float = 1.0):
     import torch
 

@@ -1,13 +1,23 @@
 """Serving loop: continuous batching of build and probe requests.
 
-Requests arrive over time (a Poisson stream).  A request is admitted as soon
-as an execution slot is free and its device memory fits under the HBM cap,
-evicting least-recently-used tables that no in-flight request holds.  Admitted
-requests run concurrently, each on the stream of its slot, so the work of
-requests that arrived at different times overlaps on the device.  Built
-tables stay resident for later probes.  A probe whose table was evicted
-rebuilds it from the table's seed first, on the probe's own stream, so every
-result is the same whatever the mix.
+Requests arrive over time (a Poisson stream), each carrying its data: the
+keys of a build, the queries of a probe.  The client side prepares that
+payload on its own stream shortly before the request arrives (a bounded
+lookahead), so a request's latency covers the server's work, not the
+generation of its input.
+
+A request is admitted as soon as an execution slot is free, its payload is
+ready and its device memory fits under the HBM cap, evicting
+least-recently-used tables that no in-flight request holds.  Admission
+follows arrival order, but a request that must wait (for memory, for its
+payload, or for the build of its table) does not hold up later requests
+that can start, until it has waited `max_wait` seconds: from then on nothing
+behind it starts before it, so no request starves.  Admitted requests run
+concurrently, each on the stream of its slot, so the work of requests that
+arrived at different times overlaps on the device.  Built tables stay
+resident for later probes.  A probe whose table was evicted rebuilds it from
+the table's seed first, on the probe's own stream, so every result is the
+same whatever the mix.
 
 The executor does the work: ``GpuExecutor`` calls the HIP library on torch
 streams; tests plug in a CPU executor with a virtual clock.
@@ -16,7 +26,6 @@ streams; tests plug in a CPU executor with a virtual clock.
 from __future__ import annotations
 
 import dataclasses
-import heapq
 import math
 import time
 from collections import OrderedDict
@@ -39,6 +48,7 @@ class Request:
     start: float = math.nan
     finish: float = math.nan
     result: object = None
+    payload: object = None  # the request's keys or queries, once the client has prepared them
 
 
 def table_bytes(n: int) -> int:
@@ -47,15 +57,21 @@ def table_bytes(n: int) -> int:
 
 
 def build_work_bytes(n: int) -> int:
-    """Transient device memory of a build of n keys: the generated keys, two
-    split buffers and the split counts."""
+    """Transient device memory of a build of n keys: the keys (the request's
+    payload, or regenerated for a rebuild), two split buffers and the split
+    counts."""
     return 3 * KEY_BYTES * n + n // 2 + (1 << 20)
 
 
 def probe_work_bytes(q: int, table_n: int) -> int:
-    """Transient device memory of a probe: queries, the table's keys to draw
-    hits from, two split buffers, three count arrays."""
-    return 3 * KEY_BYTES * q + KEY_BYTES * table_n + 12 * q + (1 << 20)
+    """Transient device memory of a probe: the queries (its payload), two
+    split buffers, the slot and count arrays.  (table_n: kept for callers
+    that size by table; the queries no longer need the table's keys.)"""
+    return 3 * KEY_BYTES * q + 12 * q + (1 << 20)
+
+
+def payload_bytes(req: Request) -> int:
+    return KEY_BYTES * req.size
 
 
 def make_trace(num: int, seed: int = 0x5EED0500, build_frac: float = 0.3, build_log2=(10, 24),
@@ -133,9 +149,16 @@ class TableCache:
 
 
 class Server:
-    """Continuous batching over `slots` concurrent requests."""
+    """Continuous batching over `slots` concurrent requests.
 
-    def __init__(self, executor, table_sizes, table_seeds, capacity_bytes: int, slots: int = 4):
+    lookahead: the client prepares the payloads of requests that arrive
+    within this many seconds, at most `max_prepared` (or `max_prepared_bytes`)
+    at a time.  max_wait: seconds a waiting request may be passed over by
+    later ones."""
+
+    def __init__(self, executor, table_sizes, table_seeds, capacity_bytes: int, slots: int = 4,
+                 lookahead: float = 0.02, max_prepared: int = 64, max_prepared_bytes: int = 4 << 30,
+                 max_wait: float = 0.05, scan: int = 64):
         self.ex = executor
         self.sizes = table_sizes
         self.seeds = table_seeds
@@ -143,6 +166,13 @@ class Server:
         self.slots = slots
         self.inflight = []  # [token, request, reserved bytes, output]
         self.rebuilds = 0
+        self.lookahead = lookahead
+        self.max_prepared = max_prepared
+        self.max_prepared_bytes = max_prepared_bytes
+        self.max_wait = max_wait
+        self.scan = scan
+        self.overtakes = 0  # admissions ahead of an earlier waiting request
+        self.unbuilt = set()
 
     def _admit(self, req: Request, now: float) -> bool:
         tid = req.table
@@ -165,18 +195,18 @@ class Server:
                 return False
         stream = self.ex.pick_stream()
         if req.kind == "build":
-            out = self.ex.build(req.size, req.seed, stream)
+            out = self.ex.build(req.payload, stream)
         else:
             if rebuild:
                 # The rebuilt table is resident from now on: its bytes move
                 # from this request's reservation to the cache.
                 self.rebuilds += 1
-                table = self.ex.build(self.sizes[tid], self.seeds[tid], stream)
+                table = self.ex.build(self.ex.table_keys(self.sizes[tid], self.seeds[tid], stream), stream)
                 tb = table_bytes(self.sizes[tid])
                 self.cache.add(tid, table, tb, pins=1)
                 need -= tb
-            out = self.ex.probe(self.cache.entries[tid][0], self.sizes[tid], self.seeds[tid], req.size, req.seed,
-                                stream)
+            out = self.ex.probe(self.cache.entries[tid][0], req.payload, stream)
+        req.payload = None  # the stream holds it until the request's work is done
         self.cache.reserved += need
         self.cache.peak = max(self.cache.peak, self.cache.used + self.cache.reserved)
         req.start = now
@@ -192,6 +222,7 @@ class Server:
             req.finish = self.ex.finish_time(token, now)
             self.cache.reserved -= need
             if req.kind == "build":
+                self.unbuilt.discard(req.table)
                 if self.cache.resident(req.table):  # rebuilt for a probe meanwhile
                     self.ex.free(out)
                 else:
@@ -201,36 +232,76 @@ class Server:
                 self.cache.unpin(req.table)
         self.inflight = still
 
-    def _build_pending(self, tid: int) -> bool:
-        return any(r.kind == "build" and r.table == tid for _, r, _, _ in self.inflight)
+    def _prepare(self, reqs, j: int, now: float, pending: list) -> int:
+        """Client side: prepare the payloads of requests j.. that arrive
+        within the lookahead, keeping at most max_prepared of them (and
+        max_prepared_bytes) prepared but not yet admitted."""
+        held = sum(payload_bytes(r) for r in pending)
+        while j < len(reqs) and reqs[j].arrival <= now + self.lookahead and len(pending) < self.max_prepared:
+            if pending and held + payload_bytes(reqs[j]) > self.max_prepared_bytes:
+                break
+            reqs[j].payload = self.ex.prepare(reqs[j], self.sizes, self.seeds)
+            held += payload_bytes(reqs[j])
+            pending.append(reqs[j])
+            j += 1
+        return j
 
     def run(self, reqs, clock, progress=None, every: int = 5000):
         """Serve `reqs` (sorted by arrival) against `clock`; `progress(msg)`
         is called each time `every` more requests have been admitted."""
-        queue = []
-        i = 0
+        queue = []    # arrived, not admitted, in arrival order
+        pending = []  # payload prepared, not admitted
+        i = j = 0
         admitted = 0
+        # Tables whose first build has not completed: their probes wait.
+        self.unbuilt = {r.table for r in reqs if r.kind == "build"}
         while i < len(reqs) or queue or self.inflight:
             now = clock.now()
-            while i < len(reqs) and reqs[i].arrival <= now:
-                heapq.heappush(queue, (reqs[i].arrival, reqs[i].rid, reqs[i]))
+            j = self._prepare(reqs, j, now, pending)
+            while i < len(reqs) and reqs[i].arrival <= now and i < j:
+                queue.append(reqs[i])
                 i += 1
             self._retire(now)
-            # Admit in arrival order while a slot and memory allow; a probe
-            # waits for the build of its table to complete.
-            while queue and len(self.inflight) < self.slots:
-                req = queue[0][2]
-                if req.kind == "probe" and self._build_pending(req.table):
-                    break
+            # Admit in arrival order while slots allow.  A request that
+            # cannot start yet (payload not ready, its table's build still
+            # running, memory short) is passed over, unless it has waited
+            # max_wait: then nothing behind it starts first.
+            k = 0
+            while k < len(queue) and k < self.scan and len(self.inflight) < self.slots:
+                req = queue[k]
+                aged = now - req.arrival > self.max_wait
+                if not self.ex.ready(req.payload):
+                    if aged:
+                        break
+                    k += 1
+                    continue
+                if req.kind == "probe" and req.table in self.unbuilt:
+                    k += 1  # its table's build (earlier in the queue, or running) comes first
+                    continue
                 if not self._admit(req, now):
                     if not self.inflight:
                         raise MemoryError(f"request {req.rid} needs more than the HBM cap")
-                    break
-                heapq.heappop(queue)
+                    if aged:
+                        break
+                    k += 1
+                    continue
+                if k > 0:
+                    self.overtakes += 1
+                queue.pop(k)
+                pending.remove(req)
                 admitted += 1
                 if progress is not None and admitted % every == 0:
                     progress(f"admitted {admitted} of {len(reqs)}")
-            clock.wait(self, reqs[i].arrival if i < len(reqs) else None)
+            # The next event that is not a completion: the next prepared
+            # request's arrival, or the moment the next one enters the
+            # lookahead (none while the prepared ones fill the limit).
+            if i < j:
+                nxt = reqs[i].arrival
+            elif j < len(reqs) and len(pending) < self.max_prepared:
+                nxt = max(now, reqs[j].arrival - self.lookahead)
+            else:
+                nxt = None
+            clock.wait(self, nxt)
         return reqs
 
 
@@ -281,6 +352,7 @@ class GpuExecutor:
         self.hg = hg
         self.dev = device or torch.device("cuda:0")
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
+        self.client = torch.cuda.Stream(device=self.dev)  # where payloads are drawn
         self.next = 0
         self.oom_retries = 0
         self.keep_results = keep_results
@@ -305,25 +377,53 @@ class GpuExecutor:
             self.oom_retries += 1
             return fn()
 
-    def build(self, n: int, seed: int, stream):
+    def prepare(self, req, sizes, seeds):
+        """The client's payload of `req`, drawn on the client stream: a
+        build's keys, or a probe's queries (50% hits among its table's keys,
+        drawn without the table's key array).  Returns (tensor, event)."""
         def run():
-            with self.torch.cuda.stream(stream):
-                keys = inputs.uniform_u32_t(n, seed, self.dev)
-                table = self.hg.hg_build(keys, stream=stream)
-                keys.record_stream(stream)
-            return table
+            with self.torch.cuda.stream(self.client):
+                if req.kind == "build":
+                    x = inputs.uniform_u32_t(req.size, req.seed, self.dev)
+                else:
+                    x = inputs.table_queries_t(sizes[req.table], seeds[req.table], req.size, req.seed, self.dev)
+                ev = self.torch.cuda.Event()
+                ev.record(self.client)
+            return x, ev
 
         return self._retry_on_oom(run)
 
-    def probe(self, table, table_n: int, table_seed: int, q: int, q_seed: int, stream):
+    def ready(self, payload) -> bool:
+        return payload[1].query()
+
+    def table_keys(self, n: int, seed: int, stream):
+        """A table's keys regenerated by the server (rebuild after an
+        eviction), on the request's stream."""
+        with self.torch.cuda.stream(stream):
+            x = inputs.uniform_u32_t(n, seed, self.dev)
+            ev = self.torch.cuda.Event()
+            ev.record(stream)
+        return x, ev
+
+    def _use(self, payload, stream):
+        x, ev = payload
+        stream.wait_event(ev)
+        x.record_stream(stream)
+        return x
+
+    def build(self, payload, stream):
         def run():
+            keys = self._use(payload, stream)
             with self.torch.cuda.stream(stream):
-                keys = inputs.uniform_u32_t(table_n, table_seed, self.dev)
-                queries = inputs.queries_hit50_t(keys, q, q_seed, self.dev)
-                counts = self.hg.hg_count(table, queries, stream=stream)
-                keys.record_stream(stream)
-                queries.record_stream(stream)
-            return counts
+                return self.hg.hg_build(keys, stream=stream)
+
+        return self._retry_on_oom(run)
+
+    def probe(self, table, payload, stream):
+        def run():
+            queries = self._use(payload, stream)
+            with self.torch.cuda.stream(stream):
+                return self.hg.hg_count(table, queries, stream=stream)
 
         return self._retry_on_oom(run)
 
@@ -363,7 +463,7 @@ def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10*
     torch.cuda.synchronize()
     closed = latency_report(reqs, clock.now())
     closed.update(evictions=srv.cache.evictions, rebuilds=srv.rebuilds, peak_reserved_bytes=srv.cache.peak,
-                  oom_retries=ex.oom_retries)
+                  oom_retries=ex.oom_retries, overtakes=srv.overtakes)
     _release(srv, ex)
     opened = {}
     for load in loads:
@@ -378,7 +478,8 @@ def run_serving(num: int = 2000, slots: int = 4, capacity_bytes: int = 200 * 10*
         torch.cuda.synchronize()
         rep = latency_report(reqs, clock.now())
         rep.update(load=load, offered_requests_per_s=lam, evictions=srv.cache.evictions, rebuilds=srv.rebuilds,
-                   peak_reserved_bytes=srv.cache.peak, oom_retries=ex.oom_retries)
+                   peak_reserved_bytes=srv.cache.peak, oom_retries=ex.oom_retries, overtakes=srv.overtakes,
+                   sustained=rep["requests_per_s"] >= 0.97 * lam)
         opened[load] = rep
         _release(srv, ex)
     return closed, opened, reqs

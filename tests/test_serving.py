@@ -44,13 +44,23 @@ class OracleExecutor:
     def pick_stream(self):
         return None
 
-    def build(self, n, seed, stream):
-        self.cost += self.fixed + self.per_key * n
+    def prepare(self, req, sizes, seeds):
+        if req.kind == "build":
+            return inputs.uniform_u32(req.size, req.seed)
+        return inputs.table_queries(sizes[req.table], seeds[req.table], req.size, req.seed)
+
+    def ready(self, payload):
+        return True
+
+    def table_keys(self, n, seed, stream):
         return inputs.uniform_u32(n, seed)
 
-    def probe(self, table, table_n, table_seed, q, q_seed, stream):
-        self.cost += self.fixed + self.per_key * q
-        queries = inputs.queries_hit50(inputs.uniform_u32(table_n, table_seed), q, q_seed)
+    def build(self, keys, stream):
+        self.cost += self.fixed + self.per_key * keys.size
+        return keys
+
+    def probe(self, table, queries, stream):
+        self.cost += self.fixed + self.per_key * queries.size
         return oracle.count(table, queries)
 
     def record(self, stream):
@@ -127,6 +137,64 @@ def test_probe_waits_for_its_build():
             assert r.start >= built[r.table]
 
 
+def _blocked_build_scenario():
+    """Table A is built, then one long probe of A pins it; a build of table B
+    arrives and does not fit beside A and that probe; small probes of A
+    arrive after it and do fit."""
+    big, small = 1 << 20, 1 << 8
+    n = 1 << 16
+    reqs = [serve.Request(0, "build", 0, n, 101, 0.0), serve.Request(1, "probe", 0, big, 201, 0.001),
+            serve.Request(2, "build", 1, n, 102, 0.002)]
+    reqs += [serve.Request(3 + k, "probe", 0, small, 301 + k, 0.003 + 0.001 * k) for k in range(6)]
+    cap = serve.table_bytes(n) + serve.probe_work_bytes(big, n) + 2 * serve.probe_work_bytes(small, n) + 100000
+    assert serve.table_bytes(n) + serve.build_work_bytes(n) > cap - serve.table_bytes(n) - \
+        serve.probe_work_bytes(big, n)
+    return reqs, [n, n], [101, 102], cap
+
+
+def test_waiting_request_does_not_block_later_ones():
+    """The build of B waits for memory; the small probes behind it start
+    first (no head-of-line blocking), and every result is still exact."""
+    reqs, sizes, seeds, cap = _blocked_build_scenario()
+    clock = VirtualClock()
+    srv = serve.Server(OracleExecutor(clock), sizes, seeds, cap, slots=4, max_wait=1.0)
+    srv.run(reqs, clock)
+    b = reqs[2]
+    assert all(r.start < b.start for r in reqs[3:]), [(r.rid, r.start) for r in reqs]
+    assert srv.overtakes >= 6
+    for r in reqs:
+        if r.kind == "probe":
+            assert np.array_equal(r.result, alone(r, sizes, seeds))
+    assert srv.cache.peak <= cap
+
+
+def test_age_bound_stops_overtaking():
+    """With no waiting allowed (max_wait = 0) the build of B is never passed
+    over: the small probes that arrived after it start after it."""
+    reqs, sizes, seeds, cap = _blocked_build_scenario()
+    clock = VirtualClock()
+    srv = serve.Server(OracleExecutor(clock), sizes, seeds, cap, slots=4, max_wait=0.0)
+    srv.run(reqs, clock)
+    b = reqs[2]
+    assert all(r.start >= b.start for r in reqs[3:]), [(r.rid, r.start) for r in reqs]
+    for r in reqs:
+        if r.kind == "probe":
+            assert np.array_equal(r.result, alone(r, sizes, seeds))
+
+
+def test_payload_prepared_within_lookahead():
+    """The client prepares at most max_prepared payloads ahead, and only
+    for requests arriving within the lookahead."""
+    reqs, sizes, seeds = small_trace(num=40, rate=100.0)  # 10 ms apart on average
+    clock = VirtualClock()
+    srv = serve.Server(OracleExecutor(clock), sizes, seeds, 1 << 40, slots=2, lookahead=0.005, max_prepared=3)
+    pending = []
+    j = srv._prepare(reqs, 0, 0.0, pending)
+    assert 1 <= j <= 3 and all(r.arrival <= 0.005 for r in reqs[:j]) and reqs[j].payload is None
+    srv.run(reqs, clock)
+    assert all(r.finish >= r.arrival for r in reqs)
+
+
 def test_lru_evicts_oldest_unpinned_first():
     freed = []
     c = serve.TableCache(100, freed.append)
@@ -175,9 +243,9 @@ def test_gpu_mix_equals_alone(gpu):
             continue
         want = alone(r, sizes, seeds)
         assert np.array_equal(r.result.cpu().numpy(), want), r.rid
-        keys = torch.from_numpy(inputs.uniform_u32(sizes[r.table], seeds[r.table])).cuda()
-        t = gpu.hg_build(keys)
-        q = torch.from_numpy(inputs.queries_hit50(keys.cpu().numpy(), r.size, r.seed)).cuda()
+        keys_np = inputs.uniform_u32(sizes[r.table], seeds[r.table])
+        t = gpu.hg_build(torch.from_numpy(keys_np).cuda())
+        q = torch.from_numpy(inputs.queries_hit50(keys_np, r.size, r.seed)).cuda()
         assert np.array_equal(gpu.hg_count(t, q).cpu().numpy(), want)
         t.free()
     assert srv.cache.peak <= cap
