@@ -93,19 +93,34 @@ __host__ __device__ __forceinline__ uint32_t mod_by_recip(uint64_t h, uint32_t V
   return static_cast<uint32_t>(r >= V ? r - V : r);
 }
 
-// Per-partition table descriptor: table size, first global bucket, and the
-// two reciprocals of the bucket map.
+// Per-partition table descriptor: table size, first global bucket, the two
+// reciprocals of the bucket map, and pmask = V - 1 when V is a power of two
+// (then hash mod V is the hash's low bits), else kNotPow2.
+constexpr uint32_t kNotPow2 = 0xFFFFFFFFu;
 struct PartDesc {
   uint32_t V;
   uint32_t base;
   uint32_t m32;
-  uint32_t pad;
+  uint32_t pmask;
   uint64_t m64;
 };
 
-// Global bucket of a hash under descriptor d.
+__host__ __device__ __forceinline__ PartDesc make_desc(uint32_t V, uint32_t base) {
+  PartDesc d;
+  d.V = V;
+  d.base = base;
+  d.m32 = recip32(V);
+  d.pmask = (V & (V - 1u)) == 0u ? V - 1u : kNotPow2;  // V >= 1
+  d.m64 = recip64(V);
+  return d;
+}
+
+// Global bucket of a hash under descriptor d: the low bits for a table size
+// that is a power of two (no multiply), else the remainder by reciprocal.
+// Both give hash mod V exactly.
 template <typename H>
 __device__ __forceinline__ uint32_t global_bucket(H h, const PartDesc& d) {
+  if (d.pmask != kNotPow2) return d.base + (static_cast<uint32_t>(h) & d.pmask);
   return d.base + mod_by_recip(h, d.V, d.m32, d.m64);
 }
 

@@ -194,13 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_layout(const uint32_t* __restrict__ 
   uint32_t total;
   const uint32_t ex = block_exclusive_sum<kBlock>(V, wtot, total);
   if (t < P) {
-    PartDesc pd;
-    pd.V = V;
-    pd.base = ex;
-    pd.m32 = recip32(V);
-    pd.pad = 0;
-    pd.m64 = recip64(V);
-    desc[t] = pd;
+    desc[t] = make_desc(V, ex);
     bb[t] = ex;
   }
   if (t == 0) bb[P] = total;
@@ -293,13 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_range_splits(const uint32_t* __restr
     bounds[d] = static_cast<uint32_t>(hb < HR ? hb : HR);
   }
   if (threadIdx.x == 0) {
-    PartDesc pd;
-    pd.V = HR;
-    pd.base = 0;
-    pd.m32 = recip32(HR);
-    pd.pad = 0;
-    pd.m64 = recip64(HR);
-    rdesc[0] = pd;
+    rdesc[0] = make_desc(HR, 0);
   }
 }
 
@@ -418,14 +406,13 @@ __global__ __launch_bounds__(kBlock) void k_probe(const K* __restrict__ tkeys, c
 
 // --------------------------------------------------------- hash + bucket (a1)
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_hash_bucket(const K* __restrict__ keys, uint32_t n, uint32_t V,
-                                                        uint32_t m32, uint64_t m64, uint64_t* __restrict__ hash,
-                                                        uint32_t* __restrict__ bucket) {
+__global__ __launch_bounds__(kBlock) void k_hash_bucket(const K* __restrict__ keys, uint32_t n, PartDesc d,
+                                                        uint64_t* __restrict__ hash, uint32_t* __restrict__ bucket) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
     const auto h = KeyTraits<K>::hash(keys[i]);
     if (hash) hash[i] = static_cast<uint64_t>(h);
-    if (bucket) bucket[i] = mod_by_recip(h, V, m32, m64);
+    if (bucket) bucket[i] = global_bucket(h, d);  // the tables' own map (base 0)
   }
 }
 
@@ -568,12 +555,11 @@ hipError_t launch_probe(int kt, bool count, const void* tkeys, const uint32_t* o
 hipError_t launch_hash_bucket(int kt, const void* keys, uint32_t n, uint32_t V, uint64_t* hash, uint32_t* bucket,
                               hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint32_t m32 = recip32(V);
-  const uint64_t m64 = recip64(V);
+  const PartDesc d = make_desc(V, 0);
   if (kt == 0)
-    k_hash_bucket<uint32_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, V, m32, m64, hash, bucket);
+    k_hash_bucket<uint32_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint32_t*>(keys), n, d, hash, bucket);
   else
-    k_hash_bucket<uint64_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, V, m32, m64, hash, bucket);
+    k_hash_bucket<uint64_t><<<grid_for(n), kBlock, 0, s>>>(static_cast<const uint64_t*>(keys), n, d, hash, bucket);
   return hipGetLastError();
 }
 

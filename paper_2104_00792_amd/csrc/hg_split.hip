@@ -612,13 +612,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_layout(const uint32_t* _
     if (bb != nullptr && x < T) {
       const uint32_t nxt = max(cur, val(x + 1));
       const uint32_t V = size_of(nxt - cur);
-      PartDesc pd;
-      pd.V = V;
-      pd.base = base;
-      pd.m32 = recip32(V);
-      pd.pad = 0;
-      pd.m64 = recip64(V);
-      desc[x] = pd;
+      desc[x] = make_desc(V, base);
       bb[x] = base;
       base += V;
       cur = nxt;
@@ -1288,6 +1282,7 @@ constexpr uint32_t kProbeKeyBytes = 40 * 1024;
 // bucket overflows the expected count needs.
 constexpr uint32_t kProbeOffWords = (1u << kMaxLog2W) + 4;
 constexpr uint32_t kProbeLdsWords = kProbeOffWords + kProbeKeyBytes / 4 + 8;
+static_assert(kProbeLdsWords < (1u << 16), "compacted key positions of a window fit 16 bits");
 
 template <typename K, int THREADS, int REG, int MINW>
 __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict__ q2,
@@ -1469,14 +1464,16 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
       const uint32_t cap_short = kcap - kTableBytes / static_cast<uint32_t>(sizeof(K));  // 4 spare kept
       staged = wave_uniform(nall <= kWinLong && nk - nlong <= cap_short ? 1u : 0u) != 0;
       if (staged) {
-        // Offsets in compacted positions: less the window's first key and
-        // the keys of the long buckets before the bucket.
+        // Offsets in compacted positions (below 2^16): less the window's
+        // first key and the keys of the long buckets before the bucket.  A
+        // long bucket's own offset also carries kLongMark and its list slot
+        // in bits 16.., so a query finds its runs without a search.
         for (uint32_t b = t; b <= R; b += THREADS) {
           uint32_t before = 0, mark = 0;
           for (uint32_t s = 0; s < nl; ++s) {
             const uint32_t g = lbkt[s];
             before += g < b ? lhi[s] - llo[s] : 0u;
-            mark |= g == b ? kLongMark : 0u;
+            mark |= g == b ? (kLongMark | (s << 16)) : 0u;
           }
           soff[b] = (soff[b] - ka - before) | mark;
         }
@@ -1505,7 +1502,19 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
         if (hi - lo <= kLongT) return count_short(skeys, lo - ka, hi - ka, v);
         return count_equal(skeys, lo - ka, hi - ka, v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
       }
-      if (MODE == 1 && !(lo & kLongMark)) return count_short(sshort, lo, hi & ~kLongMark, v);
+      if (MODE == 1) {
+        if (!(lo & kLongMark)) return count_short(sshort, lo, hi & 0xFFFFu, v);
+        // A long bucket: its runs, else its keys in global memory.
+        const uint32_t s = (lo >> 16) & 0x7FFFu;
+        const uint32_t nr = lnr[s];
+        if (nr != kOver) {
+          uint32_t c = 0;
+          for (uint32_t r = 0; r < nr; ++r)
+            if (rkey[s * kSetMax + r] == v) c = rcnt[s * kSetMax + r];
+          return c;
+        }
+        return count_equal(tkeys, llo[s], lhi[s], v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
+      }
       if (MODE == 2 && hi - lo <= kLongT) return count_equal(tkeys, lo, hi, v, false);
       // A long bucket: its runs, else a scan of its keys in global memory.
       for (uint32_t s = 0; s < nl; ++s) {
@@ -1519,7 +1528,6 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
         }
         return count_equal(tkeys, llo[s], lhi[s], v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
       }
-      if (MODE == 1) return 0;  // not reached: every long bucket is listed
       return count_equal(tkeys, lo, hi, v, long_bucket_sorted(unsorted, nuns, sb.gA + lb, kMaxUnsorted));
     };
     // A thread remembers its last query and count: in a sub-bin that holds
