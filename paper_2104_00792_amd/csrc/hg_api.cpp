@@ -595,7 +595,7 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   st = split_two_levels(queries, q, kt, sp, t->log2P, t->P, t->d_desc, w, perm1, perm2, kNames, s);
   if (st != HG_OK) return st;
   void* qv = nullptr;
-  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys() + 1)) * sizeof(uint32_t)), "allocate probe queue");
+  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys(kt) + 1)) * sizeof(uint32_t)), "allocate probe queue");
   HG_LAUNCH("lds_probe", s,
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q, t->log2P, t->P, t->d_desc,
                                  t->d_offsets, t->d_keys, t->d_unsorted, log2W, static_cast<uint32_t*>(qv), c2, s));
@@ -711,7 +711,7 @@ hg_status probe_batched(const hg_table* t, const void* d_queries, uint64_t q, co
   if (st != HG_OK) return st;
   const uint32_t max_subbins = w.max_subbins;
   void* qv = nullptr;
-  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys() + 1)) * sizeof(uint32_t)), "allocate probe queue");
+  HG_TRY(mem.get(&qv, (3 + 2ull * (q / hg::probe_chunk_keys(kt) + 1)) * sizeof(uint32_t)), "allocate probe queue");
   HG_LAUNCH("blds_probe", s,
             hg::launch_lds_probe(kt, w.buf2, w.plan, w.counts2, max_subbins, q32, 0, 1, t->d_desc, t->d_offsets,
                                  t->d_keys, t->d_unsorted, probe_log2W(kt, t->n, t->buckets_bound),

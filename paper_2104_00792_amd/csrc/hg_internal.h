@@ -204,9 +204,12 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
 // sub-bin with more is shared through a queue): windows of 2^log2W buckets
 // of the table (offsets and keys) in LDS; counts in the split order, as
 // bytes when the table has no long bucket (kHasLongWord), else as u32.
-// Workspace: queue[1 + 2 * (q / probe_chunk_keys() + 1)].
-constexpr int kProbeReg = 20;
-uint32_t probe_chunk_keys();
+// Workspace: queue[1 + 2 * (q / probe_chunk_keys(kt) + 1)].  A workgroup
+// holds kProbeReg(kt) queries per thread (fewer 64-bit ones, so that the
+// kernel keeps within 64 VGPRs and two workgroups share a CU).
+constexpr int kProbeReg32 = 20;
+constexpr int kProbeReg64 = 10;
+uint32_t probe_chunk_keys(int kt);
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
                             uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,

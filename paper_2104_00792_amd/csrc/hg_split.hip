@@ -1355,7 +1355,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
     if (m == 0) return;  // whole workgroup
     constexpr int kUO = ((1u << kMaxLog2W) + THREADS) / THREADS;  // R + 1 <= 2^kMaxLog2W + 1 offsets
     constexpr int kUK = (KCAP + THREADS - 1) / THREADS;
-    constexpr int kUQ = 10;
+    constexpr int kUQ = REG / 2;  // queries requested per thread and round
     uint32_t xo[kUO];
     K xk[kUK], qv[kUQ];
 #pragma unroll
@@ -2264,24 +2264,24 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
                           static_cast<uint64_t*>(out), long_count, long_list, heavy, max_chunks, s);
 }
 
-uint32_t probe_chunk_keys() { return kLdsThreads * kProbeReg; }
+uint32_t probe_chunk_keys(int kt) { return kLdsThreads * (kt == 0 ? kProbeReg32 : kProbeReg64); }
 
 hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const uint32_t* qscan2,
                             uint32_t max_subbins, uint32_t q, uint32_t log2P, uint32_t P, const PartDesc* desc,
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
                             uint32_t* queue, void* c2, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
-  const uint32_t max_queued = q / probe_chunk_keys() + 1;
+  const uint32_t max_queued = q / probe_chunk_keys(kt) + 1;
   hipError_t e = launch_fill_u32(queue, 1, 0u, s);
   if (e != hipSuccess) return e;
   for (int pass = 0; pass < 2; ++pass) {
     const uint32_t grid = pass == 0 ? max_subbins : max_queued;
     if (kt == 0)
-      k_lds_probe<uint32_t, kLdsThreads, kProbeReg, 8><<<grid, kLdsThreads, 0, s>>>(
+      k_lds_probe<uint32_t, kLdsThreads, kProbeReg32, 8><<<grid, kLdsThreads, 0, s>>>(
           static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
           static_cast<const uint32_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
     else
-      k_lds_probe<uint64_t, kLdsThreads, kProbeReg, 4><<<grid, kLdsThreads, 0, s>>>(
+      k_lds_probe<uint64_t, kLdsThreads, kProbeReg64, 8><<<grid, kLdsThreads, 0, s>>>(
           static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
           static_cast<const uint64_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
     e = hipGetLastError();
