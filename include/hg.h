@@ -128,9 +128,9 @@ typedef struct hg_table_desc {
  *   d_keys  n keys of type kt (read only; the table keeps its own copy).
  *   opts    build options (required).
  *   out     receives the new table; set only on HG_OK.
- * Allocates the table and temporary workspace from the library's
- * stream-ordered pool (or the allocator of hg_set_allocator); the call does
- * not synchronize.  n = 0 builds an empty table (every bucket empty, every
+ * Allocates the table and temporary workspace from the library's block
+ * cache (or the allocator of hg_set_allocator); the call does not
+ * synchronize (only a cache miss, served by hipMalloc, may wait).  n = 0 builds an empty table (every bucket empty, every
  * count 0).  Errors: HG_ERR_INVALID_ARG for
  * null d_keys with n > 0, null opts/out, n >= 2^32, P not a power of two,
  * a zero ratio without num_buckets, too many buckets, unknown flags, or
@@ -291,12 +291,15 @@ hg_status hg_table_export(const hg_table* table, uint32_t* d_part_offsets,
                           void* d_keys, hipStream_t stream);
 
 /* hg_trim_pool -- hand cached device memory back to the system.  The
- * library allocates tables and workspace from a stream-ordered pool of the
- * current device that keeps freed blocks for reuse; this releases all but
- * keep_bytes of the blocks no stream still uses (callers that share the
- * device with other allocators, such as a serving loop, call it after
- * freeing tables).  The library also trims the pool by itself when an
- * allocation fails, then tries once more.  Errors: HG_ERR_HIP. */
+ * library allocates tables and workspace from a per-device cache of
+ * hipMalloc blocks that keeps freed blocks for reuse: a freed block serves
+ * the next request of its size on the same stream at once, and on other
+ * streams once the work enqueued before its free has completed.  This
+ * releases idle blocks of the current device, largest first, until at most
+ * keep_bytes stay cached, waiting for each block's last use (callers that
+ * share the device with other allocators, such as a serving loop, call it
+ * after freeing tables).  The library also releases every idle block by
+ * itself when hipMalloc fails, then tries once more.  Errors: HG_ERR_HIP. */
 hg_status hg_trim_pool(uint64_t keep_bytes);
 
 /* Device allocator hook (hg_set_allocator).
@@ -314,8 +317,8 @@ typedef void (*hg_free_fn)(void* ptr, size_t bytes, hipStream_t stream,
 /* hg_set_allocator -- route every device allocation of the library (table
  * memory and per-call workspace) through a caller-owned allocator, such as a
  * framework's caching allocator or an arena sized with hg_workspace_size,
- * instead of the library's stream-ordered pool.  Both functions null
- * restores the pool.  The setting is process-wide and applies to calls that
+ * instead of the library's block cache.  Both functions null restores the
+ * cache.  The setting is process-wide and applies to calls that
  * start after it; a table remembers the allocator it was built with and
  * hg_table_free returns its memory there, so the allocator must outlive its
  * tables.  Errors: HG_ERR_INVALID_ARG when exactly one function is null.  A

@@ -88,31 +88,132 @@ bool debug_sync() {
   return on;
 }
 
-// ------------------------------------------------------------ memory pool
-std::mutex g_pool_mu;
-std::map<int, hipMemPool_t> g_pools;
+// ------------------------------------------------------------ block cache
+// The library's own device memory: blocks from hipMalloc that stay cached
+// after they are freed.  A block freed on stream s serves later requests on
+// s at once (stream order keeps its last use ahead of the next), and
+// requests on other streams once the event recorded at its free has
+// completed.  In the steady state of repeated calls nothing here waits for
+// the device, so a caller can enqueue call after call while the GPU works
+// (a stream-ordered hipMemPool has been measured to block the host in
+// every allocation that reuses a block).  Only hipMalloc of a new block,
+// the out-of-memory path and hg_trim_pool wait.
+struct CachedBlock {
+  void* p;
+  size_t bytes;     // rounded size
+  hipStream_t s;    // stream of its last use
+  hipEvent_t ev;    // recorded on s at its free
+};
+struct DevCache {
+  std::multimap<size_t, CachedBlock> idle;  // by rounded size
+  std::vector<hipEvent_t> events;           // recorded events no block holds
+  uint64_t idle_bytes = 0;
+};
+struct LiveBlock {
+  int dev;
+  size_t bytes;
+};
+std::mutex g_cache_mu;
+std::map<int, DevCache> g_cache;
+std::map<void*, LiveBlock> g_live;
 
-hipError_t pool_for(int dev, hipMemPool_t* out) {
-  std::lock_guard<std::mutex> lk(g_pool_mu);
-  auto it = g_pools.find(dev);
-  if (it != g_pools.end()) {
-    *out = it->second;
+// Sizes are rounded so that blocks of nearly equal requests are shared:
+// 512 bytes up to 1 MiB, 2 MiB above.  A request takes an idle block of its
+// rounded size up to an eighth more.
+size_t cache_round(size_t b) {
+  const size_t g = b <= (size_t(1) << 20) ? 512 : (size_t(2) << 20);
+  return (b + g - 1) / g * g;
+}
+
+// Hands idle blocks of dev back to HIP, largest first, until at most keep
+// bytes stay idle; waits for each block's last use.  Caller holds the lock
+// with dev current.
+hipError_t cache_release(DevCache& c, uint64_t keep) {
+  hipError_t first = hipSuccess;
+  while (c.idle_bytes > keep && !c.idle.empty()) {
+    auto it = std::prev(c.idle.end());
+    const CachedBlock b = it->second;
+    c.idle.erase(it);
+    c.idle_bytes -= b.bytes;
+    hipError_t e = hipEventSynchronize(b.ev);
+    if (e == hipSuccess) e = hipFree(b.p);
+    if (e != hipSuccess && first == hipSuccess) first = e;
+    c.events.push_back(b.ev);
+  }
+  return first;
+}
+
+hipError_t cache_alloc(int dev, void** p, size_t bytes, hipStream_t s) {
+  const size_t r = cache_round(bytes);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  DevCache& c = g_cache[dev];
+  auto pick = c.idle.end();
+  for (auto it = c.idle.lower_bound(r); it != c.idle.end() && it->first <= r + r / 8; ++it) {
+    if (it->second.s == s) {
+      pick = it;
+      break;
+    }
+    if (pick == c.idle.end()) {
+      const hipError_t q = hipEventQuery(it->second.ev);
+      if (q == hipSuccess)
+        pick = it;
+      else
+        (void)hipGetLastError();  // not ready: no error for the caller's later checks
+    }
+  }
+  if (pick != c.idle.end()) {
+    *p = pick->second.p;
+    c.events.push_back(pick->second.ev);
+    c.idle_bytes -= pick->second.bytes;
+    g_live[*p] = {dev, pick->second.bytes};
+    c.idle.erase(pick);
     return hipSuccess;
   }
-  hipMemPoolProps props = {};
-  props.allocType = hipMemAllocationTypePinned;
-  props.handleTypes = hipMemHandleTypeNone;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = dev;
-  hipMemPool_t pool;
-  hipError_t e = hipMemPoolCreate(&pool, &props);
-  if (e != hipSuccess) return e;
-  uint64_t keep = UINT64_MAX;  // keep freed blocks for reuse
-  e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  if (e != hipSuccess) return e;
-  g_pools[dev] = pool;
-  *out = pool;
+  hipError_t e = hipMalloc(p, r);
+  if (e == hipErrorOutOfMemory) {
+    // Idle blocks of other sizes hold the memory: give them back, once.
+    (void)hipGetLastError();
+    (void)cache_release(c, 0);
+    e = hipMalloc(p, r);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  g_live[*p] = {dev, r};
   return hipSuccess;
+}
+
+// Takes back a block in stream order: work enqueued on s before this call
+// may still use it.
+void cache_free(void* p, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  const LiveBlock lb = it->second;
+  g_live.erase(it);
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != lb.dev) (void)hipSetDevice(lb.dev);
+  DevCache& c = g_cache[lb.dev];
+  hipEvent_t ev = nullptr;
+  if (!c.events.empty()) {
+    ev = c.events.back();
+    c.events.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    ev = nullptr;
+  }
+  if (ev != nullptr && hipEventRecord(ev, s) == hipSuccess) {
+    c.idle.emplace(lb.bytes, CachedBlock{p, lb.bytes, s, ev});
+    c.idle_bytes += lb.bytes;
+  } else {
+    // No event to order its reuse: wait for the stream and give it back.
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    if (ev != nullptr) c.events.push_back(ev);
+  }
+  if (cur >= 0 && cur != lb.dev) (void)hipSetDevice(cur);
 }
 
 std::atomic<uint64_t> g_next_table_id{1};
@@ -151,7 +252,7 @@ void free_block(const TableBlock& b, hipStream_t s) {
   if (b.hook.free_fn)
     b.hook.free_fn(b.p, b.bytes, s, b.hook.ctx);
   else
-    (void)hipFreeAsync(b.p, s);
+    cache_free(b.p, s);
 }
 
 // Outcome of one allocation: a HIP status, or a block from the caller's
@@ -193,17 +294,7 @@ class Allocs {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return {e, false};
-    hipMemPool_t pool;
-    e = pool_for(dev, &pool);
-    if (e != hipSuccess) return {e, false};
-    e = hipMallocFromPoolAsync(p, bytes, pool, s_);
-    if (e == hipErrorOutOfMemory) {
-      // The pool keeps freed blocks; hand back what no stream still uses
-      // and try once more.
-      (void)hipGetLastError();
-      (void)hipMemPoolTrimTo(pool, 0);
-      e = hipMallocFromPoolAsync(p, bytes, pool, s_);
-    }
+    e = cache_alloc(dev, p, bytes, s_);
     if (e == hipSuccess) owned_.push_back({*p, bytes, hook_});
     return {e, false};
   }
@@ -1292,9 +1383,8 @@ hg_status hg_workspace_size(hg_op op, const hg_table* table, uint64_t n, hg_key_
 hg_status hg_trim_pool(uint64_t keep_bytes) {
   int dev = 0;
   HG_TRY(hipGetDevice(&dev), "hipGetDevice");
-  hipMemPool_t pool;
-  HG_TRY(pool_for(dev, &pool), "memory pool");
-  HG_TRY(hipMemPoolTrimTo(pool, static_cast<size_t>(keep_bytes)), "trim memory pool");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  HG_TRY(cache_release(g_cache[dev], keep_bytes), "release cached blocks");
   return HG_OK;
 }
 

@@ -40,6 +40,55 @@ __device__ __forceinline__ void in_regs(T& x) {
   asm volatile("" : "+v"(x));
 }
 
+// Adds add (0 or 1) to h[idx] for every lane of the wave; with kReturn each
+// lane with add = 1 gets a distinct old value (its rank).  LDS serves the
+// lanes of one atomic that hit one address one after another, so a wave of
+// mostly equal indexes (many copies of one key) would take 64 turns.  While
+// the first lane not yet served shares its index with at least kHistGroup
+// lanes (for up to kHistRounds indexes), those lanes add their sum with one
+// atomic; the rest add their own.  The grouping costs a few instructions
+// per call and, with kReturn, a wait for each atomic's result, so callers
+// take this path only for waves that wave_skewed flags.
+constexpr uint32_t kHistGroup = 8;
+constexpr int kHistRounds = 3;
+constexpr uint32_t kSkewLanes = 16;
+
+// Whether at least kSkewLanes active lanes hold the first active lane's idx
+// (wave-uniform): one sample per wave decides which histogram path the wave
+// takes for all its items.
+__device__ __forceinline__ bool wave_skewed(uint32_t idx) {
+  return popc64(ballot(idx == wave_uniform(idx))) >= kSkewLanes;
+}
+
+template <bool kReturn>
+__device__ __forceinline__ uint32_t lds_hist_add(uint32_t* h, uint32_t idx, uint32_t add) {
+  uint32_t pos = 0;
+  bool done = false;
+#pragma unroll
+  for (int r = 0; r < kHistRounds; ++r) {
+    const uint64_t rest = ballot(!done);
+    if (rest == 0) break;
+    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(rest)) - 1);
+    const uint32_t li = readlane(idx, leader);
+    const bool in = !done && idx == li;
+    const uint64_t same = ballot(in);
+    if (popc64(same) < kHistGroup) break;
+    const uint64_t adds = ballot(in && add != 0);
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(&h[li], popc64(adds));
+    if (kReturn) {
+      base = readlane(base, leader);
+      if (in) pos = base + popc64(adds & lanemask_lt());
+    }
+    done = done || in;
+  }
+  if (!done && (kReturn || add != 0)) {
+    const uint32_t p = atomicAdd(&h[idx], add);
+    if (kReturn) pos = p;
+  }
+  return pos;
+}
+
 // p[i] for a wave-uniform i, where p points into an array that earlier
 // launches wrote and this one only reads (the plan's arrays and scanned
 // counts).  The pointer is taken as a constant-address-space pointer, so
@@ -238,8 +287,14 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
     }
   }
 
+  // A wave whose first items mostly share one digit (a run of copies of
+  // one key) groups its atomics; every other wave adds one per key.
+  const bool skew = wave_skewed(d[0]);
   if (kCount) {
-    if (vec) {
+    if (skew) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) lds_hist_add<false>(hist, d[i], (mask >> i) & 1u);
+    } else if (vec) {
       // A whole tile (nearly every tile): no item is masked.
 #pragma unroll
       for (int i = 0; i < ITEMS; ++i) atomicAdd(&hist[d[i]], 1u);
@@ -254,8 +309,13 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
   }
 
   // Rank of each key among the tile's keys of its digit (invalid items add 0).
+  if (skew) {
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) d[i] |= atomicAdd(&hist[d[i]], (mask >> i) & 1u) << 16;
+    for (int i = 0; i < ITEMS; ++i) d[i] |= lds_hist_add<true>(hist, d[i], (mask >> i) & 1u) << 16;
+  } else {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) d[i] |= atomicAdd(&hist[d[i]], (mask >> i) & 1u) << 16;
+  }
   __syncthreads();
 
   // Digit starts in the tile (exclusive scan of the histogram; thread t
@@ -848,19 +908,21 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
 
   if (R <= kWideR && m <= 0xFFFFu) {
     // The common sub-bin (at most 2^13 buckets): one 32-bit counter per
-    // bucket, so no key pays for packing.  Thread t scans counters 16t ..
-    // 16t + 15 in registers, which also shows it the long buckets; the
-    // offsets then leave in one coalesced pass.
-    static_assert(kWideR == 16u * THREADS, "sixteen counters per thread");
+    // bucket, so no key pays for packing.  Thread t scans its CPT counters
+    // CPT t .. CPT t + CPT - 1 in registers, which also shows it the long
+    // buckets; the offsets then leave in one coalesced pass.
+    constexpr int CPT = static_cast<int>(kWideR) / THREADS, CQ = CPT / 4;
+    static_assert(CPT * THREADS == static_cast<int>(kWideR) && CPT % 4 == 0 && CPT <= 16,
+                  "whole uint4 groups of at most sixteen counters per thread");
     uint4* lds4 = reinterpret_cast<uint4*>(lds);
     for (uint32_t i = t; i < kWideR / 4; i += THREADS) lds4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     // Counters to exclusive offsets, in LDS (the scatter's cursors) and out.
     auto scan_counters = [&]() {
-      uint32_t c[16];
+      uint32_t c[CPT];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const uint4 q = lds4[4 * t + x];
+      for (int x = 0; x < CQ; ++x) {
+        const uint4 q = lds4[CQ * t + x];
         c[4 * x] = q.x;
         c[4 * x + 1] = q.y;
         c[4 * x + 2] = q.z;
@@ -868,7 +930,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       }
       uint32_t sum = 0;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) sum += c[k];
+      for (int k = 0; k < CPT; ++k) sum += c[k];
       if constexpr (sizeof(K) == 4) {
         // 32-bit keys: the register path holds this kernel at 64 VGPRs
         // (eight waves per SIMD), with no room for the reservation below,
@@ -876,18 +938,18 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
         uint32_t total;
         uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
+        for (int x = 0; x < CQ; ++x) {
           uint4 q;
           q.x = ex;
           q.y = q.x + c[4 * x];
           q.z = q.y + c[4 * x + 1];
           q.w = q.z + c[4 * x + 2];
           ex = q.w + c[4 * x + 3];
-          lds4[4 * t + x] = q;
+          lds4[CQ * t + x] = q;
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-          if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + 16u * t + k, c[k]);
+        for (int k = 0; k < CPT; ++k)
+          if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + CPT * t + k, c[k]);
         __syncthreads();
       } else {
         // One scan carries three sums: keys (bits 0-15, at most
@@ -897,11 +959,11 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
         // workgroup then reserves its entries with one atomic per end
         // instead of one per bucket: atomics on one address are served one
         // at a time, and a skewed table has long buckets in almost every
-        // sub-bin.  Bit k of marks: bucket 16t + k is long; bit 16 + k: it
+        // sub-bin.  Bit k of marks: bucket CPT t + k is long; bit 16 + k: it
         // goes to the back (more than kWaveLong keys).
         uint32_t marks = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < CPT; ++k) {
           marks |= (c[k] > kLongT ? 1u : 0u) << k;
           marks |= (c[k] > kWaveLong ? 1u : 0u) << (16 + k);
         }
@@ -910,14 +972,14 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
         const uint32_t exs = block_exclusive_sum<THREADS>(sum | (nfront << 16) | (nback << 26), wsum, total);
         uint32_t ex = exs & 0xFFFFu;
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
+        for (int x = 0; x < CQ; ++x) {
           uint4 q;
           q.x = ex;
           q.y = q.x + c[4 * x];
           q.z = q.y + c[4 * x + 1];
           q.w = q.z + c[4 * x + 2];
           ex = q.w + c[4 * x + 3];
-          lds4[4 * t + x] = q;
+          lds4[CQ * t + x] = q;
         }
         const uint32_t tfront = (total >> 16) & 0x3FFu, tback = total >> 26;
         if (t == 0) {
@@ -929,7 +991,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
           uint32_t f = lbase[0] + ((exs >> 16) & 0x3FFu), b = lbase[1] + (exs >> 26);
           for (uint32_t left = marks & 0xFFFFu; left != 0; left &= left - 1) {
             const uint32_t k = static_cast<uint32_t>(__ffs(left)) - 1;
-            const uint32_t g = sb.gA + 16u * t + k;
+            const uint32_t g = sb.gA + CPT * t + k;
             if ((marks >> (16 + k)) & 1u)
               long_list[long_count[4] - 1 - b++] = g;
             else
@@ -2230,6 +2292,8 @@ hipError_t lds_build_passes(const K* in, const SegPlan* plan, const uint32_t* sc
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, K* out,
                             uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
                             hipStream_t s) {
+  // 64-bit keys: 105 VGPRs, four waves per SIMD.  (1024 threads x 10 keys
+  // at eight waves per SIMD spills across the scan and measured slower.)
   constexpr int kMinW = sizeof(K) == 4 ? 8 : 4;
   uint32_t* heavy_chunks = heavy + 2;
   uint32_t* heavy_bins = heavy_chunks + 2 * static_cast<size_t>(max_chunks);

@@ -364,7 +364,7 @@ class GpuExecutor:
 
     def _retry_on_oom(self, fn):
         """Run fn; if the device is out of memory (both torch's cache and the
-        library's pool keep freed blocks of many sizes), wait for the device,
+        library's block cache keep freed blocks of many sizes), wait for the device,
         hand both caches back and run it once more."""
         try:
             return fn()

@@ -2,7 +2,7 @@
 that hg_workspace_size reports, on the GPU.
 
 An arena of exactly the reported size serves each call; the results equal
-those of the same calls served by the library's pool; every block goes back
+those of the same calls served by the library's block cache; every block goes back
 once, tables to the allocator they were built with; an allocator that fails
 or breaks the alignment contract turns into an error with nothing leaked.
 Counts and offsets are integers, so "equal" means bit-exact."""
@@ -198,3 +198,74 @@ def test_misaligned_block_is_rejected_and_returned(gpu):
         hg.hg_set_allocator()
     assert err.value.status == 1 and "aligned" in str(err.value)
     assert not arena.live and arena.calls == 1
+
+
+def test_block_cache_reuses_freed_blocks(gpu):
+    """Repeated build + count + free on one stream is served from the
+    library's block cache: device memory does not grow after the first
+    round, every round's results are equal, and hg_trim_pool(0) hands the
+    idle blocks back."""
+    import torch
+
+    hg = gpu
+    n = (1 << 22) + 5
+    raw = inputs.uniform_u32(n, 0xE0)
+    keys = to_dev(raw)
+    queries = to_dev(inputs.queries_hit50(raw, n, 0xE1))
+    counts = torch.empty(n, dtype=torch.uint32, device="cuda")
+
+    def round_trip():
+        t = hg.hg_build(keys, P=16)
+        hg.hg_count(t, queries, out=counts)
+        t.free()
+
+    round_trip()
+    torch.cuda.synchronize()
+    want = counts.cpu().numpy().copy()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(5):
+        counts.zero_()
+        round_trip()
+        torch.cuda.synchronize()
+        assert np.array_equal(counts.cpu().numpy(), want)
+    _, tb = hg.hg_workspace_size(hg.HG_OP_BUILD, n=n, P=16)
+    # Without reuse every round would take at least one more table; the HIP
+    # runtime's own buffers may move the figure by a few MiB.
+    assert free0 - torch.cuda.mem_get_info()[0] <= 8 << 20 < tb
+    hg.hg_trim_pool(0)
+    assert torch.cuda.mem_get_info()[0] >= free0 + tb
+
+
+def test_block_cache_across_streams(gpu):
+    """Blocks freed on one stream and requested on another while the first
+    stream may still be working: every result equals the one computed
+    alone (a block handed over before its last use had completed would
+    corrupt the first stream's table or counts)."""
+    import torch
+
+    hg = gpu
+    sizes = [(1 << 21) + 17, (1 << 20) + 3]
+    raws = [inputs.uniform_u32(m, 0xE10 + i) for i, m in enumerate(sizes)]
+    keys = [to_dev(r) for r in raws]
+    queries = [to_dev(inputs.queries_hit50(r, m, 0xE20 + i)) for i, (r, m) in enumerate(zip(raws, sizes))]
+    want = []
+    for k, q in zip(keys, queries):
+        t = hg.hg_build(k, P=4)
+        want.append(hg.hg_count(t, q).cpu().numpy())
+        t.free()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for it in range(6):
+        for j, s in enumerate(streams):
+            w = (it + j) % 2
+            with torch.cuda.stream(s):
+                t = hg.hg_build(keys[w], P=4)
+                c = hg.hg_count(t, queries[w])
+                t.free()
+            outs.append((w, c, s))
+    torch.cuda.synchronize()
+    for w, c, _ in outs:
+        assert np.array_equal(c.cpu().numpy(), want[w])
