@@ -353,6 +353,7 @@ def main():
         "roofline": roof,
         "graph": dict(graph, keys_per_s=n / (graph["ms_per_step"] / 1000.0)),
         "kernels": kernels,
+        "launch_share": launch_share(kernels, ms_per_step),
     }
     if parity is not None:
         result["parity"] = parity
@@ -410,6 +411,17 @@ def timed_with_roofline(hg, step, steps: int, sizes: dict, workload: str, cb: in
                      "design_bytes": sum(algorithmic_bytes(k, **sizes, cb=cb) * v["launches_per_step"]
                                          for k, v in kernels.items())}}
     return sec, kernels, roof
+
+
+def launch_share(kernels: dict, ms_per_step: float) -> dict:
+    """How much of a step lies between launches: the step's time against the
+    sum of its launch groups' event times (each group one or more dispatches
+    of one library call site, such as the LDS build with its heavy-key passes)."""
+    busy = sum(v["ms_per_step"] for v in kernels.values())
+    groups = sum(v["launches_per_step"] for v in kernels.values())
+    between = max(0.0, ms_per_step - busy)
+    return {"launch_groups_per_step": groups, "kernel_ms_per_step": round(busy, 4),
+            "between_launches_ms": round(between, 4), "between_frac": round(between / ms_per_step, 4)}
 
 
 def kernel_table(prof_results: dict, steps: int, sizes: dict, cb: int = 4) -> dict:
@@ -531,6 +543,7 @@ def run_batched(args, dev):
         "graph": dict(graph, keys_per_s=total / (graph["ms_per_step"] / 1000.0)),
         "roofline": roof,
         "kernels": kernels,
+        "launch_share": launch_share(kernels, sec * 1000.0),
     }
     print(json.dumps(result), flush=True)
 

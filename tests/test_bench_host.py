@@ -88,3 +88,11 @@ def test_traffic_is_read_only_for_the_sources_it_was_taken_on(tmp_path, monkeypa
     assert bench.read_traffic("w", "qgather1") is None  # kernel not in the summary
     f.write_text("kernel_source_sha256_16 = 0000000000000000\nhbm_bytes_per_launch.lds_probe = 4319000000\n")
     assert bench.read_traffic("w", "lds_probe") is None  # taken on other sources
+
+
+def test_launch_share_is_the_step_outside_its_launch_groups():
+    kernels = {"a": {"ms_per_step": 1.0, "launches_per_step": 2}, "b": {"ms_per_step": 2.5, "launches_per_step": 1}}
+    share = bench.launch_share(kernels, 4.0)
+    assert share["launch_groups_per_step"] == 3 and share["kernel_ms_per_step"] == 3.5
+    assert share["between_launches_ms"] == 0.5 and share["between_frac"] == 0.125
+    assert bench.launch_share(kernels, 3.0)["between_launches_ms"] == 0.0  # event overhead can exceed the gaps
