@@ -386,8 +386,11 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_msplit(con
 // (stage[perm[i]] != 0) bytes (GATHER_FOUND).  The counts come as bytes when
 // the table has no long bucket, else as u32.  Every global access reads or
 // writes consecutive elements: a run, the slots, the output.
-template <int THREADS, int ITEMS, int MAXD, int OUT>
-__global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gather(
+// SB: bytes per staged count.  Both widths are launched; the instance that
+// does not match the table (bytes without long buckets) returns at once, so
+// the byte instance, a quarter of the staging LDS, fits more workgroups.
+template <int THREADS, int ITEMS, int MAXD, int OUT, int SB>
+__global__ __launch_bounds__(THREADS, THREADS >= 1024 || (THREADS >= 512 && SB == 1) ? 8 : 4) void k_tile_gather(
     const uint16_t* __restrict__ perm, const void* __restrict__ src, uint32_t n,
     const SegPlan* __restrict__ plan, uint32_t nd, const uint32_t* __restrict__ scan,
     const uint32_t* __restrict__ unsorted, void* __restrict__ out) {
@@ -396,18 +399,21 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
   constexpr int kW = THREADS / kWave;
   constexpr bool FOUND = OUT == GATHER_FOUND;
   static_assert(ITEMS % 4 == 0, "four slots per 8-byte load");
+  static_assert(SB == 1 || SB == 4, "counts staged as bytes or words");
+  using StageT = typename std::conditional<SB == 1, uint8_t, uint32_t>::type;
   __shared__ uint32_t dstart[MAXD + 1];
   __shared__ uint32_t delta[MAXD];  // src index of a slot minus the slot
   __shared__ uint32_t wtot[kW];
-  __shared__ uint32_t stage[TILE];
+  __shared__ StageT stage[TILE];
   __shared__ uint16_t sdg[TILE];    // digit of each slot
   const uint32_t t = threadIdx.x;
+  // Counts as bytes in src, and in out for a further gather.
+  const bool narrow = unsorted[kHasLongWord] == 0;
+  if (narrow != (SB == 1)) return;  // the other instance serves this table
   TileLoc L;
   if (!tile_loc(plan, nd, n, TILE, L)) return;  // whole workgroup
   const uint32_t cnt = L.tail - L.head;         // at least 1: a tile holds keys
   const uint32_t first = L.base + L.head;       // input order: elements first + e, e < cnt
-  // Counts as bytes in src, and in out for a further gather.
-  const bool narrow = unsorted[kHasLongWord] == 0;
   const bool out_bytes = FOUND || (OUT == GATHER_STAGE && narrow);
   const uintptr_t oa = out_bytes ? reinterpret_cast<uintptr_t>(static_cast<uint8_t*>(out) + first)
                                  : reinterpret_cast<uintptr_t>(static_cast<uint32_t*>(out) + first);
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 ? 8 : 4) void k_tile_gathe
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const uint32_t j = static_cast<uint32_t>(i) * THREADS + t;
-    if (j < cnt) stage[j] = v[i];
+    if (j < cnt) stage[j] = static_cast<StageT>(v[i]);
   }
   __syncthreads();
 
@@ -2233,20 +2239,33 @@ hipError_t launch_msplit(int kt, int level, int op, int dig, const void* in, uin
                                 desc, shift, counts, static_cast<uint64_t*>(out), perm, s);
 }
 
+template <int THREADS, int ITEMS, int MAXD, int SB>
+hipError_t tile_gather_sb(dim3 grid, const uint16_t* perm, const void* src, uint32_t n, const SegPlan* plan,
+                          uint32_t nd, const uint32_t* scan, const uint32_t* unsorted, void* out, int out_kind,
+                          hipStream_t s) {
+  if (out_kind == GATHER_FOUND)
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_FOUND, SB><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                                  unsorted, out);
+  else if (out_kind == GATHER_COUNT)
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_COUNT, SB><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                                  unsorted, out);
+  else
+    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_STAGE, SB><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
+                                                                                  unsorted, out);
+  return hipGetLastError();
+}
+
+// Byte counts first (no long bucket, the common case), then word counts;
+// exactly one of the two does the work (the table's flag decides on the
+// device, so nothing waits for the host).
 template <int THREADS, int ITEMS, int MAXD>
 hipError_t tile_gather(dim3 grid, const uint16_t* perm, const void* src, uint32_t n, const SegPlan* plan,
                        uint32_t nd, const uint32_t* scan, const uint32_t* unsorted, void* out, int out_kind,
                        hipStream_t s) {
-  if (out_kind == GATHER_FOUND)
-    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_FOUND><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
-                                                                              unsorted, out);
-  else if (out_kind == GATHER_COUNT)
-    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_COUNT><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
-                                                                              unsorted, out);
-  else
-    k_tile_gather<THREADS, ITEMS, MAXD, GATHER_STAGE><<<grid, THREADS, 0, s>>>(perm, src, n, plan, nd, scan,
-                                                                              unsorted, out);
-  return hipGetLastError();
+  hipError_t e = tile_gather_sb<THREADS, ITEMS, MAXD, 1>(grid, perm, src, n, plan, nd, scan, unsorted, out,
+                                                         out_kind, s);
+  if (e != hipSuccess) return e;
+  return tile_gather_sb<THREADS, ITEMS, MAXD, 4>(grid, perm, src, n, plan, nd, scan, unsorted, out, out_kind, s);
 }
 
 hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const void* src, uint32_t n,
@@ -2256,14 +2275,17 @@ hipError_t launch_tile_gather(int kt, int level, const uint16_t* perm, const voi
     const uint32_t tiles = div_up(n, kL1Tile);
     if (tiles == 0) return hipSuccess;
     if (nd > 256) return hipErrorInvalidValue;
-    return tile_gather<kL1Tile / 8, 8, 256>(dim3(tiles), perm, src, n, nullptr, nd, scan, unsorted, out, out_kind,
-                                            s);
+    return tile_gather<kL1Tile / 16, 16, 256>(dim3(tiles), perm, src, n, nullptr, nd, scan, unsorted, out,
+                                              out_kind, s);
   }
   if (max_tiles == 0) return hipSuccess;
+  // Half the split's threads, twice the items: a tile's gather takes eight
+  // waves, so four of them fit on a CU instead of two.
   if (kt == 0)
-    return tile_gather<kL2Threads, 8, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out, out_kind,
-                                              s);
-  return tile_gather<kL2Threads, 4, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out, out_kind, s);
+    return tile_gather<kL2Threads / 2, 16, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out,
+                                                   out_kind, s);
+  return tile_gather<kL2Threads / 2, 8, kMaxD2>(dim3(max_tiles), perm, src, n, plan, 0, scan, unsorted, out,
+                                                out_kind, s);
 }
 
 hipError_t launch_plan(const uint32_t* scan1, uint32_t tiles1, uint32_t nseg, uint32_t n, int mode,
