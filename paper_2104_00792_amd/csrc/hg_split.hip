@@ -405,10 +405,12 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 || (THREADS >= 512 && SB =
   __shared__ uint32_t delta[MAXD];  // src index of a slot minus the slot
   __shared__ uint32_t wtot[kW];
   __shared__ StageT stage[TILE];
-  __shared__ uint16_t sdg[TILE];    // digit of each slot
+  __shared__ __align__(16) uint16_t sdg[TILE];  // digit of each slot
   const uint32_t t = threadIdx.x;
-  // Counts as bytes in src, and in out for a further gather.
-  const bool narrow = unsorted[kHasLongWord] == 0;
+  // Counts as bytes in src, and in out for a further gather.  A scalar load:
+  // the instance that does not serve this table has every workgroup read the
+  // flag and leave, so that read's latency is all it costs.
+  const bool narrow = ld_uniform(unsorted, kHasLongWord) == 0;
   if (narrow != (SB == 1)) return;  // the other instance serves this table
   TileLoc L;
   if (!tile_loc(plan, nd, n, TILE, L)) return;  // whole workgroup
@@ -459,12 +461,41 @@ __global__ __launch_bounds__(THREADS, THREADS >= 1024 || (THREADS >= 512 && SB =
   if (t == 0) dstart[L.D] = total;
   __syncthreads();
 
-  // Digit of every slot: wave w marks the runs of digits w, w + kW, ...
+  // Digit of every slot.  Thread t takes slots ITEMS t .. ITEMS t + ITEMS - 1:
+  // a binary search over the run starts finds the digit of the first (an
+  // empty run shares its successor's start, so the last digit whose start
+  // is at or below the slot holds it; dstart[0] = 0 and dstart[D] = cnt
+  // bound the search), then a walk over the consecutive slots.  Every
+  // thread's search runs at once, where marking run by run took one
+  // dependent LDS round trip per digit and wave.
   {
-    const uint32_t w = t / kWave, l = lane_id();
-    for (uint32_t dd = w; dd < L.D; dd += kW) {
-      const uint32_t a = dstart[dd], b = dstart[dd + 1];
-      for (uint32_t j = a + l; j < b; j += kWave) sdg[j] = static_cast<uint16_t>(dd);
+    static_assert(ITEMS % 8 == 0, "whole 16-byte stores of slot digits");
+    const uint32_t j0 = static_cast<uint32_t>(ITEMS) * t;
+    if (j0 < cnt) {
+      uint32_t lo = 0, hi = L.D;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (dstart[mid] <= j0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      uint32_t d = lo, dg[ITEMS / 2];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = j0 + static_cast<uint32_t>(i);
+        while (d + 1 < L.D && dstart[d + 1] <= j) ++d;  // stops at the run holding j (j < cnt = dstart[D])
+        if (i & 1) dg[i >> 1] |= d << 16; else dg[i >> 1] = d;
+      }
+      if (j0 + ITEMS <= cnt) {
+        uint4* dst = reinterpret_cast<uint4*>(sdg + j0);
+#pragma unroll
+        for (int x = 0; x < ITEMS / 8; ++x) dst[x] = make_uint4(dg[4 * x], dg[4 * x + 1], dg[4 * x + 2], dg[4 * x + 3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+          if (j0 + i < cnt) sdg[j0 + i] = static_cast<uint16_t>(dg[i >> 1] >> ((i & 1) << 4));
+      }
     }
   }
   __syncthreads();
