@@ -1241,12 +1241,11 @@ __global__ __launch_bounds__(THREADS) void k_heavy_count(const K* __restrict__ i
     load_sub_bin_desc<K>(sd, plan, desc, sb.seg, P, THREADS);
     for (uint32_t i = t; i < R; i += THREADS) hist[i] = 0;
     __syncthreads();
+    // Every load in flight at once: a lane past the chunk's end re-reads its
+    // last key (c1 > c0) and adds nothing.
     K v[REG];
 #pragma unroll
-    for (int j = 0; j < REG; ++j) {
-      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
-      v[j] = e < c1 ? in[e] : K(0);
-    }
+    for (int j = 0; j < REG; ++j) v[j] = in[min(c0 + static_cast<uint32_t>(j) * THREADS + t, c1 - 1)];
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
@@ -1303,10 +1302,7 @@ __global__ __launch_bounds__(THREADS) void k_heavy_scatter(const K* __restrict__
     K v[REG];
     uint32_t lb[REG];
 #pragma unroll
-    for (int j = 0; j < REG; ++j) {
-      const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
-      v[j] = e < c1 ? in[e] : K(0);
-    }
+    for (int j = 0; j < REG; ++j) v[j] = in[min(c0 + static_cast<uint32_t>(j) * THREADS + t, c1 - 1)];
 #pragma unroll
     for (int j = 0; j < REG; ++j) {
       const uint32_t e = c0 + static_cast<uint32_t>(j) * THREADS + t;
@@ -2106,14 +2102,16 @@ __global__ __launch_bounds__(kLongThreads) void k_big_scan(const uint32_t* __res
 }
 
 // One workgroup per big bucket: the chunk sets merged, ranked into runs;
-// too many distinct keys list the bucket as unsorted.
+// too many distinct keys list the bucket as unsorted.  Wave w merges chunks
+// w, w + W, ... into its own set, then wave 0 merges the W sets (a bucket of
+// one heavy key has one chunk per 2^16 of its copies).
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __restrict__ offsets, BigWork<K> bw,
                                                           uint32_t* __restrict__ unsorted) {
   constexpr int W = kLongThreads / kWave;
   __shared__ K sval[W][kSetMax];
   __shared__ uint32_t scnt[W][kSetMax];
-  __shared__ uint32_t ssize[1];
+  __shared__ uint32_t ssize[W];
   __shared__ uint32_t run0[kSetMax + 1];
   __shared__ uint32_t soverflow;
   const uint32_t t = threadIdx.x, w = t / kWave, l = lane_id();
@@ -2122,22 +2120,35 @@ __global__ __launch_bounds__(kLongThreads) void k_big_fix(const uint32_t* __rest
     const uint32_t g = bw.big_g[bi];
     const uint32_t L = offsets[g + 1] - offsets[g];
     const uint32_t first = bw.big_first[bi], nch = (L + kBigChunk - 1) / kBigChunk;
-    if (t == 0) {
-      ssize[0] = 0;
-      soverflow = 0;
-    }
+    if (t < W) ssize[t] = 0;
+    if (t == 0) soverflow = 0;
     __syncthreads();
-    if (w == 0) {
+    {
       bool full = false;
-      for (uint32_t c = first; c < first + nch && !full; ++c) {
+      for (uint32_t c = first + w; c < first + nch && !full; c += W) {
         const uint32_t nd = wave_uniform(bw.chunk_n[c]);
         if (nd == kOver) {
           if (l == 0) soverflow = 1;
           break;
         }
         for (uint32_t e = 0; e < nd; ++e) {
-          if (!set_add(sval[0], scnt[0], &ssize[0], bw.chunk_key[static_cast<size_t>(c) * kSetMax + e],
+          if (!set_add(sval[w], scnt[w], &ssize[w], bw.chunk_key[static_cast<size_t>(c) * kSetMax + e],
                        bw.chunk_cnt[static_cast<size_t>(c) * kSetMax + e])) {
+            if (l == 0) soverflow = 1;
+            full = true;
+            break;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    if (w == 0 && wave_uniform(soverflow) == 0) {
+      bool full = false;
+      for (uint32_t o = 1; o < static_cast<uint32_t>(W) && !full; ++o) {
+        const uint32_t n = wave_uniform(ssize[o]);
+        for (uint32_t e = 0; e < n; ++e) {
+          if (!set_add(sval[0], scnt[0], &ssize[0], sval[o][e], scnt[o][e])) {
             if (l == 0) soverflow = 1;
             full = true;
             break;
