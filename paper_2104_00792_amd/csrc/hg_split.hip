@@ -1799,11 +1799,10 @@ __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_
   for (uint32_t c0 = first; c0 < b && ok; c0 += step) {
     if (stop != nullptr && wave_uniform(*stop)) return false;
     K kv[kGroups];
+    // All kGroups loads in flight: a lane past b re-reads src[b - 1] (c0 < b)
+    // and is not valid below.
 #pragma unroll
-    for (int gi = 0; gi < kGroups; ++gi) {
-      const uint32_t i = c0 + gi * kWave + l;
-      kv[gi] = i < b ? src[i] : K(0);
-    }
+    for (int gi = 0; gi < kGroups; ++gi) kv[gi] = src[min(c0 + gi * kWave + l, b - 1)];
 #pragma unroll
     for (int gi = 0; gi < kGroups; ++gi) {
       const uint32_t i = c0 + gi * kWave + l;
