@@ -658,8 +658,21 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   // window each (every query then hashes and is counted once), as long as a
   // coarse range keeps at most kMaxD2 of them.
   const uint32_t log2W = probe_log2W(kt, t->n, t->buckets_bound);
-  if (sp.mode == 1)
+  if (sp.mode == 1) {
     while (sp.log2S > log2W && sp.log2S > hg::kLog2SMin && sp.sh1 - (sp.log2S - 1) <= 10) --sp.log2S;
+    // Narrower sub-bins mean more level-2 digits per coarse range and
+    // shorter runs in the level-2 split and gather; narrower ranges take
+    // them back while the level-1 split keeps at most 256 digits (the
+    // query split needs no ranges of the table's width: only its sub-bins
+    // meet the table's windows).
+    const uint64_t bound = t->buckets_bound;
+    uint32_t sh = sp.sh1;
+    while (sh > sp.log2S + split_l2_bits() && ((bound + (1ull << (sh - 1)) - 1) >> (sh - 1)) <= 256) --sh;
+    if (sh != sp.sh1) {
+      sp.sh1 = sh;
+      sp.nd1 = static_cast<uint32_t>((t->buckets_bound + (1ull << sh) - 1) >> sh);
+    }
+  }
   Allocs mem(s);
   SplitBufs w;
   hg_status st = alloc_split(mem, q, kt, sp, t->P, t->buckets_bound, w, 0);
