@@ -1395,11 +1395,14 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t nwl;
   const uint32_t t = threadIdx.x;
-  // A workgroup takes at most CH of a sub-bin's queries.  First launch:
-  // workgroup b takes chunk 0 of sub-bin b and queues chunks 1.. of a sub-bin
-  // with more queries (queue[0] = count, then (sub-bin, chunk) pairs).
-  // Second launch (from_queue): workgroup w takes queued item w.
+  // First launch: workgroup b takes the first CH queries of sub-bin b and
+  // queues the rest of a sub-bin with more, in chunks of CHQ (queue[0] =
+  // count, then (sub-bin, chunk) pairs; chunk k >= 1 starts at CH + (k - 1)
+  // CHQ).  Second launch (from_queue): workgroup w takes queued item w.  A
+  // queued chunk is several register loads of queries against one window
+  // set-up (a sub-bin that holds a heavy key takes millions of queries).
   constexpr uint32_t CH = THREADS * REG;
+  constexpr uint32_t CHQ = 4 * CH;
   uint32_t b, chunk;
   if (from_queue) {
     if (blockIdx.x >= queue[0]) return;  // whole workgroup
@@ -1412,15 +1415,16 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
   }
   const SubBin sb = sub_bin<true>(qplan, qscan2, b);
   if (!from_queue && t == 0 && sb.kB - sb.kA > CH) {
-    const uint32_t extra = (sb.kB - sb.kA - 1) / CH;  // chunks after the first
+    // No more items than chunks of CH would make: the queue's bound holds.
+    const uint32_t extra = (sb.kB - sb.kA - CH + CHQ - 1) / CHQ;  // chunks after the first
     const uint32_t at = atomicAdd(&queue[0], extra);
     for (uint32_t k = 0; k < extra; ++k) {
       queue[1 + 2 * (at + k)] = b;
       queue[2 + 2 * (at + k)] = k + 1;
     }
   }
-  const uint32_t qa = sb.kA + min(chunk * CH, sb.kB - sb.kA);
-  const uint32_t R = sb.gB - sb.gA, m = min(CH, sb.kB - qa);
+  const uint32_t qa = sb.kA + min(chunk == 0 ? 0u : CH + (chunk - 1) * CHQ, sb.kB - sb.kA);
+  const uint32_t R = sb.gB - sb.gA, m = min(chunk == 0 ? CH : CHQ, sb.kB - qa);
   const uint32_t Wb = 1u << log2W;
   const uint32_t nuns = unsorted[0];
   // Counts leave as bytes when the table has no long bucket (every count is
