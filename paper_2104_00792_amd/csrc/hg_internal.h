@@ -204,7 +204,8 @@ hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const u
 // sub-bin with more is shared through a queue): windows of 2^log2W buckets
 // of the table (offsets and keys) in LDS; counts in the split order, as
 // bytes when the table has no long bucket (kHasLongWord), else as u32.
-// Workspace: queue[1 + 2 * (q / probe_chunk_keys(kt) + 1)].  A workgroup
+// Workspace: queue[1 + 2 * (q / probe_chunk_keys(kt) + 1)] (a small kernel
+// lists the chunks of every sub-bin with more queries first).  A workgroup
 // holds kProbeReg(kt) queries per thread (fewer 64-bit ones, so that the
 // kernel keeps within 64 VGPRs and two workgroups share a CU).
 constexpr int kProbeReg32 = 20;

@@ -1349,6 +1349,29 @@ __global__ __launch_bounds__(THREADS) void k_heavy_fix(const SegPlan* __restrict
 }
 
 // ------------------------------------------------------------- LDS probe
+// Queued chunks of a probe sub-bin hold kProbeQueueLoads register loads of
+// queries each (one window set-up per chunk).
+constexpr uint32_t kProbeQueueLoads = 4;
+
+// The probe's queue: for every sub-bin with more than ch queries, its
+// queries after the first ch in chunks of kProbeQueueLoads * ch, as
+// (sub-bin, chunk) pairs after the count queue[0] (zeroed before).  No more
+// items than chunks of ch would make: the queue holds q / ch + 1 of them.
+__global__ __launch_bounds__(256) void k_probe_queue(const SegPlan* __restrict__ qplan,
+                                                     const uint32_t* __restrict__ qscan2, uint32_t ch,
+                                                     uint32_t* __restrict__ queue) {
+  const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+  if (b >= qplan->total_subbins) return;
+  const SubBin sb = sub_bin<false>(qplan, qscan2, b);
+  const uint32_t m = sb.kB - sb.kA, chq = kProbeQueueLoads * ch;
+  if (m <= ch) return;
+  const uint32_t extra = (m - ch + chq - 1) / chq;
+  const uint32_t at = atomicAdd(&queue[0], extra);
+  for (uint32_t k = 0; k < extra; ++k) {
+    queue[1 + 2 * (at + k)] = b;
+    queue[2 + 2 * (at + k)] = k + 1;
+  }
+}
 // dst[0 .. len) = src[0 .. len), U loads in flight per thread before their
 // LDS stores (one wait per batch instead of one per element).
 template <int THREADS, int U, typename T>
@@ -1387,42 +1410,33 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
                                                              const uint32_t* __restrict__ offsets,
                                                              const K* __restrict__ tkeys,
                                                              const uint32_t* __restrict__ unsorted, uint32_t log2W,
-                                                             uint32_t* __restrict__ queue, bool from_queue,
-                                                             void* __restrict__ c2v) {
+                                                             const uint32_t* __restrict__ queue,
+                                                             uint32_t max_queued, void* __restrict__ c2v) {
   constexpr uint32_t KCAP = kProbeKeyBytes / sizeof(K);  // keys in LDS at the largest window
   __shared__ __align__(16) uint32_t sbuf[kProbeLdsWords];
   static_assert((kProbeLdsWords - kProbeOffWords) * 4 / sizeof(K) - 4 >= KCAP, "the largest window keeps KCAP keys");
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t nwl;
   const uint32_t t = threadIdx.x;
-  // First launch: workgroup b takes the first CH queries of sub-bin b and
-  // queues the rest of a sub-bin with more, in chunks of CHQ (queue[0] =
-  // count, then (sub-bin, chunk) pairs; chunk k >= 1 starts at CH + (k - 1)
-  // CHQ).  Second launch (from_queue): workgroup w takes queued item w.  A
-  // queued chunk is several register loads of queries against one window
-  // set-up (a sub-bin that holds a heavy key takes millions of queries).
+  // Workgroup w < max_queued takes queued item w (k_probe_queue listed the
+  // rest of every sub-bin with more than CH queries, in chunks of CHQ);
+  // workgroup max_queued + b takes the first CH queries of sub-bin b.  The
+  // long queued chunks (a heavy key's sub-bin) start first, and the short
+  // sub-bins fill in around them in the same launch.
   constexpr uint32_t CH = THREADS * REG;
-  constexpr uint32_t CHQ = 4 * CH;
+  constexpr uint32_t CHQ = kProbeQueueLoads * CH;
   uint32_t b, chunk;
-  if (from_queue) {
-    if (blockIdx.x >= queue[0]) return;  // whole workgroup
-    b = queue[1 + 2 * blockIdx.x];
-    chunk = queue[2 + 2 * blockIdx.x];
+  if (blockIdx.x < max_queued) {
+    const uint32_t w = blockIdx.x;
+    if (w >= ld_uniform(queue, 0)) return;  // whole workgroup
+    b = ld_uniform(queue, 1 + 2 * w);
+    chunk = ld_uniform(queue, 2 + 2 * w);
   } else {
-    if (blockIdx.x >= qplan->total_subbins) return;  // whole workgroup
-    b = blockIdx.x;
+    b = blockIdx.x - max_queued;
+    if (b >= qplan->total_subbins) return;  // whole workgroup
     chunk = 0;
   }
   const SubBin sb = sub_bin<true>(qplan, qscan2, b);
-  if (!from_queue && t == 0 && sb.kB - sb.kA > CH) {
-    // No more items than chunks of CH would make: the queue's bound holds.
-    const uint32_t extra = (sb.kB - sb.kA - CH + CHQ - 1) / CHQ;  // chunks after the first
-    const uint32_t at = atomicAdd(&queue[0], extra);
-    for (uint32_t k = 0; k < extra; ++k) {
-      queue[1 + 2 * (at + k)] = b;
-      queue[2 + 2 * (at + k)] = k + 1;
-    }
-  }
   const uint32_t qa = sb.kA + min(chunk == 0 ? 0u : CH + (chunk - 1) * CHQ, sb.kB - sb.kA);
   const uint32_t R = sb.gB - sb.gA, m = min(chunk == 0 ? CH : CHQ, sb.kB - qa);
   const uint32_t Wb = 1u << log2W;
@@ -2402,23 +2416,22 @@ hipError_t launch_lds_probe(int kt, const void* q2, const SegPlan* qplan, const 
                             const uint32_t* offsets, const void* tkeys, const uint32_t* unsorted, uint32_t log2W,
                             uint32_t* queue, void* c2, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
-  const uint32_t max_queued = q / probe_chunk_keys(kt) + 1;
+  const uint32_t ch = probe_chunk_keys(kt);
+  const uint32_t max_queued = q / ch + 1;
   hipError_t e = launch_fill_u32(queue, 1, 0u, s);
   if (e != hipSuccess) return e;
-  for (int pass = 0; pass < 2; ++pass) {
-    const uint32_t grid = pass == 0 ? max_subbins : max_queued;
-    if (kt == 0)
-      k_lds_probe<uint32_t, kLdsThreads, kProbeReg32, 8><<<grid, kLdsThreads, 0, s>>>(
-          static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
-          static_cast<const uint32_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
-    else
-      k_lds_probe<uint64_t, kLdsThreads, kProbeReg64, 8><<<grid, kLdsThreads, 0, s>>>(
-          static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets,
-          static_cast<const uint64_t*>(tkeys), unsorted, log2W, queue, pass == 1, c2);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  k_probe_queue<<<div_up(max_subbins, 256), 256, 0, s>>>(qplan, qscan2, ch, queue);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const uint32_t grid = max_subbins + max_queued;
+  if (kt == 0)
+    k_lds_probe<uint32_t, kLdsThreads, kProbeReg32, 8><<<grid, kLdsThreads, 0, s>>>(
+        static_cast<const uint32_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint32_t*>(tkeys),
+        unsorted, log2W, queue, max_queued, c2);
+  else
+    k_lds_probe<uint64_t, kLdsThreads, kProbeReg64, 8><<<grid, kLdsThreads, 0, s>>>(
+        static_cast<const uint64_t*>(q2), qplan, qscan2, log2P, P, desc, offsets, static_cast<const uint64_t*>(tkeys),
+        unsorted, log2W, queue, max_queued, c2);
+  return hipGetLastError();
 }
 
 hipError_t launch_find_long(const uint32_t* offsets, const uint32_t* num_buckets_dev, uint64_t bound,
