@@ -484,26 +484,33 @@ uint32_t split_l2_bits() {
 // otherwise by coarse bucket ranges of 2^L2 sub-bins each (at most 256
 // ranges; ranges grow when the table needs more).
 // opts->log2_subbin and opts->split_bits, when nonzero, replace the two
-// choices (already range-checked).
-SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound, const hg_build_opts* opts) {
+// choices (already range-checked).  Sub-bins keep about 2^13 keys however
+// many keys share a bucket (a table with long buckets then still sorts and
+// probes every sub-bin in LDS), but no fewer than min_log2S buckets, and
+// enough that 256 ranges of kMaxD2 sub-bins cover the table.
+SplitParams split_params(uint32_t P, uint64_t n, uint64_t bound, const hg_build_opts* opts,
+                         uint32_t min_log2S = 0) {
   SplitParams sp;
   const uint64_t buckets = bound > P ? bound - P : 1;
   uint32_t rho_log = 0;  // ceil(log2(keys per bucket)), at least 0
   while ((buckets << rho_log) < n) ++rho_log;
+  const uint32_t lb = ceil_log2(bound < 2 ? 2 : bound);
   uint32_t l = hg::kLog2SMax > rho_log ? hg::kLog2SMax - rho_log : 0;
-  if (l < hg::kLog2SMin) l = hg::kLog2SMin;
+  if (l < min_log2S) l = min_log2S;
+  if (lb > 18 && l < lb - 18) l = lb - 18;
   if (opts->log2_subbin != 0) l = opts->log2_subbin;
   sp.log2S = l;
   const uint64_t S = 1ull << l;
   const uint32_t l2 = opts->split_bits != 0 ? opts->split_bits : split_l2_bits();
-  const uint64_t fits = ((1ull << l2) - 1) * S + (1ull << hg::kLog2SLds) / 2;
+  // A partition's last sub-bin may take up to 2^13 keys more than S buckets
+  // hold on average.
+  const uint64_t fits = ((1ull << l2) - 1) * S + std::max<uint64_t>(S, ((1ull << hg::kLog2SLds) / 2) >> rho_log);
   if (P > 1 && (buckets + P - 1) / P <= fits) {
     sp.mode = 0;
     sp.sh1 = 0;
     sp.nd1 = P;
     return sp;
   }
-  const uint32_t lb = ceil_log2(bound < 2 ? 2 : bound);
   uint32_t sh = l + l2;                // 2^l2 sub-bins per range
   if (lb > 8 && sh < lb - 8) sh = lb - 8;  // at most 256 ranges
   if (sh > l + 10) sh = l + 10;            // at most kMaxD2 sub-bins per range
@@ -518,7 +525,7 @@ uint32_t probe_log2W(hg_key_type kt, uint64_t n, uint64_t buckets) {
   const uint64_t kcap = hg::kProbeKeyCapBytes / key_bytes(kt);
   const double per_bucket = buckets ? static_cast<double>(n) / static_cast<double>(buckets) : 1.0;
   uint32_t l = hg::kMaxLog2W;
-  while (l > 6 && static_cast<double>(1u << l) * (per_bucket * 1.1 + 0.01) > static_cast<double>(kcap)) --l;
+  while (l > 0 && static_cast<double>(1u << l) * (per_bucket * 1.1 + 0.01) > static_cast<double>(kcap)) --l;
   return l;
 }
 
@@ -659,7 +666,7 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
   // coarse range keeps at most kMaxD2 of them.
   const uint32_t log2W = probe_log2W(kt, t->n, t->buckets_bound);
   if (sp.mode == 1) {
-    while (sp.log2S > log2W && sp.log2S > hg::kLog2SMin && sp.sh1 - (sp.log2S - 1) <= 10) --sp.log2S;
+    while (sp.log2S > log2W && sp.sh1 - (sp.log2S - 1) <= 10) --sp.log2S;
     // Narrower sub-bins mean more level-2 digits per coarse range and
     // shorter runs in the level-2 split and gather; narrower ranges take
     // them back while the level-1 split keeps at most 256 digits (the
@@ -719,7 +726,9 @@ hg_status probe_sorted(const hg_table* t, const void* queries, uint32_t q, void*
 bool use_sorted_probe(const hg_table* t, uint64_t q, uint32_t flags) {
   if (flags & HG_PROBE_DIRECT) return false;
   if (flags & HG_PROBE_SORTED) return true;
-  return t->buckets_bound >= (1ull << 22) && q >= (1ull << 20);
+  // Large tables, or tables of long buckets (a direct probe searches each
+  // query's bucket in global memory).
+  return q >= (1ull << 20) && (t->buckets_bound >= (1ull << 22) || t->n >= 16 * t->buckets_bound);
 }
 
 hg_status probe(const hg_table* t, const void* d_queries, uint64_t q, void* d_out, bool count, uint32_t flags,
@@ -899,8 +908,11 @@ static hg_status build_impl(const void* d_keys, uint64_t n, hg_key_type kt, cons
 
   const SplitParams sp = split_params(P, n, bound, opts);
   uint32_t* offs = static_cast<uint32_t*>(offsets);
+  // Large tables, or tables of long buckets (the atomic histogram and
+  // scatter then serialise on few counters).
   const bool sorted = (opts->flags & HG_BUILD_SORTED) != 0 ||
-                      ((opts->flags & HG_BUILD_ATOMIC) == 0 && bound >= (1ull << 22) && n >= (1ull << 20));
+                      ((opts->flags & HG_BUILD_ATOMIC) == 0 && n >= (1ull << 20) &&
+                       (bound >= (1ull << 22) || n >= 16 * bound));
   if (sorted) {
     st = build_sorted(d_keys, n32, kt, P, log2P, opts, plain_V, bound, sp, like_desc, po, bb, desc, offs, keys_out,
                       long_ctr, long_list, mem, stream);
@@ -1071,7 +1083,9 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   HG_LAUNCH("batch_layout", stream,
             hg::launch_batch_layout(d_table_offsets, T, n32, opts->ratio_num, opts->ratio_den, po, bb, desc, stream));
 
-  const SplitParams sp = split_params(1, n, bound, opts);  // sub-bin size from the batch's keys per bucket
+  // Sub-bin size from the batch's keys per bucket; a table's sub-bins stay at
+  // 2^kLog2SMin buckets or more, so that its segment has at most kMaxD2.
+  const SplitParams sp = split_params(1, n, bound, opts, hg::kLog2SMin);
   L2Bufs w;
   st = alloc_l2(mem, n, kt, T, bound, sp.log2S, w);
   if (st != HG_OK) return st;

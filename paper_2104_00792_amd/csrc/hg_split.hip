@@ -1750,19 +1750,24 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 // --------------------------------------------------------- long buckets
 // Buckets with more than kLongT keys are sorted in place, so that a probe
 // counts them with two binary searches (the order inside a bucket is free).
-// One workgroup per long bucket, taken from a work counter:
+// Buckets of at most kWaveLong keys are taken by single waves first
+// (k_long_small: runs, or a sort in registers up to wave_sort_max keys);
+// the rest, and those a wave could neither rewrite nor sort, take one
+// workgroup each, from a work counter (k_long_sort):
 //   1. the distinct keys of the bucket and their multiplicities, found by
 //      leader election in each wave (one round per distinct key in the
 //      wave's 64 keys) and merged into a set of at most kSetMax;
 //   2. the bucket rewritten as runs of those keys in ascending order (not
 //      needed for a single distinct key);
 //   3. a bucket with more distinct keys is bitonic-sorted in LDS when it has
-//      at most kSortCap keys, and otherwise listed as unsorted.
+//      at most sort_cap<K>() keys (64 KiB), and otherwise listed as
+//      unsorted.
 // A bucket of more than kBigChunk keys is queued instead, in chunks: every
 // chunk finds its own distinct keys (k_big_scan), one workgroup per bucket
 // merges them and lays out the runs (k_big_fix), and every chunk rewrites
 // its range (k_big_write).
-constexpr uint32_t kSortCap = 4096;
+template <typename K>
+constexpr uint32_t sort_cap() { return 65536u / sizeof(K); }
 
 template <typename K>
 __device__ __forceinline__ K readlane_key(K v, uint32_t lane);
@@ -1777,17 +1782,99 @@ __device__ __forceinline__ uint64_t readlane_key<uint64_t>(uint64_t v, uint32_t 
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Adds (v, c) to the set of wave-owned slots sv/sc (size *sz), the whole wave
-// searching in parallel.  Returns false when the set is full.
+// The value of lane (this lane ^ j) (j < 64), through ds_bpermute.
 template <typename K>
-__device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, uint32_t c) {
+__device__ __forceinline__ K lane_xor(K v, uint32_t j);
+template <>
+__device__ __forceinline__ uint32_t lane_xor<uint32_t>(uint32_t v, uint32_t j) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_ds_bpermute(static_cast<int>((lane_id() ^ j) << 2), static_cast<int>(v)));
+}
+template <>
+__device__ __forceinline__ uint64_t lane_xor<uint64_t>(uint64_t v, uint32_t j) {
+  const int a = static_cast<int>((lane_id() ^ j) << 2);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a, static_cast<int>(static_cast<uint32_t>(v))));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(a, static_cast<int>(static_cast<uint32_t>(v >> 32))));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Bitonic sort, ascending, of the 64 * KPL keys a wave holds in registers:
+// element e = 64 r + lane sits in v[r].  A compare-exchange at distance
+// 2^lj < 64 pairs lanes (one lane exchange per register), one at 64 or more
+// pairs registers of the same lane.  Both exponent loops are unrolled, so
+// every register index is a constant.
+template <typename K, int KPL>
+__device__ __forceinline__ void wave_bitonic(K (&v)[KPL]) {
+  constexpr int kLog2N = 6 + (KPL >= 2) + (KPL >= 4) + (KPL >= 8) + (KPL >= 16) + (KPL >= 32);
+  static_assert((64 * KPL) == (1 << kLog2N), "KPL is a power of two up to 32");
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int lk = 1; lk <= kLog2N; ++lk) {
+#pragma unroll
+    for (int lj = lk - 1; lj >= 0; --lj) {
+      if (lj >= 6) {
+        const int jr = 1 << (lj - 6);
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          if ((r & jr) == 0) {
+            // Elements 64 r + l and 64 (r + jr) + l; the direction bit
+            // (element & 2^lk, lk > 6) depends on r alone.
+            const bool up = ((r << 6) & (1 << lk)) == 0;
+            const K a = v[r], b = v[r + jr];
+            const bool sw = (a > b) == up;
+            v[r] = sw ? b : a;
+            v[r + jr] = sw ? a : b;
+          }
+        }
+      } else {
+        const uint32_t j = 1u << lj;
+        const bool lower = (l & j) == 0;  // this lane holds the smaller element of its pair
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const K o = lane_xor<K>(v[r], j);
+          const uint32_t e = (static_cast<uint32_t>(r) << 6) | l;
+          const bool up = (e & (1u << lk)) == 0;
+          // Ascending pairs keep the smaller key in the lower element.
+          v[r] = (lower == up) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+        }
+      }
+    }
+  }
+}
+
+// Sorts keys[lo, lo + L) (64 (KPL / 2) < L <= 64 KPL) by one wave: the keys
+// are padded with the largest key, sorted in registers and the first L
+// written back (padding equals the largest key, so the first L hold the
+// bucket's own multiset).
+template <typename K, int KPL>
+__device__ __forceinline__ void wave_sort_range(K* __restrict__ keys, uint32_t lo, uint32_t L) {
+  const uint32_t l = lane_id();
+  K v[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    const uint32_t e = (static_cast<uint32_t>(r) << 6) | l;
+    v[r] = e < L ? keys[lo + e] : ~K(0);
+  }
+  wave_bitonic<K, KPL>(v);
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    const uint32_t e = (static_cast<uint32_t>(r) << 6) | l;
+    if (e < L) keys[lo + e] = v[r];
+  }
+}
+
+// Adds (v, c) to the set of wave-owned slots sv/sc (size *sz, at most cap <=
+// kSetMax), the whole wave searching in parallel.  Returns false when the
+// set is full.
+template <typename K>
+__device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, uint32_t c, uint32_t cap = kSetMax) {
   const uint32_t l = lane_id();
   const uint32_t n = wave_uniform(*sz);
   const uint64_t hit = ballot(l < n && sv[l] == v);
   if (hit != 0) {
     if (l == static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(hit)) - 1)) sc[l] += c;
   } else {
-    if (n >= kSetMax) return false;
+    if (n >= cap) return false;
     if (l == 0) {
       sv[n] = v;
       sc[n] = c;
@@ -1805,10 +1892,10 @@ __device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, 
 // key it met and that key's pending count in registers, and touches the set
 // only when the key changes (a run of one heavy key costs a ballot per 64
 // keys); it reads kGroups groups of 64 keys per round, all loads in flight
-// before the first is used.
+// before the first is used.  The set holds at most cap keys.
 template <typename K>
 __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_t first, uint32_t b, uint32_t step, K* sv,
-                              uint32_t* sc, uint32_t* sz, const uint32_t* stop) {
+                              uint32_t* sc, uint32_t* sz, const uint32_t* stop, uint32_t cap = kSetMax) {
   constexpr int kGroups = 8;
   const uint32_t l = lane_id();
   K last = K(0);
@@ -1837,7 +1924,7 @@ __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_
         const K v = readlane_key(key, leader);
         const uint64_t match = ballot(valid && key == v) & active;
         active &= ~match;
-        if (pend != 0 && !set_add(sv, sc, sz, last, pend)) {
+        if (pend != 0 && !set_add(sv, sc, sz, last, pend, cap)) {
           ok = false;
           break;
         }
@@ -1846,7 +1933,7 @@ __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_
       }
     }
   }
-  if (ok && pend != 0 && !set_add(sv, sc, sz, last, pend)) ok = false;
+  if (ok && pend != 0 && !set_add(sv, sc, sz, last, pend, cap)) ok = false;
   return ok;
 }
 
@@ -1961,35 +2048,71 @@ BigWork<K> big_work(uint32_t* base, uint64_t n) {
   return w;
 }
 
-// Long buckets of at most kWaveLong keys, one wave each: distinct keys
-// (ballots into the wave's set), then the runs in ascending order written
-// by the whole wave.  A bucket with more than kSetMax distinct keys moves to
-// the list of longer buckets (the workgroups of k_long_sort).
+// Long buckets of up to this many keys are sorted by one wave in registers
+// when they have more than kWaveProbe distinct keys (64 KPL keys per lane,
+// KPL <= 32 for 32-bit keys and <= 16 for 64-bit ones).
 template <typename K>
-__global__ __launch_bounds__(kLongThreads) void k_long_small(const uint32_t* __restrict__ offsets,
-                                                             uint32_t* __restrict__ ctr, uint32_t* __restrict__ list,
-                                                             K* __restrict__ keys, uint32_t* __restrict__ unsorted) {
-  constexpr int W = kLongThreads / kWave;
+constexpr uint32_t wave_sort_max() { return sizeof(K) == 4 ? 2048u : 1024u; }
+constexpr uint32_t kWaveProbe = 16;
+constexpr int kLongWaveThreads = 256;
+
+// Sorts keys[lo, lo + L) by one wave (kLongT < L <= wave_sort_max<K>()).
+template <typename K>
+__device__ __forceinline__ void wave_sort_bucket(K* __restrict__ keys, uint32_t lo, uint32_t L) {
+  if (L <= 128)
+    wave_sort_range<K, 2>(keys, lo, L);
+  else if (L <= 256)
+    wave_sort_range<K, 4>(keys, lo, L);
+  else if (L <= 512)
+    wave_sort_range<K, 8>(keys, lo, L);
+  else if (L <= 1024)
+    wave_sort_range<K, 16>(keys, lo, L);
+  else if constexpr (wave_sort_max<K>() >= 2048)
+    wave_sort_range<K, 32>(keys, lo, L);
+}
+
+// Long buckets of at most kWaveLong keys (the front of the list), one wave
+// each.  SORT: the buckets of at most wave_sort_max<K>() keys; their
+// distinct keys are searched for up to kWaveProbe of them (a few ballot
+// rounds), and a bucket with more is sorted by the wave.  !SORT: the longer
+// ones; up to kSetMax distinct keys, and a bucket with more moves to the
+// back of the list (the workgroups of k_long_sort).  A bucket whose
+// distinct keys were all found is rewritten as their runs in ascending
+// order by the whole wave.  The two instances read the same list, each
+// skipping the other's buckets, so the sorting instance's registers do not
+// lower the occupancy of the other, which serves runs of heavy keys.
+template <typename K, int THREADS, bool SORT>
+__global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint32_t* __restrict__ offsets,
+                                                                    uint32_t* __restrict__ ctr,
+                                                                    uint32_t* __restrict__ list, K* __restrict__ keys,
+                                                                    uint32_t* __restrict__ unsorted) {
+  constexpr int W = THREADS / kWave;
   __shared__ K sval[W][kSetMax];
   __shared__ uint32_t scnt[W][kSetMax];
   __shared__ uint32_t ssize[W];
   const uint32_t w = threadIdx.x / kWave, l = lane_id();
   const uint32_t total = ctr[0];
   // Whether the table has a long bucket: some bucket was listed, at the
-  // front (ctr[0], not changed here) or at the back (ctr[2], which this
-  // kernel only raises, and only when ctr[0] is nonzero).
-  if (blockIdx.x == 0 && threadIdx.x == 0) unsorted[kHasLongWord] = (total | ctr[2]) != 0 ? 1u : 0u;
+  // front (ctr[0], not changed here) or at the back (ctr[2], which the
+  // !SORT instance only raises, and only when ctr[0] is nonzero).
+  if (!SORT && blockIdx.x == 0 && threadIdx.x == 0) unsorted[kHasLongWord] = (total | ctr[2]) != 0 ? 1u : 0u;
   // Wave i takes list entries i, i + (waves in the grid), ...: no claims
   // through a shared counter (the buckets are at most kWaveLong keys, so a
   // fixed deal stays balanced).  The loop is uniform over the wave.
   const uint32_t waves = gridDim.x * W;
   for (uint32_t idx = blockIdx.x * W + wave_uniform(w); idx < total; idx += waves) {
     const uint32_t g = wave_uniform(list[idx]);
-    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+    // Uniform over the wave: the sort's lane exchanges need every lane.
+    const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
+    if ((L <= wave_sort_max<K>()) != SORT) continue;  // the other instance's bucket
     if (l == 0) ssize[w] = 0;
     __builtin_amdgcn_wave_barrier();
-    if (!wave_distinct<K>(keys + lo, 0, L, kWave * 8, sval[w], scnt[w], &ssize[w], nullptr)) {
-      if (l == 0) list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
+    if (!wave_distinct<K>(keys + lo, 0, L, kWave * 8, sval[w], scnt[w], &ssize[w], nullptr,
+                          SORT ? kWaveProbe : kSetMax)) {
+      if (SORT)
+        wave_sort_bucket<K>(keys, lo, L);
+      else if (l == 0)
+        list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
       continue;
     }
     const uint32_t nd = wave_uniform(ssize[w]);
@@ -2019,7 +2142,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   __shared__ uint32_t run0[kSetMax + 1];
   __shared__ uint32_t soverflow;
   __shared__ uint32_t sidx;
-  __shared__ K sbuf[kSortCap];
+  __shared__ K sbuf[sort_cap<K>()];
   const uint32_t t = threadIdx.x;
   const uint32_t total = ctr[2], cap = ctr[4];
   for (;;) {
@@ -2061,7 +2184,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
         while (a + 1 < nd && run0[a + 1] <= i) ++a;
         keys[lo + i] = sval[1][a];
       }
-    } else if (L <= kSortCap) {
+    } else if (L <= sort_cap<K>()) {
       // many distinct keys, few enough to sort in LDS
       uint32_t p2 = 1;
       while (p2 < L) p2 <<= 1;
@@ -2449,7 +2572,10 @@ hipError_t long_sort_typed(const uint32_t* offsets, uint32_t* ctr, uint32_t* lis
   const BigWork<K> bw = big_work<K>(big, n);
   hipError_t e = launch_fill_u32(bw.ctr, 2, 0u, s);
   if (e != hipSuccess) return e;
-  k_long_small<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
+  k_long_small<K, kLongWaveThreads, true>
+      <<<kLongGrid * (kLongThreads / kLongWaveThreads), kLongWaveThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_long_small<K, kLongThreads, false><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted, bw);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -101,6 +101,20 @@ def test_ratios(gpu, ratio, P, build):
 
 
 @pytest.mark.parametrize("build", sorted(BUILDS))
+@pytest.mark.parametrize("occ", [16, 64, 256, 1024, 4096])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64], ids=["u32", "u64"])
+@pytest.mark.parametrize("P", [1, 16])
+def test_high_occupancy(gpu, occ, dtype, P, build):
+    """The duplicate study of Sec. 5.4 in small: the hash range shrunk so
+    that about `occ` keys share a bucket (V_p = n_p / occ).  Sorted builds
+    then take sub-bins of fewer buckets (about 2^13 keys each), nearly every
+    bucket is long and sorted in place, and sorted probes take windows of
+    fewer buckets."""
+    n = (1 << 20) + 333
+    check_table(gpu, make_keys("uniform", n, dtype, 23 + occ), P=P, num=1, den=occ, build=build)
+
+
+@pytest.mark.parametrize("build", sorted(BUILDS))
 @pytest.mark.parametrize("V", [1, 2, 3, 1000, (1 << 20) + 1, 1 << 22])
 def test_explicit_bucket_count(gpu, V, build):
     n = 30000
@@ -220,8 +234,18 @@ LONG_CASES = {
     "one_key_100k": lambda: (np.full(100000, 7, np.uint64), 0),
     # many distinct keys, at most 4096 per bucket: bitonic sort in LDS
     "bitonic_V8": lambda: (make_keys("uniform", 20000, np.uint64, 8), 8),
-    # many distinct keys in buckets longer than 4096: left unsorted, scanned
+    # many distinct keys, about 6700 per bucket: bitonic sort in LDS by a
+    # workgroup
     "unsorted_V3": lambda: (make_keys("uniform", 20000, np.uint64, 9), 3),
+    # many distinct keys in buckets of about 20000 (more than the LDS sort
+    # holds, fewer than a chunked bucket): left unsorted, scanned
+    "unsorted_V2": lambda: (make_keys("uniform", 40000, np.uint64, 11), 2),
+    # many distinct keys, sorted by one wave in registers: about 105, 700
+    # and 1750 keys per bucket (1750: 32 keys per lane for 32-bit keys, a
+    # workgroup's LDS sort for 64-bit ones)
+    "wave_sort_V10000": lambda: (make_keys("uniform", 1 << 20, np.uint64, 12), 10000),
+    "wave_sort_V1500": lambda: (make_keys("uniform", 1 << 20, np.uint64, 13), 1500),
+    "wave_sort_V600": lambda: (make_keys("uniform", 1 << 20, np.uint64, 14), 600),
     "mixed_70x100_V2": lambda: (np.repeat(np.arange(70, dtype=np.uint64) * 977, 100), 2),
     # 4096 buckets of about 256 distinct keys: every one overflows the
     # wave's set and moves to the back of the shared long-bucket list, which
@@ -248,7 +272,7 @@ LONG_CASES = {
 def test_long_buckets(gpu, case, dtype, build):
     """Buckets longer than 64 keys: exact counts through both probes, and in
     the raw table every long bucket the build could sort (at most 64 distinct
-    keys, or at most 4096 keys) is ascending."""
+    keys, or at most 64 KiB of keys) is ascending."""
     import torch
 
     keys, V = LONG_CASES[case]()
@@ -261,7 +285,7 @@ def test_long_buckets(gpu, case, dtype, build):
     offs, tk = offs.cpu().numpy().astype(np.int64), tk.cpu().numpy()
     for g in np.nonzero(np.diff(offs) > 64)[0]:
         seg = tk[offs[g]:offs[g + 1]]
-        if np.unique(seg).size <= 64 or seg.size <= 4096:
+        if np.unique(seg).size <= 64 or seg.size <= 65536 // np.dtype(dtype).itemsize:
             assert np.all(seg[1:] >= seg[:-1]), f"long bucket {g} of {seg.size} keys is not sorted"
     t.free()
 
