@@ -56,10 +56,13 @@ static_assert(kLongT < 256, "a count of a table without long buckets fits a byte
 // ones by a workgroup.  Their ids share one list (the short ones from the
 // front, the others from the back) of long_list_cap(n) entries, after
 // kLongCtr counter words: [0] short ones, [2] long ones, [3] the work
-// counter of the long ones, [4] the list's length ([1], [5..7] unused).
+// counter of the long ones, [4] the list's length, [5] the ones listed for
+// a workgroup's register sort, placed right after the short ones ([1],
+// [6..7] unused).  A bucket appears at most once in each of the three, so
+// three entries per possible long bucket always suffice.
 constexpr uint32_t kWaveLong = 4096;
 constexpr uint32_t kLongCtr = 8;
-inline uint64_t long_list_cap(uint64_t n) { return 2 * (n / (kLongT + 1) + 1); }
+inline uint64_t long_list_cap(uint64_t n) { return 3 * (n / (kLongT + 1) + 1); }
 constexpr int kLongThreads = 1024;
 constexpr uint32_t kLongGrid = 512;  // resident workgroups (two per CU)
 

@@ -864,6 +864,46 @@ __device__ __forceinline__ void note_long(uint32_t* ctr, uint32_t* list, uint32_
     list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
 }
 
+// note_long for the buckets g0 + k (k < CPT, c[k] keys each) of every lane
+// of a wave, with one atomic per end of the list and wave: the lanes' numbers
+// of front and back entries (at most CPT each) are scanned across the wave
+// in one word, and the last lane reserves the wave's entries.  Every lane of
+// the wave calls it.
+template <int CPT>
+__device__ __forceinline__ void note_long_wave(uint32_t* ctr, uint32_t* list, uint32_t g0, const uint32_t (&c)[CPT]) {
+  static_assert(CPT <= 16 && CPT * kWave < 65536, "one mask word; per-wave totals fit 16 bits");
+  uint32_t mx = 0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) mx = max(mx, c[k]);
+  if (ballot(mx > kLongT) == 0) return;  // uniform: no long bucket in the wave (the common case)
+  // Bit k: bucket g0 + k goes to the front; bit 16 + k: to the back.  The
+  // counters are dead once the mask holds them.
+  uint32_t marks = 0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    marks |= ((c[k] > kLongT && c[k] <= kWaveLong) ? 1u : 0u) << k;
+    marks |= (c[k] > kWaveLong ? 1u : 0u) << (16 + k);
+  }
+  const uint32_t own = static_cast<uint32_t>(__popc(marks & 0xFFFFu)) | (static_cast<uint32_t>(__popc(marks >> 16)) << 16);
+  const uint32_t incl = wave_inclusive_sum(own);
+  const uint32_t tot = wave_uniform(readlane(incl, kWave - 1));
+  uint32_t basef = 0, baseb = 0;
+  if (lane_id() == kWave - 1) {
+    if ((tot & 0xFFFFu) != 0) basef = atomicAdd(&ctr[0], tot & 0xFFFFu);
+    if ((tot >> 16) != 0) baseb = atomicAdd(&ctr[2], tot >> 16);
+  }
+  basef = readlane(basef, kWave - 1);
+  baseb = readlane(baseb, kWave - 1);
+  const uint32_t ex = incl - own;
+  uint32_t f = basef + (ex & 0xFFFFu), b = baseb + (ex >> 16);
+  const uint32_t cap = ctr[4];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if ((marks >> k) & 1u) list[f++] = g0 + k;
+    if ((marks >> (16 + k)) & 1u) list[cap - 1 - b++] = g0 + k;
+  }
+}
+
 // The keys of one sub-bin, each with its position p < m packed as 16-bit
 // halves of pos (key j in half j & 1 of word j >> 1), staged in LDS in
 // position order and written to out[0 .. m) in whole lines, in chunks of
@@ -970,8 +1010,9 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       for (int k = 0; k < CPT; ++k) sum += c[k];
       if constexpr (sizeof(K) == 4) {
         // 32-bit keys: the register path holds this kernel at 64 VGPRs
-        // (eight waves per SIMD), with no room for the reservation below,
-        // so each long bucket appends itself.
+        // (eight waves per SIMD), with no room for the workgroup reservation
+        // below; the long buckets are appended per wave instead (one atomic
+        // per end and wave, from a lane scan of the threads' numbers).
         uint32_t total;
         uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
 #pragma unroll
@@ -984,9 +1025,7 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
           ex = q.w + c[4 * x + 3];
           lds4[CQ * t + x] = q;
         }
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-          if (c[k] > kLongT) note_long(long_count, long_list, sb.gA + CPT * t + k, c[k]);
+        note_long_wave<CPT>(long_count, long_list, sb.gA + CPT * t, c);
         __syncthreads();
       } else {
         // One scan carries three sums: keys (bits 0-15, at most
@@ -1891,12 +1930,16 @@ __device__ __forceinline__ bool set_add(K* sv, uint32_t* sc, uint32_t* sz, K v, 
 // turns nonzero: another wave's set overflowed).  The wave keeps the last
 // key it met and that key's pending count in registers, and touches the set
 // only when the key changes (a run of one heavy key costs a ballot per 64
-// keys); it reads kGroups groups of 64 keys per round, all loads in flight
-// before the first is used.  The set holds at most cap keys.
+// keys); it reads kDistinctGroups groups of 64 keys per round, all loads in
+// flight before the first is used.  The set holds at most cap keys.  `pre`,
+// when given, holds the first round's keys, already loaded as the loop
+// would load them.
+constexpr int kDistinctGroups = 8;
 template <typename K>
 __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_t first, uint32_t b, uint32_t step, K* sv,
-                              uint32_t* sc, uint32_t* sz, const uint32_t* stop, uint32_t cap = kSetMax) {
-  constexpr int kGroups = 8;
+                              uint32_t* sc, uint32_t* sz, const uint32_t* stop, uint32_t cap = kSetMax,
+                              const K* pre = nullptr) {
+  constexpr int kGroups = kDistinctGroups;
   const uint32_t l = lane_id();
   K last = K(0);
   uint32_t pend = 0;
@@ -1906,8 +1949,13 @@ __device__ __forceinline__ bool wave_distinct(const K* __restrict__ src, uint32_
     K kv[kGroups];
     // All kGroups loads in flight: a lane past b re-reads src[b - 1] (c0 < b)
     // and is not valid below.
+    if (pre != nullptr && c0 == first) {
 #pragma unroll
-    for (int gi = 0; gi < kGroups; ++gi) kv[gi] = src[min(c0 + gi * kWave + l, b - 1)];
+      for (int gi = 0; gi < kGroups; ++gi) kv[gi] = pre[gi];
+    } else {
+#pragma unroll
+      for (int gi = 0; gi < kGroups; ++gi) kv[gi] = src[min(c0 + gi * kWave + l, b - 1)];
+    }
 #pragma unroll
     for (int gi = 0; gi < kGroups; ++gi) {
       const uint32_t i = c0 + gi * kWave + l;
@@ -2048,12 +2096,84 @@ BigWork<K> big_work(uint32_t* base, uint64_t n) {
   return w;
 }
 
+// Bitonic sort, ascending, of the THREADS * KPL keys a workgroup holds in
+// registers: element e = KPL t + r sits in v[r] of thread t (a thread holds
+// KPL consecutive elements).  A compare-exchange at distance j pairs
+// registers of one thread (j < KPL), lanes of one wave (j < 64 KPL: one lane
+// exchange per register), or threads of different waves (through `lds`, one
+// element per slot: every element written, a barrier, the partner read).
+// Both exponent loops are unrolled.  Every thread of the workgroup calls it.
+template <typename K, int THREADS, int KPL>
+__device__ __forceinline__ void wg_bitonic(K (&v)[KPL], K* lds) {
+  constexpr int kLog2KPL = (KPL >= 2) + (KPL >= 4) + (KPL >= 8) + (KPL >= 16);
+  constexpr int kLog2T = 6 + (THREADS >= 128) + (THREADS >= 256) + (THREADS >= 512) + (THREADS >= 1024);
+  constexpr int kLog2N = kLog2KPL + kLog2T;
+  static_assert((1 << kLog2KPL) == KPL && (1 << kLog2T) == THREADS, "powers of two");
+  const uint32_t l = lane_id();
+  const uint32_t base = threadIdx.x * KPL;
+#pragma unroll
+  for (int lk = 1; lk <= kLog2N; ++lk) {
+#pragma unroll
+    for (int lj = lk - 1; lj >= 0; --lj) {
+      const uint32_t j = 1u << lj;
+      if (lj < kLog2KPL) {
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          if ((r & static_cast<int>(j)) == 0) {
+            const bool up = ((base + r) & (1u << lk)) == 0;
+            const K a = v[r], b = v[r + j];
+            const bool sw = (a > b) == up;
+            v[r] = sw ? b : a;
+            v[r + j] = sw ? a : b;
+          }
+        }
+      } else if (lj < kLog2KPL + 6) {
+        const uint32_t jl = j >> kLog2KPL;  // distance in lanes
+        const bool lower = (l & jl) == 0;   // this lane holds the smaller elements of its pairs
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const K o = lane_xor<K>(v[r], jl);
+          const bool up = ((base + r) & (1u << lk)) == 0;
+          v[r] = (lower == up) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+        }
+      } else {
+        __syncthreads();  // the previous exchange's reads are done
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) lds[base + r] = v[r];
+        __syncthreads();
+        const bool lower = (base & j) == 0;  // j >= 64 KPL: the same for all r
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const K o = lds[(base + r) ^ j];
+          const bool up = ((base + r) & (1u << lk)) == 0;
+          v[r] = (lower == up) ? (o < v[r] ? o : v[r]) : (o > v[r] ? o : v[r]);
+        }
+      }
+    }
+  }
+}
+
+// Sorts keys[lo, lo + L) (L <= THREADS KPL) by the workgroup: the keys are
+// padded with the largest key, sorted in registers and the first L written
+// back.  `lds` holds THREADS KPL keys.  Every thread calls it.
+template <typename K, int THREADS, int KPL>
+__device__ __forceinline__ void wg_sort_range(K* __restrict__ keys, uint32_t lo, uint32_t L, K* lds) {
+  const uint32_t base = threadIdx.x * KPL;
+  K v[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) v[r] = base + r < L ? keys[lo + base + r] : ~K(0);
+  wg_bitonic<K, THREADS, KPL>(v, lds);
+#pragma unroll
+  for (int r = 0; r < KPL; ++r)
+    if (base + r < L) keys[lo + base + r] = v[r];
+}
+
 // Long buckets of up to this many keys are sorted by one wave in registers
-// when they have more than kWaveProbe distinct keys (64 KPL keys per lane,
-// KPL <= 32 for 32-bit keys and <= 16 for 64-bit ones).
+// when no key dominates them (64 KPL keys per lane, KPL <= 32 for 32-bit
+// keys and <= 16 for 64-bit ones).
 template <typename K>
 constexpr uint32_t wave_sort_max() { return sizeof(K) == 4 ? 2048u : 1024u; }
-constexpr uint32_t kWaveProbe = 16;
+constexpr uint32_t kListDone = 0xFFFFFFFFu;  // a front-list entry the runs instance finished
 constexpr int kLongWaveThreads = 256;
 
 // Sorts keys[lo, lo + L) by one wave (kLongT < L <= wave_sort_max<K>()).
@@ -2072,15 +2192,17 @@ __device__ __forceinline__ void wave_sort_bucket(K* __restrict__ keys, uint32_t 
 }
 
 // Long buckets of at most kWaveLong keys (the front of the list), one wave
-// each.  SORT: the buckets of at most wave_sort_max<K>() keys; their
-// distinct keys are searched for up to kWaveProbe of them (a few ballot
-// rounds), and a bucket with more is sorted by the wave.  !SORT: the longer
-// ones; up to kSetMax distinct keys, and a bucket with more moves to the
-// back of the list (the workgroups of k_long_sort).  A bucket whose
-// distinct keys were all found is rewritten as their runs in ascending
-// order by the whole wave.  The two instances read the same list, each
-// skipping the other's buckets, so the sorting instance's registers do not
-// lower the occupancy of the other, which serves runs of heavy keys.
+// each, in two launches over the same list.  !SORT (first): buckets in which
+// one key dominates (at least half of the first 64 keys equal the key of
+// lane 0, 21 or 42: a heavy key and a few others), or longer than
+// wave_sort_max<K>(); their
+// distinct keys are found by ballots, up to kSetMax, and the bucket is
+// rewritten as their runs in ascending order by the whole wave, or, with
+// more, moves to the back of the list (the workgroups of k_long_sort).  Its
+// entries are then marked done.  SORT: every entry not marked, sorted by the
+// wave in registers; a wave reads 64 entries per load and passes the marked
+// ones by a ballot.  The sorting instance's registers thus lower neither the
+// occupancy of the other nor the cost of passing its entries.
 template <typename K, int THREADS, bool SORT>
 __global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint32_t* __restrict__ offsets,
                                                                     uint32_t* __restrict__ ctr,
@@ -2096,23 +2218,46 @@ __global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint
   // front (ctr[0], not changed here) or at the back (ctr[2], which the
   // !SORT instance only raises, and only when ctr[0] is nonzero).
   if (!SORT && blockIdx.x == 0 && threadIdx.x == 0) unsorted[kHasLongWord] = (total | ctr[2]) != 0 ? 1u : 0u;
+  const uint32_t waves = gridDim.x * W;
+  if (SORT) {
+    // Wave i reads entries 64 i .. 64 i + 63, then 64 (i + waves) .., in one
+    // load each, and sorts the buckets not marked done one after another.
+    for (uint32_t c0 = (blockIdx.x * W + wave_uniform(w)) * kWave; c0 < total; c0 += waves * kWave) {
+      const uint32_t gl = c0 + l < total ? list[c0 + l] : kListDone;
+      for (uint64_t todo = ballot(gl != kListDone); todo != 0; todo &= todo - 1) {
+        const uint32_t g = readlane(gl, static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(todo)) - 1));
+        // Uniform over the wave: the sort's lane exchanges need every lane.
+        const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
+        wave_sort_bucket<K>(keys, lo, L);
+      }
+    }
+    return;
+  }
   // Wave i takes list entries i, i + (waves in the grid), ...: no claims
   // through a shared counter (the buckets are at most kWaveLong keys, so a
   // fixed deal stays balanced).  The loop is uniform over the wave.
-  const uint32_t waves = gridDim.x * W;
   for (uint32_t idx = blockIdx.x * W + wave_uniform(w); idx < total; idx += waves) {
     const uint32_t g = wave_uniform(list[idx]);
-    // Uniform over the wave: the sort's lane exchanges need every lane.
     const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
-    if ((L <= wave_sort_max<K>()) != SORT) continue;  // the other instance's bucket
-    if (l == 0) ssize[w] = 0;
+    // The distinct search's first round of keys, loaded once: its first 64
+    // keys also decide whether one key dominates.
+    K kv0[kDistinctGroups];
+#pragma unroll
+    for (int gi = 0; gi < kDistinctGroups; ++gi) kv0[gi] = keys[lo + min(gi * kWave + l, L - 1)];
+    // Three candidates, so that a rare key in lane 0 does not hide a heavy one.
+    const uint32_t m0 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 0)));
+    const uint32_t m1 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 21)));
+    const uint32_t m2 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 42)));
+    const bool heavy = max(m0, max(m1, m2)) >= kWave / 2;
+    if (L <= wave_sort_max<K>() && !heavy) continue;  // the sorting instance's bucket
+    if (l == 0) {
+      ssize[w] = 0;
+      list[idx] = kListDone;  // read only by the sorting instance, after this kernel
+    }
     __builtin_amdgcn_wave_barrier();
-    if (!wave_distinct<K>(keys + lo, 0, L, kWave * 8, sval[w], scnt[w], &ssize[w], nullptr,
-                          SORT ? kWaveProbe : kSetMax)) {
-      if (SORT)
-        wave_sort_bucket<K>(keys, lo, L);
-      else if (l == 0)
-        list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
+    if (!wave_distinct<K>(keys + lo, 0, L, kWave * kDistinctGroups, sval[w], scnt[w], &ssize[w], nullptr, kSetMax,
+                          kv0)) {
+      if (l == 0) list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
       continue;
     }
     const uint32_t nd = wave_uniform(ssize[w]);
@@ -2133,7 +2278,7 @@ __global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __restrict__ offsets,
                                                             uint32_t* __restrict__ ctr,
-                                                            const uint32_t* __restrict__ list, K* __restrict__ keys,
+                                                            uint32_t* __restrict__ list, K* __restrict__ keys,
                                                             uint32_t* __restrict__ unsorted, BigWork<K> bw) {
   constexpr int W = kLongThreads / kWave;
   __shared__ K sval[W][kSetMax];
@@ -2142,7 +2287,6 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   __shared__ uint32_t run0[kSetMax + 1];
   __shared__ uint32_t soverflow;
   __shared__ uint32_t sidx;
-  __shared__ K sbuf[sort_cap<K>()];
   const uint32_t t = threadIdx.x;
   const uint32_t total = ctr[2], cap = ctr[4];
   for (;;) {
@@ -2150,8 +2294,8 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
     __syncthreads();
     const uint32_t idx = wave_uniform(sidx);
     if (idx >= total) break;  // uniform: every thread read the same sidx
-    const uint32_t g = list[cap - 1 - idx];
-    const uint32_t lo = offsets[g], L = offsets[g + 1] - lo;
+    const uint32_t g = wave_uniform(list[cap - 1 - idx]);
+    const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
     if (L > kBigChunk) {
       // Queued in chunks for the workgroups of k_big_scan.
       if (t == 0) {
@@ -2185,33 +2329,43 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
         keys[lo + i] = sval[1][a];
       }
     } else if (L <= sort_cap<K>()) {
-      // many distinct keys, few enough to sort in LDS
-      uint32_t p2 = 1;
-      while (p2 < L) p2 <<= 1;
-      for (uint32_t i = t; i < p2; i += kLongThreads) sbuf[i] = i < L ? keys[lo + i] : ~K(0);
-      __syncthreads();
-      for (uint32_t k = 2; k <= p2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-          for (uint32_t i = t; i < p2; i += kLongThreads) {
-            const uint32_t ixj = i ^ j;
-            if (ixj > i) {
-              const K a = sbuf[i], b = sbuf[ixj];
-              const bool up = (i & k) == 0;
-              if ((a > b) == up) {
-                sbuf[i] = b;
-                sbuf[ixj] = a;
-              }
-            }
-          }
-          __syncthreads();
-        }
-      }
-      for (uint32_t i = t; i < L; i += kLongThreads) keys[lo + i] = sbuf[i];
+      // many distinct keys, few enough for a workgroup's registers: listed
+      // for k_long_wgsort, in the list's free middle (after the ctr[0] front
+      // entries; the back's ctr[2] entries leave at least as many free)
+      if (t == 0) list[ctr[0] + atomicAdd(&ctr[5], 1u)] = g;
     } else if (t == 0) {
       const uint32_t u = atomicAdd(&unsorted[0], 1u);
       if (u < kMaxUnsorted) unsorted[1 + u] = g;
     }
     __syncthreads();
+  }
+}
+
+// The buckets k_long_sort listed (more than kSetMax distinct keys, at most
+// sort_cap<K>() keys): one workgroup each, sorted in registers (wg_bitonic;
+// the exchanges across waves go through LDS).  A kernel of its own, so that
+// its registers do not lower the occupancy of k_long_sort.
+template <typename K>
+__global__ __launch_bounds__(kLongThreads) void k_long_wgsort(const uint32_t* __restrict__ offsets,
+                                                              const uint32_t* __restrict__ ctr,
+                                                              const uint32_t* __restrict__ list,
+                                                              K* __restrict__ keys) {
+  __shared__ K sbuf[sort_cap<K>()];
+  const uint32_t total = ctr[5], first = ctr[0];
+  for (uint32_t idx = blockIdx.x; idx < total; idx += gridDim.x) {
+    const uint32_t g = wave_uniform(list[first + idx]);
+    const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
+    if (L <= kLongThreads)
+      wg_sort_range<K, kLongThreads, 1>(keys, lo, L, sbuf);
+    else if (L <= 2 * kLongThreads)
+      wg_sort_range<K, kLongThreads, 2>(keys, lo, L, sbuf);
+    else if (L <= 4 * kLongThreads)
+      wg_sort_range<K, kLongThreads, 4>(keys, lo, L, sbuf);
+    else if (L <= 8 * kLongThreads)
+      wg_sort_range<K, kLongThreads, 8>(keys, lo, L, sbuf);
+    else if constexpr (sort_cap<K>() >= 16 * kLongThreads)
+      wg_sort_range<K, kLongThreads, 16>(keys, lo, L, sbuf);
+    __syncthreads();  // sbuf is free for the next bucket
   }
 }
 
@@ -2572,12 +2726,14 @@ hipError_t long_sort_typed(const uint32_t* offsets, uint32_t* ctr, uint32_t* lis
   const BigWork<K> bw = big_work<K>(big, n);
   hipError_t e = launch_fill_u32(bw.ctr, 2, 0u, s);
   if (e != hipSuccess) return e;
+  k_long_small<K, kLongThreads, false><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_long_small<K, kLongWaveThreads, true>
       <<<kLongGrid * (kLongThreads / kLongWaveThreads), kLongWaveThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_long_small<K, kLongThreads, false><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_long_sort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys, unsorted, bw);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_long_wgsort<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, ctr, list, keys);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_big_scan<K><<<kLongGrid, kLongThreads, 0, s>>>(offsets, keys, bw);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -237,6 +237,11 @@ LONG_CASES = {
     # many distinct keys, about 6700 per bucket: bitonic sort in LDS by a
     # workgroup
     "unsorted_V3": lambda: (make_keys("uniform", 20000, np.uint64, 9), 3),
+    # many distinct keys, sorted by a workgroup in registers: about 3100
+    # keys per bucket (four per thread) and about 12000 (sixteen per thread
+    # for 32-bit keys; more than 64 KiB of 64-bit keys: unsorted)
+    "wg_sort_V8": lambda: (make_keys("uniform", 25000, np.uint64, 15), 8),
+    "wg_sort_V3": lambda: (make_keys("uniform", 36000, np.uint64, 16), 3),
     # many distinct keys in buckets of about 20000 (more than the LDS sort
     # holds, fewer than a chunked bucket): left unsorted, scanned
     "unsorted_V2": lambda: (make_keys("uniform", 40000, np.uint64, 11), 2),
