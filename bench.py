@@ -43,6 +43,9 @@ DESCRIPTIONS = {
                         "hg_count_batched per step",
     "copy_ceiling": "device-to-device streaming ceilings of the GPU with torch's own kernels: copy, fill and a "
                     "read-only sum over 1 GiB buffers (HIP events around each launch)",
+    "dup_sweep_u32_2^28": "the duplicate study of Sec. 5.4 on the headline's keys: n=2^28 uint32 keys uniform, P=16, "
+                          "hash range shrunk to V_p = n_p / occ for occ (average keys per bucket) = 1, 4, 16, 64, "
+                          "256, 1024, 4096; 2^28 queries at 50% hit; build and probe timed apart",
     "serving": "Poisson stream of requests, 30% builds (uint32, sizes log-uniform in [2^10, 2^24]) and 70% probes "
                "(sizes log-uniform in [2^8, 2^22], 50% hits) against earlier tables; 200 GB HBM cap with LRU "
                "eviction; 3 concurrent request streams plus one client stream; open loop at 0.8 of the "
@@ -264,6 +267,7 @@ def main():
     ap.add_argument("--cpu-sample-all", type=int, default=1 << 26, help="keys of the all-core oracle sample")
     ap.add_argument("--requests", type=int, default=100000, help="serving: requests in the stream")
     ap.add_argument("--tables", type=int, default=4096, help="batched: number of tables")
+    ap.add_argument("--occ", default=None, help="dup sweep: comma-separated keys per bucket (default: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 256 MiB once (device to device) so that a counter "
                          "run of this command also measures a plain copy of known size")
@@ -291,6 +295,8 @@ def main():
         return run_serving(args, dev)
     if args.workload == "copy_ceiling":
         return run_ceiling(args, dev)
+    if args.workload == "dup_sweep_u32_2^28":
+        return run_dup_sweep(args, dev)
 
     w = inputs.WORKLOADS[args.workload]
     n = w["n"] if args.n is None else args.n
@@ -580,6 +586,67 @@ def run_ceiling(args, dev):
                       "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
                       "config": {"workload": f"copy_ceiling: {DESCRIPTIONS['copy_ceiling']}", "bytes": nbytes},
                       "ceilings": res, "peak": HBM_PEAK_GBS}), flush=True)
+
+
+DUP_OCCUPANCIES = (1, 4, 16, 64, 256, 1024, 4096)
+
+
+def run_dup_sweep(args, dev):
+    """Build and probe rates as the hash range shrinks (the paper varies V with
+    the key count fixed; the average number of keys per bucket is n / V).
+    Per point: `steps` builds (each freed) and `steps` probes of one table,
+    each series timed with HIP events after one warm-up, and 256 sampled
+    queries checked against their exact multiplicity (a count of equal keys
+    over the whole key array, outside the timed region)."""
+    import torch
+    import paper_2104_00792_amd as hg
+    from paper_2104_00792_amd import inputs
+
+    n = 1 << 28 if args.n is None else args.n
+    keys, queries, opts = inputs.make_workload("p16_u32_2^28", n=n, device=dev)
+    P = opts["P"]
+    q = queries.numel()
+    counts = torch.empty(q, dtype=torch.uint32, device=dev)
+    ki = keys.view(torch.int32)
+    pick = torch.randint(0, q, (256,), generator=torch.Generator().manual_seed(0x5EED), dtype=torch.int64).to(dev)
+    sample = queries.view(torch.int32)[pick]
+    exact = torch.stack([(ki == sample[j]).sum() for j in range(sample.numel())]).to(torch.int64).cpu()
+    torch.cuda.synchronize()
+
+    def series(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    occs = DUP_OCCUPANCIES if args.occ is None else tuple(int(x) for x in args.occ.split(","))
+    points = []
+    for occ in occs:
+        log(f"keys per bucket {occ}")
+        ratio = (1, occ)
+        build_ms = series(lambda: hg.hg_build(keys, P=P, ratio=ratio).free(), args.steps)
+        t = hg.hg_build(keys, P=P, ratio=ratio)
+        B = t.info()["num_buckets"]
+        count_ms = series(lambda: hg.hg_count(t, queries, out=counts), args.steps)
+        got = counts.view(torch.int32)[pick].to(torch.int64).cpu()
+        t.free()
+        points.append({"occ": occ, "num_buckets": B, "build_ms": round(build_ms, 4), "count_ms": round(count_ms, 4),
+                       "build_keys_per_s": n / (build_ms / 1000.0), "count_queries_per_s": q / (count_ms / 1000.0),
+                       "sample_exact": bool(torch.equal(got, exact))})
+    worst = max(points, key=lambda p: p["build_ms"] + p["count_ms"])
+    step_ms = worst["build_ms"] + worst["count_ms"]
+    print(json.dumps({"metric": "build+probe keys/s across keys per bucket (Sec. 5.4 duplicate study), worst point",
+                      "value": n / (step_ms / 1000.0), "unit": "keys/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": 1, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+                      "config": {"workload": f"dup_sweep_u32_2^28: {DESCRIPTIONS['dup_sweep_u32_2^28']}", "n": n,
+                                 "q": q, "P": P},
+                      "points": points}), flush=True)
 
 
 def run_serving(args, dev):

@@ -185,16 +185,22 @@ __device__ __forceinline__ bool long_bucket_sorted(const uint32_t* unsorted, uin
 }
 
 // Occurrences of q among the keys a[lo, hi) of a short bucket held in LDS.
-// The first four are read whatever the bucket's length (a[] has four spare
-// entries past its last key) and masked by it, so the common bucket of a few
-// keys costs two paired LDS reads and no loop; the rest follow in a loop.
+// Keys are read four at a time whatever the bucket's length (a[] has four
+// spare entries past its last key) and masked by it, so the common bucket of
+// a few keys costs two paired LDS reads and no loop, and a longer one (up to
+// kLongT keys, a table with many keys per bucket) a quarter of the dependent
+// rounds of a key-by-key loop.
 template <typename K>
 __device__ __forceinline__ uint32_t count_short(const K* a, uint32_t lo, uint32_t hi, K q) {
   const uint32_t n = hi - lo;
   const K x0 = a[lo], x1 = a[lo + 1], x2 = a[lo + 2], x3 = a[lo + 3];
   uint32_t c = (x0 == q && n > 0 ? 1u : 0u) + (x1 == q && n > 1 ? 1u : 0u) + (x2 == q && n > 2 ? 1u : 0u) +
                (x3 == q && n > 3 ? 1u : 0u);
-  for (uint32_t x = lo + 4; x < hi; ++x) c += a[x] == q ? 1u : 0u;
+  for (uint32_t x = lo + 4; x < hi; x += 4) {
+    const K y0 = a[x], y1 = a[x + 1], y2 = a[x + 2], y3 = a[x + 3];
+    c += (y0 == q ? 1u : 0u) + (y1 == q && x + 1 < hi ? 1u : 0u) + (y2 == q && x + 2 < hi ? 1u : 0u) +
+         (y3 == q && x + 3 < hi ? 1u : 0u);
+  }
   return c;
 }
 

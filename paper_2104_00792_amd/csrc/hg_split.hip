@@ -2168,6 +2168,18 @@ __device__ __forceinline__ void wg_sort_range(K* __restrict__ keys, uint32_t lo,
     if (base + r < L) keys[lo + base + r] = v[r];
 }
 
+// Whether one key dominates a bucket: at least half of the 64 keys in kv
+// (its first 64, lane l holding key l) equal the key of lane 0, 21 or 42 (a
+// heavy key and a few others; three candidates, so that a rare key in lane 0
+// does not hide it).  Uniform over the wave.
+template <typename K>
+__device__ __forceinline__ bool key_dominates(K kv) {
+  const uint32_t m0 = popc64(ballot(kv == readlane_key(kv, 0)));
+  const uint32_t m1 = popc64(ballot(kv == readlane_key(kv, 21)));
+  const uint32_t m2 = popc64(ballot(kv == readlane_key(kv, 42)));
+  return max(m0, max(m1, m2)) >= kWave / 2;
+}
+
 // Long buckets of up to this many keys are sorted by one wave in registers
 // when no key dominates them (64 KPL keys per lane, KPL <= 32 for 32-bit
 // keys and <= 16 for 64-bit ones).
@@ -2193,9 +2205,7 @@ __device__ __forceinline__ void wave_sort_bucket(K* __restrict__ keys, uint32_t 
 
 // Long buckets of at most kWaveLong keys (the front of the list), one wave
 // each, in two launches over the same list.  !SORT (first): buckets in which
-// one key dominates (at least half of the first 64 keys equal the key of
-// lane 0, 21 or 42: a heavy key and a few others), or longer than
-// wave_sort_max<K>(); their
+// one key dominates (key_dominates), or longer than wave_sort_max<K>(); their
 // distinct keys are found by ballots, up to kSetMax, and the bucket is
 // rewritten as their runs in ascending order by the whole wave, or, with
 // more, moves to the back of the list (the workgroups of k_long_sort).  Its
@@ -2244,11 +2254,7 @@ __global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint
     K kv0[kDistinctGroups];
 #pragma unroll
     for (int gi = 0; gi < kDistinctGroups; ++gi) kv0[gi] = keys[lo + min(gi * kWave + l, L - 1)];
-    // Three candidates, so that a rare key in lane 0 does not hide a heavy one.
-    const uint32_t m0 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 0)));
-    const uint32_t m1 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 21)));
-    const uint32_t m2 = popc64(ballot(kv0[0] == readlane_key(kv0[0], 42)));
-    const bool heavy = max(m0, max(m1, m2)) >= kWave / 2;
+    const bool heavy = key_dominates<K>(kv0[0]);
     if (L <= wave_sort_max<K>() && !heavy) continue;  // the sorting instance's bucket
     if (l == 0) {
       ssize[w] = 0;
@@ -2313,6 +2319,15 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
       continue;
     }
 
+    if (L <= sort_cap<K>()) {
+      // No key dominates (every wave tests the same first 64 keys): listed
+      // for k_long_wgsort at once, without a distinct search.
+      if (!key_dominates<K>(keys[lo + min(lane_id(), L - 1)])) {
+        if (t == 0) list[ctr[0] + atomicAdd(&ctr[5], 1u)] = g;
+        __syncthreads();
+        continue;
+      }
+    }
     wg_distinct<K, kLongThreads>(keys + lo, 0, L, sval, scnt, ssize, &soverflow);
     const bool over = wave_uniform(soverflow) != 0;
     const uint32_t nd0 = wave_uniform(ssize[0]);
