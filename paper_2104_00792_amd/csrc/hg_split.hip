@@ -2261,8 +2261,10 @@ __global__ __launch_bounds__(THREADS, SORT ? 4 : 1) void k_long_small(const uint
       list[idx] = kListDone;  // read only by the sorting instance, after this kernel
     }
     __builtin_amdgcn_wave_barrier();
-    if (!wave_distinct<K>(keys + lo, 0, L, kWave * kDistinctGroups, sval[w], scnt[w], &ssize[w], nullptr, kSetMax,
-                          kv0)) {
+    // A longer bucket no key dominates goes to the back at once (its many
+    // distinct keys would overflow the set; k_long_sort sorts it).
+    if (!heavy || !wave_distinct<K>(keys + lo, 0, L, kWave * kDistinctGroups, sval[w], scnt[w], &ssize[w], nullptr,
+                                     kSetMax, kv0)) {
       if (l == 0) list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
       continue;
     }
@@ -2293,66 +2295,84 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   __shared__ uint32_t run0[kSetMax + 1];
   __shared__ uint32_t soverflow;
   __shared__ uint32_t sidx;
+  constexpr uint32_t kClaimMax = 16;
+  __shared__ uint32_t sortq[kClaimMax];  // this claim's buckets for the register sort
+  __shared__ uint32_t nsortq, sbase;
   const uint32_t t = threadIdx.x;
   const uint32_t total = ctr[2], cap = ctr[4];
+  // Buckets are claimed `claim` at a time, and a claim's buckets for the
+  // register sort are listed with one atomic: atomics on one address are
+  // served one at a time, and a table of long buckets lists tens of
+  // thousands here.  A short list (a few large buckets) is dealt one by one.
+  const uint32_t claim = min(kClaimMax, max(1u, total / (gridDim.x * 8u)));
   for (;;) {
-    if (t == 0) sidx = atomicAdd(&ctr[3], 1u);
-    __syncthreads();
-    const uint32_t idx = wave_uniform(sidx);
-    if (idx >= total) break;  // uniform: every thread read the same sidx
-    const uint32_t g = wave_uniform(list[cap - 1 - idx]);
-    const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
-    if (L > kBigChunk) {
-      // Queued in chunks for the workgroups of k_big_scan.
-      if (t == 0) {
-        const uint32_t b = atomicAdd(&bw.ctr[0], 1u);
-        const uint32_t nch = (L + kBigChunk - 1) / kBigChunk;
-        const uint32_t at = atomicAdd(&bw.ctr[1], nch);
-        bw.big_g[b] = g;
-        bw.big_first[b] = at;
-        for (uint32_t k = 0; k < nch; ++k) {
-          bw.chunk_b[at + k] = b;
-          bw.chunk_k[at + k] = k;
-        }
-      }
-      __syncthreads();
-      continue;
+    if (t == 0) {
+      sidx = atomicAdd(&ctr[3], claim);
+      nsortq = 0;
     }
-
-    if (L <= sort_cap<K>()) {
-      // No key dominates (every wave tests the same first 64 keys): listed
-      // for k_long_wgsort at once, without a distinct search.
-      if (!key_dominates<K>(keys[lo + min(lane_id(), L - 1)])) {
-        if (t == 0) list[ctr[0] + atomicAdd(&ctr[5], 1u)] = g;
+    __syncthreads();
+    const uint32_t idx0 = wave_uniform(sidx);
+    if (idx0 >= total) break;  // uniform: every thread read the same sidx
+    const uint32_t idx1 = min(idx0 + claim, total);
+    for (uint32_t idx = idx0; idx < idx1; ++idx) {
+      const uint32_t g = wave_uniform(list[cap - 1 - idx]);
+      const uint32_t lo = wave_uniform(offsets[g]), L = wave_uniform(offsets[g + 1]) - lo;
+      if (L > kBigChunk) {
+        // Queued in chunks for the workgroups of k_big_scan.
+        if (t == 0) {
+          const uint32_t b = atomicAdd(&bw.ctr[0], 1u);
+          const uint32_t nch = (L + kBigChunk - 1) / kBigChunk;
+          const uint32_t at = atomicAdd(&bw.ctr[1], nch);
+          bw.big_g[b] = g;
+          bw.big_first[b] = at;
+          for (uint32_t k = 0; k < nch; ++k) {
+            bw.chunk_b[at + k] = b;
+            bw.chunk_k[at + k] = k;
+          }
+        }
         __syncthreads();
         continue;
       }
-    }
-    wg_distinct<K, kLongThreads>(keys + lo, 0, L, sval, scnt, ssize, &soverflow);
-    const bool over = wave_uniform(soverflow) != 0;
-    const uint32_t nd0 = wave_uniform(ssize[0]);
-    if (!over && nd0 <= 1) {
-      // one distinct key: the bucket is already one run
-    } else if (!over) {
-      // rank the distinct keys, then rewrite the bucket as ascending runs
-      const uint32_t nd = nd0;
-      rank_runs<K>(nd, sval, scnt, run0);
-      // Positions only grow along a thread's loop: walk the run index.
-      uint32_t a = 0;
-      for (uint32_t i = t; i < L; i += kLongThreads) {
-        while (a + 1 < nd && run0[a + 1] <= i) ++a;
-        keys[lo + i] = sval[1][a];
+      if (L <= sort_cap<K>()) {
+        // No key dominates (every wave tests the same first 64 keys): on to
+        // the register sort at once, without a distinct search.
+        if (!key_dominates<K>(keys[lo + min(lane_id(), L - 1)])) {
+          if (t == 0) sortq[nsortq++] = g;
+          __syncthreads();
+          continue;
+        }
       }
-    } else if (L <= sort_cap<K>()) {
-      // many distinct keys, few enough for a workgroup's registers: listed
-      // for k_long_wgsort, in the list's free middle (after the ctr[0] front
-      // entries; the back's ctr[2] entries leave at least as many free)
-      if (t == 0) list[ctr[0] + atomicAdd(&ctr[5], 1u)] = g;
-    } else if (t == 0) {
-      const uint32_t u = atomicAdd(&unsorted[0], 1u);
-      if (u < kMaxUnsorted) unsorted[1 + u] = g;
+      wg_distinct<K, kLongThreads>(keys + lo, 0, L, sval, scnt, ssize, &soverflow);
+      const bool over = wave_uniform(soverflow) != 0;
+      const uint32_t nd0 = wave_uniform(ssize[0]);
+      if (!over && nd0 <= 1) {
+        // one distinct key: the bucket is already one run
+      } else if (!over) {
+        // rank the distinct keys, then rewrite the bucket as ascending runs
+        const uint32_t nd = nd0;
+        rank_runs<K>(nd, sval, scnt, run0);
+        // Positions only grow along a thread's loop: walk the run index.
+        uint32_t a = 0;
+        for (uint32_t i = t; i < L; i += kLongThreads) {
+          while (a + 1 < nd && run0[a + 1] <= i) ++a;
+          keys[lo + i] = sval[1][a];
+        }
+      } else if (L <= sort_cap<K>()) {
+        // many distinct keys, few enough for a workgroup's registers
+        if (t == 0) sortq[nsortq++] = g;
+      } else if (t == 0) {
+        const uint32_t u = atomicAdd(&unsorted[0], 1u);
+        if (u < kMaxUnsorted) unsorted[1 + u] = g;
+      }
+      __syncthreads();
     }
+    // The claim's buckets for k_long_wgsort, in the list's free middle
+    // (after the ctr[0] front entries; the back's ctr[2] entries leave room).
+    const uint32_t nq = wave_uniform(nsortq);
+    if (t == 0 && nq != 0) sbase = atomicAdd(&ctr[5], nq);
     __syncthreads();
+    if (t < nq) list[ctr[0] + sbase + t] = sortq[t];
+    __syncthreads();  // sidx, sortq and its count are free for the next claim
   }
 }
 
