@@ -38,6 +38,8 @@ DESCRIPTIONS = {
     "plain_u32_2^20": "n=2^20 uint32 keys uniform; plain table V=n; 2^20 queries at 50% hit",
     "zipf_u64_2^27": "n=2^27 uint64 keys Zipf(1.0) over 2^20 values (value of rank r = the SplitMix64 output "
                      "mixer of r, a bijection like fmix64); hash fmix64; V=n/2; 2^27 Zipf queries",
+    "zipf_u32_2^28": "n=2^28 uint32 keys Zipf(1.0) over 2^20 ranks (value of rank r = the high half of the "
+                     "SplitMix64 output mixer of r); hash fmix32; V=n/2; 2^28 Zipf queries",
     "batched_u32_4096": "4096 uint32 tables, sizes log-uniform in [2^10, 2^20] (622M keys), per-table seeds, "
                         "V_t = n_t; each probed by n_t queries at 50% hit; one hg_build_batched + "
                         "hg_count_batched per step",

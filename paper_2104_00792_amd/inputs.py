@@ -118,6 +118,13 @@ def zipf_u64(n: int, K: int, seed: int, s: float = 1.0) -> np.ndarray:
     return _mix(zipf_ranks(n, K, seed, s))
 
 
+def zipf_u32(n: int, K: int, seed: int, s: float = 1.0) -> np.ndarray:
+    """n 32-bit keys, Zipf(s) over K ranks: the high half of zipf_u64's value
+    of each rank (ranks whose halves coincide merge, which at K = 2^20 draws
+    out of 2^32 happens for about a hundred pairs)."""
+    return (zipf_u64(n, K, seed, s) >> np.uint64(32)).astype(np.uint32)
+
+
 # --------------------------------------------------------------------------
 # The same streams drawn with torch (CPU or device), bit for bit equal to the
 # numpy functions above.  64-bit words are carried as int64 bit patterns:
@@ -229,6 +236,14 @@ def zipf_u64_t(n: int, K: int, seed: int, device, s: float = 1.0):
     return _mix_t(r).view(torch.uint64)
 
 
+def zipf_u32_t(n: int, K: int, seed: int, device, s: float = 1.0):
+    """Device twin of zipf_u32."""
+    import torch
+
+    z = zipf_u64_t(n, K, seed, device, s).view(torch.int64)
+    return _lsr(z, 32).to(torch.int32).view(torch.uint32)
+
+
 # --------------------------------------------------------------------------
 # Named workloads.  Each returns (keys, queries, build options).
 # --------------------------------------------------------------------------
@@ -242,6 +257,8 @@ WORKLOADS = {
     "zipf_u64_2^27": dict(idx=3, n=1 << 27, kind="zipf64", P=1, num=1, den=2),
     # Plain reference point at the headline size: P = 1, V = n = 2^28.
     "plain_u32_2^28": dict(idx=2, n=1 << 28, kind="u32", P=1, num=1, den=1),
+    # Duplicate-heavy 32-bit keys: 2^28 uint32 Zipf(1.0) over 2^20 ranks, V = n / 2.
+    "zipf_u32_2^28": dict(idx=4, n=1 << 28, kind="zipf32", P=1, num=1, den=2),
 }
 
 
@@ -258,6 +275,9 @@ def make_workload(name: str, n: int | None = None, q: int | None = None, device=
         if w["kind"] == "u32":
             keys = uniform_u32_t(n, ks, device)
             queries = queries_hit50_t(keys, q, qs, device)
+        elif w["kind"] == "zipf32":
+            keys = zipf_u32_t(n, 1 << 20, ks, device)
+            queries = zipf_u32_t(q, 1 << 20, qs, device)
         else:
             keys = zipf_u64_t(n, 1 << 20, ks, device)
             queries = zipf_u64_t(q, 1 << 20, qs, device)
@@ -265,6 +285,9 @@ def make_workload(name: str, n: int | None = None, q: int | None = None, device=
     if w["kind"] == "u32":
         keys = uniform_u32(n, ks)
         queries = queries_hit50(keys, q, qs)
+    elif w["kind"] == "zipf32":
+        keys = zipf_u32(n, 1 << 20, ks)
+        queries = zipf_u32(q, 1 << 20, qs)
     else:
         keys = zipf_u64(n, 1 << 20, ks)
         queries = zipf_u64(q, 1 << 20, qs)

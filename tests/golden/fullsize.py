@@ -41,7 +41,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DIGESTS = os.path.join(HERE, "fullsize_digests.json")
-WORKLOADS = ("p16_u32_2^28", "zipf_u64_2^27")
+WORKLOADS = ("p16_u32_2^28", "zipf_u64_2^27", "zipf_u32_2^28")
 _CHUNK = 1 << 24
 
 _XXH_P2 = np.uint64(0xC2B2AE3D27D4EB4F)

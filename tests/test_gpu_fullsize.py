@@ -32,7 +32,7 @@ def _fullsize():
     return mod
 
 
-@pytest.mark.parametrize("name", ["p16_u32_2^28", "zipf_u64_2^27"])
+@pytest.mark.parametrize("name", ["p16_u32_2^28", "zipf_u64_2^27", "zipf_u32_2^28"])
 def test_full_size_against_oracle_digest(gpu, name):
     import torch
 

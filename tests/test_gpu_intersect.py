@@ -28,6 +28,8 @@ CASES = [
     ("u32", 70000, 90000, 1, 1, 1, 1 << 16),   # plain table, fixed V
     ("u64", 300000, 200000, 8, 1, 2, 0),
     ("zipf", 1 << 18, 1 << 17, 1, 1, 2, 0),    # long buckets in both tables
+    ("u32", (1 << 21) + 5, (1 << 20) + 9, 16, 1, 64, 0),  # 64 keys per bucket: small sub-bins, sorted long buckets
+    ("u32", (1 << 21) + 5, (1 << 20) + 9, 1, 1, 2048, 0),  # 2048 keys per bucket: wave and workgroup sorts
 ]
 
 
