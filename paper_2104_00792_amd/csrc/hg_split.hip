@@ -1792,15 +1792,17 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_probe(const K* __restrict
 // Buckets of at most kWaveLong keys are taken by single waves first
 // (k_long_small: runs, or a sort in registers up to wave_sort_max keys);
 // the rest, and those a wave could neither rewrite nor sort, take one
-// workgroup each, from a work counter (k_long_sort):
-//   1. the distinct keys of the bucket and their multiplicities, found by
-//      leader election in each wave (one round per distinct key in the
-//      wave's 64 keys) and merged into a set of at most kSetMax;
+// workgroup each, claimed from a work counter (k_long_sort):
+//   0. a bucket of at most sort_cap<K>() keys (64 KiB) that no key
+//      dominates (key_dominates) is listed for k_long_wgsort at once;
+//   1. otherwise the distinct keys of the bucket and their multiplicities,
+//      found by leader election in each wave (one round per distinct key in
+//      the wave's 64 keys) and merged into a set of at most kSetMax;
 //   2. the bucket rewritten as runs of those keys in ascending order (not
 //      needed for a single distinct key);
-//   3. a bucket with more distinct keys is bitonic-sorted in LDS when it has
-//      at most sort_cap<K>() keys (64 KiB), and otherwise listed as
-//      unsorted.
+//   3. a bucket with more distinct keys is listed for k_long_wgsort (a
+//      bitonic sort in the workgroup's registers) when it has at most
+//      sort_cap<K>() keys, and otherwise listed as unsorted.
 // A bucket of more than kBigChunk keys is queued instead, in chunks: every
 // chunk finds its own distinct keys (k_big_scan), one workgroup per bucket
 // merges them and lays out the runs (k_big_fix), and every chunk rewrites
@@ -2376,10 +2378,11 @@ __global__ __launch_bounds__(kLongThreads) void k_long_sort(const uint32_t* __re
   }
 }
 
-// The buckets k_long_sort listed (more than kSetMax distinct keys, at most
-// sort_cap<K>() keys): one workgroup each, sorted in registers (wg_bitonic;
-// the exchanges across waves go through LDS).  A kernel of its own, so that
-// its registers do not lower the occupancy of k_long_sort.
+// The buckets k_long_sort listed (no dominant key, or more than kSetMax
+// distinct keys; at most sort_cap<K>() keys): one workgroup each, sorted in
+// registers (wg_bitonic; the exchanges across waves go through LDS).  A
+// kernel of its own, so that its registers do not lower the occupancy of
+// k_long_sort.
 template <typename K>
 __global__ __launch_bounds__(kLongThreads) void k_long_wgsort(const uint32_t* __restrict__ offsets,
                                                               const uint32_t* __restrict__ ctr,
