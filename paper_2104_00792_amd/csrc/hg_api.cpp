@@ -440,15 +440,19 @@ uint32_t ceil_log2(uint64_t x) {
 struct HeavyWork {
   uint32_t* words = nullptr;
   uint32_t max_chunks = 0;
+  uint32_t* long_flags = nullptr;  // one word per sub-bin
 };
 
-hg_status alloc_heavy(Allocs& mem, uint64_t n, HeavyWork& h) {
+hg_status alloc_heavy(Allocs& mem, uint64_t n, uint32_t max_subbins, HeavyWork& h) {
   const uint64_t max_heavy = n / 65536 + 1;
   const uint64_t max_chunks = n / hg::heavy_chunk_keys() + max_heavy + 1;
+  const uint64_t heavy_words = 2 + 2 * max_chunks + max_heavy;
   void* p = nullptr;
-  HG_TRY(mem.get(&p, (2 + 2 * max_chunks + max_heavy) * sizeof(uint32_t)), "allocate heavy sub-bin queue");
+  HG_TRY(mem.get(&p, (heavy_words + std::max<uint64_t>(max_subbins, 1)) * sizeof(uint32_t)),
+         "allocate heavy sub-bin queue");
   h.words = static_cast<uint32_t*>(p);
   h.max_chunks = static_cast<uint32_t>(max_chunks);
+  h.long_flags = h.words + heavy_words;
   return HG_OK;
 }
 
@@ -644,11 +648,11 @@ hg_status build_sorted(const void* keys, uint32_t n, hg_key_type kt, uint32_t P,
   st = split_two_levels(keys, n, kt, sp, log2P, P, desc, w, nullptr, nullptr, kNames, s);
   if (st != HG_OK) return st;
   HeavyWork hw;
-  st = alloc_heavy(mem, n, hw);
+  st = alloc_heavy(mem, n, max_subbins, hw);
   if (st != HG_OK) return st;
   HG_LAUNCH("lds_build", s,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, log2P, P, desc, offs, keys_out,
-                                 long_count, long_list, hw.words, hw.max_chunks, s));
+                                 long_count, long_list, hw.words, hw.max_chunks, hw.long_flags, s));
   return HG_OK;
 }
 
@@ -1098,11 +1102,11 @@ hg_status hg_build_batched(const void* d_keys, uint64_t n, hg_key_type kt, uint3
   if (st != HG_OK) return st;
   const uint32_t max_subbins = w.max_subbins;
   HeavyWork hw;
-  st = alloc_heavy(mem, n, hw);
+  st = alloc_heavy(mem, n, max_subbins, hw);
   if (st != HG_OK) return st;
   HG_LAUNCH("blds_build", stream,
             hg::launch_lds_build(kt, w.buf2, w.plan, w.counts2, max_subbins, 0, 1, desc, offs, keys_out, long_ctr,
-                                 long_list, hw.words, hw.max_chunks, stream));
+                                 long_list, hw.words, hw.max_chunks, hw.long_flags, stream));
   void* bigv = nullptr;
   HG_TRY(mem.get(&bigv, hg::big_words(n, static_cast<uint32_t>(ks)) * sizeof(uint32_t)),
          "allocate long-bucket chunk lists");

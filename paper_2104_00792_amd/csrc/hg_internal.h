@@ -196,12 +196,13 @@ hipError_t launch_batch_layout(const uint32_t* table_keys, uint32_t T, uint32_t 
 // Sub-bins of more than 65535 keys are shared by several workgroups
 // (heavy passes); their workspace `heavy` holds 2 + 2 * max_chunks +
 // max_heavy words, max_chunks = n / heavy_chunk_keys() + max_heavy + 1 and
-// max_heavy = n / 65536 + 1.
+// max_heavy = n / 65536 + 1.  `long_flags` (max_subbins words) marks the
+// 32-bit sub-bins whose long buckets a later pass lists.
 uint32_t heavy_chunk_keys();
 hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
                             uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
-                            hipStream_t s);
+                            uint32_t* long_flags, hipStream_t s);
 
 // Queries of one sub-bin, at most probe_chunk_keys() per workgroup (a
 // sub-bin with more is shared through a queue): windows of 2^log2W buckets

@@ -864,46 +864,6 @@ __device__ __forceinline__ void note_long(uint32_t* ctr, uint32_t* list, uint32_
     list[ctr[4] - 1 - atomicAdd(&ctr[2], 1u)] = g;
 }
 
-// note_long for the buckets g0 + k (k < CPT, c[k] keys each) of every lane
-// of a wave, with one atomic per end of the list and wave: the lanes' numbers
-// of front and back entries (at most CPT each) are scanned across the wave
-// in one word, and the last lane reserves the wave's entries.  Every lane of
-// the wave calls it.
-template <int CPT>
-__device__ __forceinline__ void note_long_wave(uint32_t* ctr, uint32_t* list, uint32_t g0, const uint32_t (&c)[CPT]) {
-  static_assert(CPT <= 16 && CPT * kWave < 65536, "one mask word; per-wave totals fit 16 bits");
-  uint32_t mx = 0;
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) mx = max(mx, c[k]);
-  if (ballot(mx > kLongT) == 0) return;  // uniform: no long bucket in the wave (the common case)
-  // Bit k: bucket g0 + k goes to the front; bit 16 + k: to the back.  The
-  // counters are dead once the mask holds them.
-  uint32_t marks = 0;
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    marks |= ((c[k] > kLongT && c[k] <= kWaveLong) ? 1u : 0u) << k;
-    marks |= (c[k] > kWaveLong ? 1u : 0u) << (16 + k);
-  }
-  const uint32_t own = static_cast<uint32_t>(__popc(marks & 0xFFFFu)) | (static_cast<uint32_t>(__popc(marks >> 16)) << 16);
-  const uint32_t incl = wave_inclusive_sum(own);
-  const uint32_t tot = wave_uniform(readlane(incl, kWave - 1));
-  uint32_t basef = 0, baseb = 0;
-  if (lane_id() == kWave - 1) {
-    if ((tot & 0xFFFFu) != 0) basef = atomicAdd(&ctr[0], tot & 0xFFFFu);
-    if ((tot >> 16) != 0) baseb = atomicAdd(&ctr[2], tot >> 16);
-  }
-  basef = readlane(basef, kWave - 1);
-  baseb = readlane(baseb, kWave - 1);
-  const uint32_t ex = incl - own;
-  uint32_t f = basef + (ex & 0xFFFFu), b = baseb + (ex >> 16);
-  const uint32_t cap = ctr[4];
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    if ((marks >> k) & 1u) list[f++] = g0 + k;
-    if ((marks >> (16 + k)) & 1u) list[cap - 1 - b++] = g0 + k;
-  }
-}
-
 // The keys of one sub-bin, each with its position p < m packed as 16-bit
 // halves of pos (key j in half j & 1 of word j >> 1), staged in LDS in
 // position order and written to out[0 .. m) in whole lines, in chunks of
@@ -968,7 +928,8 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
                                                              uint32_t* __restrict__ long_list,
                                                              uint32_t* __restrict__ heavy_count,
                                                              uint32_t* __restrict__ heavy_chunks,
-                                                             uint32_t* __restrict__ heavy_bins) {
+                                                             uint32_t* __restrict__ heavy_bins,
+                                                             uint32_t* __restrict__ long_flags) {
   __shared__ uint32_t lds[kBuildWords];
   __shared__ PartDesc sd[kMaxP];
   __shared__ uint32_t wsum[THREADS / kWave];
@@ -1010,9 +971,9 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
       for (int k = 0; k < CPT; ++k) sum += c[k];
       if constexpr (sizeof(K) == 4) {
         // 32-bit keys: the register path holds this kernel at 64 VGPRs
-        // (eight waves per SIMD), with no room for the workgroup reservation
-        // below; the long buckets are appended per wave instead (one atomic
-        // per end and wave, from a lane scan of the threads' numbers).
+        // (eight waves per SIMD), and every variant of the reservation below
+        // spilled here; a sub-bin with long buckets is only flagged, and
+        // k_note_long lists them from the bucket starts written below.
         uint32_t total;
         uint32_t ex = block_exclusive_sum<THREADS>(sum, wsum, total);
 #pragma unroll
@@ -1025,7 +986,10 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
           ex = q.w + c[4 * x + 3];
           lds4[CQ * t + x] = q;
         }
-        note_long_wave<CPT>(long_count, long_list, sb.gA + CPT * t, c);
+        uint32_t mx = 0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) mx = max(mx, c[k]);
+        if (ballot(mx > kLongT) != 0 && lane_id() == 0) long_flags[blockIdx.x] = 1u;  // same value from any wave
         __syncthreads();
       } else {
         // One scan carries three sums: keys (bits 0-15, at most
@@ -1237,6 +1201,61 @@ __global__ __launch_bounds__(THREADS, MINW) void k_lds_build(const K* __restrict
     const uint32_t e0 = ld_l2(&offsets[sb.gA + i]);
     const uint32_t e1 = i + 1 < R ? ld_l2(&offsets[sb.gA + i + 1]) : sb.kB;
     if (e1 - e0 > kLongT) note_long(long_count, long_list, sb.gA + i, e1 - e0);
+  }
+}
+
+// The long buckets of the sub-bins k_lds_build flagged (32-bit keys, sub-bins
+// of at most kWideR buckets): one workgroup per flagged sub-bin reads the
+// bucket starts the build wrote and lists the sub-bin's long buckets with
+// one reservation per end of the list (atomics on one address are served one
+// at a time: one per wave cost a skewed 2^28 build 2.9 ms).  Thread t takes
+// buckets t + k THREADS; the front and back numbers travel packed in one
+// word through the workgroup scan (at most kWideR each).
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_note_long(const SegPlan* __restrict__ plan,
+                                                       const uint32_t* __restrict__ scan2,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ flags,
+                                                       uint32_t* __restrict__ long_count,
+                                                       uint32_t* __restrict__ long_list) {
+  constexpr int CPT = static_cast<int>(kWideR) / THREADS;
+  static_assert(CPT * THREADS == static_cast<int>(kWideR) && CPT <= 16 && kWideR < 65536, "one mask word");
+  __shared__ uint32_t wtot[THREADS / kWave];
+  __shared__ uint32_t base[2];
+  const uint32_t t = threadIdx.x;
+  const uint32_t nsb = plan->total_subbins;
+  for (uint32_t b = blockIdx.x; b < nsb; b += gridDim.x) {
+    if (wave_uniform(flags[b]) == 0) continue;  // every thread reads the same word
+    const SubBin sb = sub_bin<false>(plan, scan2, b);
+    const uint32_t R = sb.gB - sb.gA;
+    uint32_t marks = 0;  // bit k: bucket t + k THREADS goes to the front; bit 16 + k: to the back
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const uint32_t i = t + static_cast<uint32_t>(k) * THREADS;
+      if (i < R) {
+        const uint32_t len = (i + 1 < R ? offsets[sb.gA + i + 1] : sb.kB) - offsets[sb.gA + i];
+        marks |= ((len > kLongT && len <= kWaveLong) ? 1u : 0u) << k;
+        marks |= (len > kWaveLong ? 1u : 0u) << (16 + k);
+      }
+    }
+    const uint32_t own =
+        static_cast<uint32_t>(__popc(marks & 0xFFFFu)) | (static_cast<uint32_t>(__popc(marks >> 16)) << 16);
+    uint32_t total;
+    const uint32_t ex = block_exclusive_sum<THREADS>(own, wtot, total);
+    if (t == 0) {
+      base[0] = (total & 0xFFFFu) != 0 ? atomicAdd(&long_count[0], total & 0xFFFFu) : 0u;
+      base[1] = (total >> 16) != 0 ? atomicAdd(&long_count[2], total >> 16) : 0u;
+    }
+    __syncthreads();
+    uint32_t f = base[0] + (ex & 0xFFFFu), bk = base[1] + (ex >> 16);
+    const uint32_t cap = long_count[4];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const uint32_t g = sb.gA + t + static_cast<uint32_t>(k) * THREADS;
+      if ((marks >> k) & 1u) long_list[f++] = g;
+      if ((marks >> (16 + k)) & 1u) long_list[cap - 1 - bk++] = g;
+    }
+    __syncthreads();  // base is free for the next sub-bin
   }
 }
 
@@ -2687,7 +2706,7 @@ template <typename K>
 hipError_t lds_build_passes(const K* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, K* out,
                             uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
-                            hipStream_t s) {
+                            uint32_t* long_flags, hipStream_t s) {
   // 64-bit keys: 105 VGPRs, four waves per SIMD.  (1024 threads x 10 keys
   // at eight waves per SIMD spills across the scan and measured slower.)
   constexpr int kMinW = sizeof(K) == 4 ? 8 : 4;
@@ -2695,9 +2714,19 @@ hipError_t lds_build_passes(const K* in, const SegPlan* plan, const uint32_t* sc
   uint32_t* heavy_bins = heavy_chunks + 2 * static_cast<size_t>(max_chunks);
   hipError_t e = launch_fill_u32(heavy, 2, 0u, s);
   if (e != hipSuccess) return e;
+  if constexpr (sizeof(K) == 4) {
+    if ((e = launch_fill_u32(long_flags, max_subbins, 0u, s)) != hipSuccess) return e;
+  }
   k_lds_build<K, kBuildThreads, 20, kMinW><<<max_subbins, kBuildThreads, 0, s>>>(
-      in, plan, scan2, log2P, P, desc, offsets, out, long_count, long_list, heavy, heavy_chunks, heavy_bins);
+      in, plan, scan2, log2P, P, desc, offsets, out, long_count, long_list, heavy, heavy_chunks, heavy_bins,
+      long_flags);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if constexpr (sizeof(K) == 4) {
+    constexpr uint32_t kNoteGrid = 1024;
+    k_note_long<kBuildThreads><<<max_subbins < kNoteGrid ? max_subbins : kNoteGrid, kBuildThreads, 0, s>>>(
+        plan, scan2, offsets, long_flags, long_count, long_list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   constexpr uint32_t kGrid = 1024, kBinGrid = 256;
   k_heavy_count<K, kBuildThreads, 20><<<kGrid, kBuildThreads, 0, s>>>(in, plan, scan2, log2P, P, desc, offsets,
                                                                       heavy, heavy_chunks);
@@ -2715,13 +2744,13 @@ hipError_t lds_build_passes(const K* in, const SegPlan* plan, const uint32_t* sc
 hipError_t launch_lds_build(int kt, const void* in, const SegPlan* plan, const uint32_t* scan2, uint32_t max_subbins,
                             uint32_t log2P, uint32_t P, const PartDesc* desc, uint32_t* offsets, void* out,
                             uint32_t* long_count, uint32_t* long_list, uint32_t* heavy, uint32_t max_chunks,
-                            hipStream_t s) {
+                            uint32_t* long_flags, hipStream_t s) {
   if (max_subbins == 0) return hipSuccess;
   if (kt == 0)
     return lds_build_passes(static_cast<const uint32_t*>(in), plan, scan2, max_subbins, log2P, P, desc, offsets,
-                            static_cast<uint32_t*>(out), long_count, long_list, heavy, max_chunks, s);
+                            static_cast<uint32_t*>(out), long_count, long_list, heavy, max_chunks, long_flags, s);
   return lds_build_passes(static_cast<const uint64_t*>(in), plan, scan2, max_subbins, log2P, P, desc, offsets,
-                          static_cast<uint64_t*>(out), long_count, long_list, heavy, max_chunks, s);
+                          static_cast<uint64_t*>(out), long_count, long_list, heavy, max_chunks, long_flags, s);
 }
 
 uint32_t probe_chunk_keys(int kt) { return kLdsThreads * (kt == 0 ? kProbeReg32 : kProbeReg64); }
