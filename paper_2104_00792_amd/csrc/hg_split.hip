@@ -1222,40 +1222,56 @@ __global__ __launch_bounds__(THREADS) void k_note_long(const SegPlan* __restrict
   static_assert(CPT * THREADS == static_cast<int>(kWideR) && CPT <= 16 && kWideR < 65536, "one mask word");
   __shared__ uint32_t wtot[THREADS / kWave];
   __shared__ uint32_t base[2];
+  __shared__ uint64_t sflagged;
   const uint32_t t = threadIdx.x;
   const uint32_t nsb = plan->total_subbins;
-  for (uint32_t b = blockIdx.x; b < nsb; b += gridDim.x) {
-    if (wave_uniform(flags[b]) == 0) continue;  // every thread reads the same word
-    const SubBin sb = sub_bin<false>(plan, scan2, b);
-    const uint32_t R = sb.gB - sb.gA;
-    uint32_t marks = 0;  // bit k: bucket t + k THREADS goes to the front; bit 16 + k: to the back
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const uint32_t i = t + static_cast<uint32_t>(k) * THREADS;
-      if (i < R) {
-        const uint32_t len = (i + 1 < R ? offsets[sb.gA + i + 1] : sb.kB) - offsets[sb.gA + i];
-        marks |= ((len > kLongT && len <= kWaveLong) ? 1u : 0u) << k;
-        marks |= (len > kWaveLong ? 1u : 0u) << (16 + k);
-      }
-    }
-    const uint32_t own =
-        static_cast<uint32_t>(__popc(marks & 0xFFFFu)) | (static_cast<uint32_t>(__popc(marks >> 16)) << 16);
-    uint32_t total;
-    const uint32_t ex = block_exclusive_sum<THREADS>(own, wtot, total);
-    if (t == 0) {
-      base[0] = (total & 0xFFFFu) != 0 ? atomicAdd(&long_count[0], total & 0xFFFFu) : 0u;
-      base[1] = (total >> 16) != 0 ? atomicAdd(&long_count[2], total >> 16) : 0u;
+  // This workgroup's sub-bins are blockIdx.x + k gridDim.x; the first wave
+  // reads the flags of 64 of them in one load, and the workgroup then visits
+  // only the flagged ones (a table without long buckets costs one round trip
+  // per workgroup and group of 64).
+  for (uint32_t k0 = 0; blockIdx.x + k0 * gridDim.x < nsb; k0 += kWave) {
+    if (t < kWave) {
+      const uint32_t b = blockIdx.x + (k0 + t) * gridDim.x;
+      const uint64_t m = ballot(b < nsb && flags[b] != 0);
+      if (t == 0) sflagged = m;
     }
     __syncthreads();
-    uint32_t f = base[0] + (ex & 0xFFFFu), bk = base[1] + (ex >> 16);
-    const uint32_t cap = long_count[4];
+    uint64_t todo = sflagged;
+    __syncthreads();  // sflagged is free for the next group
+    for (; todo != 0; todo &= todo - 1) {
+      const uint32_t kb = k0 + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(todo)) - 1);
+      const uint32_t b = blockIdx.x + kb * gridDim.x;
+      const SubBin sb = sub_bin<false>(plan, scan2, b);
+      const uint32_t R = sb.gB - sb.gA;
+      uint32_t marks = 0;  // bit k: bucket t + k THREADS goes to the front; bit 16 + k: to the back
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const uint32_t g = sb.gA + t + static_cast<uint32_t>(k) * THREADS;
-      if ((marks >> k) & 1u) long_list[f++] = g;
-      if ((marks >> (16 + k)) & 1u) long_list[cap - 1 - bk++] = g;
+      for (int k = 0; k < CPT; ++k) {
+        const uint32_t i = t + static_cast<uint32_t>(k) * THREADS;
+        if (i < R) {
+          const uint32_t len = (i + 1 < R ? offsets[sb.gA + i + 1] : sb.kB) - offsets[sb.gA + i];
+          marks |= ((len > kLongT && len <= kWaveLong) ? 1u : 0u) << k;
+          marks |= (len > kWaveLong ? 1u : 0u) << (16 + k);
+        }
+      }
+      const uint32_t own =
+          static_cast<uint32_t>(__popc(marks & 0xFFFFu)) | (static_cast<uint32_t>(__popc(marks >> 16)) << 16);
+      uint32_t total;
+      const uint32_t ex = block_exclusive_sum<THREADS>(own, wtot, total);
+      if (t == 0) {
+        base[0] = (total & 0xFFFFu) != 0 ? atomicAdd(&long_count[0], total & 0xFFFFu) : 0u;
+        base[1] = (total >> 16) != 0 ? atomicAdd(&long_count[2], total >> 16) : 0u;
+      }
+      __syncthreads();
+      uint32_t f = base[0] + (ex & 0xFFFFu), bk = base[1] + (ex >> 16);
+      const uint32_t cap = long_count[4];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const uint32_t g = sb.gA + t + static_cast<uint32_t>(k) * THREADS;
+        if ((marks >> k) & 1u) long_list[f++] = g;
+        if ((marks >> (16 + k)) & 1u) long_list[cap - 1 - bk++] = g;
+      }
+      __syncthreads();  // base is free for the next sub-bin
     }
-    __syncthreads();  // base is free for the next sub-bin
   }
 }
 
