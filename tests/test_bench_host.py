@@ -96,3 +96,12 @@ def test_launch_share_is_the_step_outside_its_launch_groups():
     assert share["launch_groups_per_step"] == 3 and share["kernel_ms_per_step"] == 3.5
     assert share["between_launches_ms"] == 0.5 and share["between_frac"] == 0.125
     assert bench.launch_share(kernels, 3.0)["between_launches_ms"] == 0.0  # event overhead can exceed the gaps
+
+
+def test_duplicate_study_workload():
+    """The duplicate-study sweep runs on the headline's keys, from one key
+    per bucket up to 4096, and names itself among the bench workloads."""
+    assert "dup_sweep_u32_2^28" in bench.DESCRIPTIONS
+    occ = bench.DUP_OCCUPANCIES
+    assert occ[0] == 1 and occ[-1] == 4096 and list(occ) == sorted(set(occ))
+    assert all(o & (o - 1) == 0 for o in occ)  # V_p = n_p / occ stays exact for n_p a power of two

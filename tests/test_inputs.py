@@ -48,6 +48,16 @@ def test_zipf_rank_one_frequency():
     assert v.dtype == np.uint64
 
 
+def test_zipf_u32_is_the_high_half_of_zipf_u64():
+    K = 1 << 20
+    v64 = inputs.zipf_u64(1 << 16, K, 9)
+    v32 = inputs.zipf_u32(1 << 16, K, 9)
+    assert v32.dtype == np.uint32
+    assert np.array_equal(v32, (v64 >> np.uint64(32)).astype(np.uint32))
+    # the rank structure survives: as many distinct values, up to a rare merge
+    assert abs(np.unique(v32).size - np.unique(v64).size) <= 2
+
+
 def test_sequential_and_sample_with_replacement():
     assert inputs.sequential(5).tolist() == [1, 2, 3, 4, 5]
     s = inputs.sample_with_replacement(1 << 16, 2)
