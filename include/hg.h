@@ -66,7 +66,10 @@ typedef enum hg_key_type { HG_KEY_U32 = 0, HG_KEY_U64 = 1 } hg_key_type;
  *                (1 <= V <= 2^32 - 2); otherwise ignored.
  *   log2_subbin  sorted build: sub-bins of 2^log2_subbin buckets (10..13),
  *                which sets the keys each workgroup of the LDS build takes;
- *                0 lets the library choose.
+ *                0 lets the library choose: about 2^13 keys per sub-bin,
+ *                so tables with many keys per bucket (the duplicate study
+ *                of Sec. 5.4) get sub-bins of fewer than 2^10 buckets, a
+ *                size this knob does not offer.
  *   split_bits   sorted build: at most 2^split_bits level-2 digits per
  *                level-1 segment (7..10); 0 lets the library choose.
  * The last two change speed only, never the table; a table keeps them for
